@@ -1,0 +1,125 @@
+"""Seeded synthetic inputs for robust tensor PCA: X = L* + S*.
+
+This module draws test and benchmark inputs only.  It holds none of the
+RTCUR arithmetic: the oracle under ``oracle/`` and the HIP library both take
+the tensor it returns as a plain input, and neither imports the other.
+
+Recipe (the synthetic experiment of Section 4.1, restated with the choices
+written out in the design doc):
+
+* L* = G x_1 U_1 x_2 ... x_n U_n with core G of i.i.d. N(0,1) entries and
+  factors U_i whose columns are the Q factor of a d_i x r_i i.i.d. N(0,1)
+  matrix (``orthonormal=False`` keeps the raw Gaussian factors, as the paper's
+  text does);
+* the support of S* is Bernoulli(alpha) per entry, and its values are i.i.d.
+  uniform in [-c * mean|L*|, c * mean|L*|];
+* draw order from ``numpy.random.default_rng(seed)``: core, U_1 .. U_n,
+  support mask, values.  X is formed in float64 and then cast to the storage
+  dtype, so float32 storage upcasts back to float64 exactly.
+"""
+
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import Optional, Sequence
+
+import numpy as np
+
+__all__ = ["Instance", "tucker_plus_sparse", "sample_sizes", "CONFIGS",
+           "config_instance"]
+
+
+@dataclass
+class Instance:
+    X: np.ndarray                      # observed tensor, storage dtype
+    L_star: np.ndarray                 # low-rank part, float64
+    S_star: np.ndarray                 # sparse part, float64 (dense array)
+    dims: tuple
+    ranks: tuple
+    alpha: float
+    seed: int
+    meta: dict = field(default_factory=dict)
+
+
+def _tucker(core: np.ndarray, factors: Sequence[np.ndarray]) -> np.ndarray:
+    """Full tensor core x_1 U_1 ... x_n U_n (input construction only)."""
+    out = core
+    for k, U in enumerate(factors):
+        # contract axis k of `out` with the columns of U, put the new axis back
+        out = np.moveaxis(np.tensordot(U, out, axes=(1, k)), 0, k)
+    return out
+
+
+def tucker_plus_sparse(dims: Sequence[int], ranks: Sequence[int], alpha: float,
+                       c: float = 1.0, seed: int = 0,
+                       storage=np.float64, orthonormal: bool = True,
+                       keep_parts: bool = True) -> Instance:
+    """Low-multilinear-rank tensor plus Bernoulli(alpha) sparse outliers."""
+    dims = tuple(int(d) for d in dims)
+    ranks = tuple(int(r) for r in ranks)
+    if len(dims) != len(ranks):
+        raise ValueError("dims and ranks must have the same length")
+    rng = np.random.default_rng(seed)
+    core = rng.standard_normal(ranks)
+    factors = []
+    for d, r in zip(dims, ranks):
+        Y = rng.standard_normal((d, r))
+        if orthonormal:
+            Y = np.linalg.qr(Y)[0]
+        factors.append(Y)
+    L = _tucker(core, factors)
+    mask = rng.random(dims) < alpha
+    amp = c * float(np.mean(np.abs(L)))
+    vals = rng.uniform(-amp, amp, size=int(mask.sum()))
+    S = np.zeros(dims, dtype=np.float64)
+    S[mask] = vals
+    X = (L + S).astype(storage)
+    meta = {"amp": amp, "support": int(mask.sum()), "c": c,
+            "orthonormal": orthonormal}
+    if not keep_parts:
+        return Instance(X, None, None, dims, ranks, alpha, seed, meta)
+    return Instance(X, L, S, dims, ranks, alpha, seed, meta)
+
+
+def sample_sizes(dims: Sequence[int], ranks: Sequence[int],
+                 upsilon: float = 3.0, fiber: bool = False):
+    """|I_i| = ceil(upsilon r_i ln d_i) clamped to d_i (Section 4 sizes rule).
+
+    With ``fiber=True`` also returns |J_i| = ceil(upsilon r_i ln prod_{j!=i} d_j)
+    clamped to prod_{j!=i} d_j; otherwise J sizes are None (chidori).
+    """
+    dims = [int(d) for d in dims]
+    I = [min(d, int(math.ceil(upsilon * r * math.log(d)))) for d, r in
+         zip(dims, ranks)]
+    if not fiber:
+        return I, None
+    J = []
+    for i, r in enumerate(ranks):
+        P = 1
+        for j, d in enumerate(dims):
+            if j != i:
+                P *= d
+        J.append(min(P, int(math.ceil(upsilon * r * math.log(P)))))
+    return I, J
+
+
+# Named workloads.  Each is a dict of generator and solver settings.
+CONFIGS = {
+    # 100^3 float64, rank 3, alpha 0.2 (small case the oracle finishes fast)
+    "cube100_r3": dict(dims=(100, 100, 100), ranks=(3, 3, 3), alpha=0.2,
+                       c=1.0, storage=np.float64, upsilon=3.0, gamma=0.7,
+                       tol=1e-5, max_iter=100, seed=0),
+    # 300^3 float32 storage, rank 5, alpha 0.3 (the headline workload)
+    "cube300_r5": dict(dims=(300, 300, 300), ranks=(5, 5, 5), alpha=0.3,
+                       c=1.0, storage=np.float32, upsilon=3.0, gamma=0.7,
+                       tol=1e-5, max_iter=100, seed=0),
+}
+
+
+def config_instance(name: str, seed: Optional[int] = None, **over) -> Instance:
+    cfg = dict(CONFIGS[name])
+    cfg.update(over)
+    return tucker_plus_sparse(cfg["dims"], cfg["ranks"], cfg["alpha"],
+                              c=cfg["c"], seed=cfg["seed"] if seed is None
+                              else seed, storage=cfg["storage"])
