@@ -1,0 +1,151 @@
+/*
+ * rtcur.h - C ABI of librtcur, Robust Tensor CUR (RTCUR) on one gfx950 GPU.
+ *
+ * RTCUR (Cai, Chao, Huang, Needell, "Fast Robust Tensor Principal Component
+ * Analysis via Fiber CUR Decomposition", Algorithm 1) splits an observed
+ * n-mode tensor X = L + S into a low-multilinear-rank part L and a sparse
+ * outlier part S by alternating projections that only ever touch sampled
+ * entries of X:
+ *
+ *   - Omega: index sets I_i (rows of mode i, |I_i| = s_i) and J_i (columns of
+ *     the mode-i unfolding, |J_i| = m_i).  The sampled blocks are the core
+ *     subtensor R = X(I_1, ..., I_n) and the fiber blocks C_i = X_(i)(:, J_i).
+ *   - Step (I), equations 8-10: S = HT_zeta(X - L) on the blocks, with
+ *     zeta_{k+1} = gamma * zeta_k (equation 9) and HT keeping |x| > zeta.
+ *   - Step (II), equations 5-6: L = R x_i (C_i U_i^+) with U_i = C_i(I_i, :)
+ *     truncated to rank r_i; only the factors are kept (Section 3.3).
+ *   - Stop when e^(k) <= tol, e^(k) the sampled relative error of
+ *     equation 11.
+ *   - RTCUR-F keeps one sample; RTCUR-R draws a new one before every iteration
+ *     after the first (Section 3.4).
+ *
+ * Conventions
+ *   - Tensors are dense, C-contiguous (last mode fastest), on the device.
+ *     The mode-i unfolding numbers its columns in C order over the remaining
+ *     modes.
+ *   - All entry points return an int status (RTCUR_OK or one of the codes
+ *     below); no exception or abort crosses the ABI.  rtcur_last_error gives
+ *     a per-handle message for the last failure.
+ *   - A handle is not thread-safe.  All device work runs on the stream given
+ *     to rtcur_create, in stream order; rtcur_solve returns after its device
+ *     work has finished.
+ *   - Limits: 2 <= n <= 4; 1 <= r_i <= 16; prod(r_i) <= 4096; s_i <= 256.
+ */
+#ifndef RTCUR_H
+#define RTCUR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rtcur_s* rtcur_t;
+
+enum rtcur_status {
+    RTCUR_OK = 0,
+    RTCUR_NOT_CONVERGED = 1,  /* max_iter reached with e > tol; results valid */
+    RTCUR_E_INVAL = -1,       /* invalid argument                              */
+    RTCUR_E_NOMEM = -2,       /* device or host allocation failed              */
+    RTCUR_E_HIP = -3,         /* HIP runtime error (includes: no device)       */
+    RTCUR_E_RANK = -4,        /* some U_i has numerical rank below r_i         */
+    RTCUR_E_NONFINITE = -5,   /* NaN/Inf in sampled X, max|X| or e^(k)         */
+    RTCUR_E_STATE = -6        /* call out of order (e.g. reconstruct first)    */
+};
+
+enum rtcur_dtype { RTCUR_F64 = 0, RTCUR_F32 = 1 };
+enum rtcur_variant { RTCUR_FIXED = 0 /* RTCUR-F */, RTCUR_RESAMPLE = 1 /* RTCUR-R */ };
+enum rtcur_block_what { RTCUR_BLOCK_X = 0, RTCUR_BLOCK_C = 1, RTCUR_BLOCK_L = 2,
+                        RTCUR_BLOCK_SUPPORT = 3 };
+
+typedef struct {
+    int32_t iters;       /* number of L-updates done (k)                      */
+    int32_t converged;   /* 1 if e^(k) <= tol                                 */
+    double err;          /* e^(k), equation 11, of the returned iterate       */
+    double zeta;         /* zeta_k, the last threshold used                   */
+    double zeta0;        /* zeta_0 used (given, or max|X|)                    */
+    int32_t eig_steps;   /* total subspace-iteration steps of the eigensolver */
+    int32_t status;      /* status of the last rtcur_solve                    */
+} rtcur_info;
+
+/* Create a solver bound to HIP device `device` and stream `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  variant: RTCUR_FIXED or
+ * RTCUR_RESAMPLE.  compute_dtype: RTCUR_F64 or RTCUR_F32, the precision of
+ * the sampled blocks, factors and the rebuilt L; the truncated SVD and the
+ * stopping-rule norms always run in float64.  Fails with RTCUR_E_HIP when no
+ * usable device exists.  *out is set to NULL on failure. */
+int rtcur_create(rtcur_t* out, int device, void* hip_stream, int variant,
+                 int compute_dtype);
+
+/* Run Algorithm 1 on the device tensor X (x_dtype RTCUR_F64 or RTCUR_F32,
+ * dims[0..n) C-contiguous, read-only, borrowed for this call only).
+ *   ranks[i]   target multilinear rank r_i (Algorithm 1 input)
+ *   I_sizes[i] s_i = |I_i|, with r_i <= s_i <= dims[i]
+ *   J_sizes    NULL: chidori sampling, J_i = product of I_j (j != i);
+ *              else m_i = |J_i| fiber columns, r_i <= m_i <= prod_{j!=i} d_j
+ *   zeta0      initial threshold; <= 0 means max|X| over the whole tensor
+ *   gamma      threshold decay, 0 < gamma < 1 (equation 9)
+ *   tol        target e^(k) (equation 11), >= 0; stop when e^(k) <= tol
+ *   max_iter   >= 1 L-updates at most; RTCUR_NOT_CONVERGED if reached
+ *   seed       sampler seed; samples are a pure function of (seed, t, dims,
+ *              sizes), identical to the oracle's
+ *   info       optional summary (may be NULL)
+ * The handle keeps the samples, blocks and factors until the next solve or
+ * destroy.  Returns RTCUR_OK, RTCUR_NOT_CONVERGED or an error; after
+ * RTCUR_E_RANK / RTCUR_E_NONFINITE the handle stays usable. */
+int rtcur_solve(rtcur_t h, const void* X, int x_dtype, int32_t n,
+                const int64_t* dims, const int32_t* ranks,
+                const int64_t* I_sizes, const int64_t* J_sizes, double zeta0,
+                double gamma, double tol, int32_t max_iter, uint64_t seed,
+                rtcur_info* info);
+
+/* Write the full L = R x_i (C_i U_i^+) of the last solve (Algorithm 1
+ * output, expanded over every entry) into the caller's device buffer L_out
+ * of prod(dims) elements, C-contiguous, dtype out_dtype (RTCUR_F64/F32).
+ * RTCUR_E_STATE if no successful solve precedes it. */
+int rtcur_reconstruct(rtcur_t h, void* L_out, int out_dtype);
+
+/* Release the handle and its device workspace.  NULL-safe. */
+int rtcur_destroy(rtcur_t h);
+
+/* ---- introspection (host copies; for tests and diagnostics, not hot) ---- */
+
+/* Indices of the sample the returned iterate lives on: which = 0 gives I_i
+ * (sorted), which = 1 gives J_i as mode-i unfolding column numbers (C order,
+ * sorted).  Copies min(cap, length) values; *len = length. */
+int rtcur_get_indices(rtcur_t h, int32_t mode, int32_t which, int64_t* out,
+                      int64_t cap, int64_t* len);
+
+/* e^(1..k) and zeta_1..zeta_k of the last solve.  *len = k. */
+int rtcur_get_history(rtcur_t h, double* err, double* zeta, int32_t cap,
+                      int32_t* len);
+
+/* One sampled block of the returned iterate as float64 on the host:
+ * block 0 = R (s_1 x ... x s_n, C order), block 1+i = C_i (d_i x m_i,
+ * row-major).  what: RTCUR_BLOCK_X (gathered X), RTCUR_BLOCK_C (X - S),
+ * RTCUR_BLOCK_L (L on the block), RTCUR_BLOCK_SUPPORT (1.0 where S != 0).
+ * *len = number of entries of the block. */
+int rtcur_get_block(rtcur_t h, int32_t block, int32_t what, double* out,
+                    int64_t cap, int64_t* len);
+
+/* Tucker form of the returned L = G x_1 B_1 ... x_n B_n: core G (prod r_i,
+ * C order) and B_i (d_i x r_i, row-major), float64 host buffers.  Either
+ * pointer may be NULL.  B is an array of n host pointers. */
+int rtcur_get_tucker(rtcur_t h, double* core, double* const* B);
+
+/* Host-only sampler (no device needed): the index set of Algorithm 1's
+ * sampling step for resample counter t, mode `mode`; which = 0 gives I_mode,
+ * which = 1 gives J_mode column numbers (chidori when J_sizes is NULL).
+ * Same definition as the solver uses. */
+int rtcur_sample(uint64_t seed, int64_t t, int32_t n, const int64_t* dims,
+                 const int64_t* I_sizes, const int64_t* J_sizes, int32_t mode,
+                 int32_t which, int64_t* out, int64_t cap, int64_t* len);
+
+const char* rtcur_strerror(int status);
+const char* rtcur_last_error(rtcur_t h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RTCUR_H */

@@ -1,0 +1,298 @@
+"""Python binding of librtcur, Robust Tensor CUR (RTCUR) on one gfx950 GPU.
+
+Argument marshalling only: every step of the solve runs in the library's HIP
+kernels.  PyTorch supplies device memory and the stream.  The functions
+mirror the C ABI in include/rtcur.h:
+
+    create(device=0, stream=None, variant="F", dtype=torch.float64) -> Handle
+    solve(handle, X, ranks, I_sizes=None, J_sizes=None, ...) -> Info
+    reconstruct(handle, out=None, dtype=None) -> torch.Tensor
+    destroy(handle)
+    get_indices / get_history / get_block / get_tucker / sample
+
+The library must have been built (``python -m paper_2108_10448_amd.build``);
+importing the binding never falls back to anything else.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import warnings
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librtcur.so")
+
+OK, NOT_CONVERGED = 0, 1
+E_INVAL, E_NOMEM, E_HIP, E_RANK, E_NONFINITE, E_STATE = -1, -2, -3, -4, -5, -6
+F64, F32 = 0, 1
+FIXED, RESAMPLE = 0, 1
+BLOCK_X, BLOCK_C, BLOCK_L, BLOCK_SUPPORT = 0, 1, 2, 3
+
+SYMBOLS = ["rtcur_create", "rtcur_solve", "rtcur_reconstruct", "rtcur_destroy",
+           "rtcur_get_indices", "rtcur_get_history", "rtcur_get_block",
+           "rtcur_get_tucker", "rtcur_sample", "rtcur_strerror",
+           "rtcur_last_error"]
+
+
+class RtcurInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("err", ctypes.c_double), ("zeta", ctypes.c_double),
+                ("zeta0", ctypes.c_double), ("eig_steps", ctypes.c_int32),
+                ("status", ctypes.c_int32)]
+
+
+class RTCURError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load librtcur.so (built in-tree); raise if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run "
+                           "`python -m paper_2108_10448_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, u64, dbl = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
+                              ctypes.c_uint64, ctypes.c_double)
+    p64 = ctypes.POINTER(ctypes.c_int64)
+    pd = ctypes.POINTER(ctypes.c_double)
+    L.rtcur_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, vp, ctypes.c_int,
+                               ctypes.c_int]
+    L.rtcur_solve.argtypes = [vp, vp, ctypes.c_int, i32, p64,
+                              ctypes.POINTER(ctypes.c_int32), p64, p64, dbl, dbl,
+                              dbl, i32, u64, ctypes.POINTER(RtcurInfo)]
+    L.rtcur_reconstruct.argtypes = [vp, vp, ctypes.c_int]
+    L.rtcur_destroy.argtypes = [vp]
+    L.rtcur_get_indices.argtypes = [vp, i32, i32, p64, i64, p64]
+    L.rtcur_get_history.argtypes = [vp, pd, pd, i32, ctypes.POINTER(ctypes.c_int32)]
+    L.rtcur_get_block.argtypes = [vp, i32, i32, pd, i64, p64]
+    L.rtcur_get_tucker.argtypes = [vp, pd, ctypes.POINTER(pd)]
+    L.rtcur_sample.argtypes = [u64, i64, i32, p64, p64, p64, i32, i32, p64, i64, p64]
+    L.rtcur_strerror.argtypes = [ctypes.c_int]
+    L.rtcur_strerror.restype = ctypes.c_char_p
+    L.rtcur_last_error.argtypes = [vp]
+    L.rtcur_last_error.restype = ctypes.c_char_p
+    for name in SYMBOLS:
+        if name not in ("rtcur_strerror", "rtcur_last_error"):
+            getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def strerror(status: int) -> str:
+    return lib().rtcur_strerror(status).decode()
+
+
+def _i64(seq) -> ctypes.Array:
+    return (ctypes.c_int64 * len(seq))(*[int(v) for v in seq])
+
+
+def default_sizes(dims: Sequence[int], ranks: Sequence[int], upsilon: float = 3.0,
+                  fiber: bool = False):
+    """|I_i| = ceil(upsilon r_i ln d_i) (the sample-size rule of Section 4),
+    clamped to d_i; with fiber=True also |J_i| = ceil(upsilon r_i ln prod d_j)."""
+    I = [min(int(d), int(math.ceil(upsilon * r * math.log(d)))) for d, r in zip(dims, ranks)]
+    if not fiber:
+        return I, None
+    J = []
+    for i, r in enumerate(ranks):
+        P = 1
+        for j, d in enumerate(dims):
+            if j != i:
+                P *= int(d)
+        J.append(min(P, int(math.ceil(upsilon * r * math.log(P)))))
+    return I, J
+
+
+def sample(seed: int, t: int, dims, I_sizes, J_sizes, mode: int, which: int) -> np.ndarray:
+    """The library's own sampler (host only): I_mode (which=0) or J_mode
+    column numbers (which=1) for resample counter t."""
+    L = lib()
+    n = len(dims)
+    ln = ctypes.c_int64(0)
+    Jarr = _i64(J_sizes) if J_sizes is not None else None
+    rc = L.rtcur_sample(seed, t, n, _i64(dims), _i64(I_sizes), Jarr, mode, which,
+                        None, 0, ctypes.byref(ln))
+    if rc != OK:
+        raise RTCURError(rc, strerror(rc))
+    out = np.zeros(ln.value, dtype=np.int64)
+    rc = L.rtcur_sample(seed, t, n, _i64(dims), _i64(I_sizes), Jarr, mode, which,
+                        out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), ln.value,
+                        ctypes.byref(ln))
+    if rc != OK:
+        raise RTCURError(rc, strerror(rc))
+    return out
+
+
+@dataclass
+class Info:
+    status: int
+    iters: int
+    converged: bool
+    err: float
+    zeta: float
+    zeta0: float
+    eig_steps: int
+
+
+class Handle:
+    """Owns an rtcur_t; closes it on destroy() or garbage collection."""
+
+    def __init__(self, ptr, device, variant, dtype):
+        self.ptr = ptr
+        self.device = device
+        self.variant = variant
+        self.dtype = dtype
+        self.dims = None
+        self.ranks = None
+
+    def __del__(self):
+        try:
+            destroy(self)
+        except Exception:
+            pass
+
+    def last_error(self) -> str:
+        return lib().rtcur_last_error(self.ptr).decode() if self.ptr else ""
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def create(device: int = 0, stream=None, variant: str = "F", dtype=None) -> Handle:
+    """rtcur_create on `device`, bound to `stream` (default: torch's current
+    stream of that device).  variant "F" (fixed samples) or "R" (resample)."""
+    torch = _torch()
+    dtype = torch.float64 if dtype is None else dtype
+    cdt = F64 if dtype == torch.float64 else F32
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    sptr = ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else stream)
+    out = ctypes.c_void_p()
+    rc = lib().rtcur_create(ctypes.byref(out), device, sptr,
+                            FIXED if variant == "F" else RESAMPLE, cdt)
+    if rc != OK:
+        raise RTCURError(rc, f"rtcur_create: {strerror(rc)}")
+    return Handle(out, device, variant, dtype)
+
+
+def destroy(h: Handle) -> None:
+    if h is not None and h.ptr:
+        lib().rtcur_destroy(h.ptr)
+        h.ptr = None
+
+
+def solve(h: Handle, X, ranks: Sequence[int], I_sizes: Optional[Sequence[int]] = None,
+          J_sizes: Optional[Sequence[int]] = None, *, upsilon: float = 3.0,
+          zeta0: Optional[float] = None, gamma: float = 0.7, tol: float = 1e-5,
+          max_iter: int = 100, seed: int = 0, check: bool = True) -> Info:
+    """rtcur_solve on the device tensor X (float32/float64, C-contiguous)."""
+    torch = _torch()
+    if not isinstance(X, torch.Tensor) or not X.is_cuda:
+        raise TypeError("X must be a device torch.Tensor")
+    if X.dtype not in (torch.float32, torch.float64):
+        raise TypeError("X must be float32 or float64")
+    if not X.is_contiguous():
+        raise ValueError("X must be C-contiguous")
+    dims = list(X.shape)
+    if I_sizes is None:
+        I_sizes, _ = default_sizes(dims, ranks, upsilon)
+    info = RtcurInfo()
+    r32 = (ctypes.c_int32 * len(ranks))(*[int(r) for r in ranks])
+    rc = lib().rtcur_solve(h.ptr, ctypes.c_void_p(X.data_ptr()),
+                           F64 if X.dtype == torch.float64 else F32, len(dims),
+                           _i64(dims), r32, _i64(I_sizes),
+                           _i64(J_sizes) if J_sizes is not None else None,
+                           float(zeta0) if zeta0 else 0.0, float(gamma), float(tol),
+                           int(max_iter), int(seed) & ((1 << 64) - 1),
+                           ctypes.byref(info))
+    h.dims, h.ranks = dims, list(ranks)
+    if rc < 0 and check:
+        raise RTCURError(rc, f"rtcur_solve: {strerror(rc)}: {h.last_error()}")
+    if rc == NOT_CONVERGED and check:
+        warnings.warn(f"RTCUR did not reach tol in {max_iter} iterations (e={info.err:.3e})")
+    return Info(rc, info.iters, bool(info.converged), info.err, info.zeta, info.zeta0,
+                info.eig_steps)
+
+
+def reconstruct(h: Handle, out=None, dtype=None):
+    """rtcur_reconstruct: the full L into `out` (allocated if None)."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty(h.dims, dtype=dtype or h.dtype, device=f"cuda:{h.device}")
+    rc = lib().rtcur_reconstruct(h.ptr, ctypes.c_void_p(out.data_ptr()),
+                                 F64 if out.dtype == torch.float64 else F32)
+    if rc != OK:
+        raise RTCURError(rc, f"rtcur_reconstruct: {strerror(rc)}: {h.last_error()}")
+    return out
+
+
+def get_indices(h: Handle, mode: int, which: int) -> np.ndarray:
+    L = lib()
+    ln = ctypes.c_int64(0)
+    rc = L.rtcur_get_indices(h.ptr, mode, which, None, 0, ctypes.byref(ln))
+    if rc != OK:
+        raise RTCURError(rc, h.last_error())
+    out = np.zeros(ln.value, dtype=np.int64)
+    L.rtcur_get_indices(h.ptr, mode, which, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                        ln.value, ctypes.byref(ln))
+    return out
+
+
+def get_history(h: Handle):
+    L = lib()
+    ln = ctypes.c_int32(0)
+    rc = L.rtcur_get_history(h.ptr, None, None, 0, ctypes.byref(ln))
+    if rc != OK:
+        raise RTCURError(rc, h.last_error())
+    e = np.zeros(ln.value)
+    z = np.zeros(ln.value)
+    pd = ctypes.POINTER(ctypes.c_double)
+    L.rtcur_get_history(h.ptr, e.ctypes.data_as(pd), z.ctypes.data_as(pd), ln.value,
+                        ctypes.byref(ln))
+    return e, z
+
+
+def get_block(h: Handle, block: int, what: int) -> np.ndarray:
+    """A sampled block as float64 (block 0 = R with shape (s_1..s_n), block
+    1+i = C_i with shape (d_i, m_i))."""
+    L = lib()
+    ln = ctypes.c_int64(0)
+    rc = L.rtcur_get_block(h.ptr, block, what, None, 0, ctypes.byref(ln))
+    if rc != OK:
+        raise RTCURError(rc, h.last_error())
+    out = np.zeros(ln.value)
+    rc = L.rtcur_get_block(h.ptr, block, what,
+                           out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ln.value,
+                           ctypes.byref(ln))
+    if rc != OK:
+        raise RTCURError(rc, h.last_error())
+    return out
+
+
+def get_tucker(h: Handle):
+    """(core G of shape ranks, [B_i of shape (d_i, r_i)]) as float64 arrays."""
+    L = lib()
+    core = np.zeros(h.ranks)
+    Bs = [np.zeros((d, r)) for d, r in zip(h.dims, h.ranks)]
+    pd = ctypes.POINTER(ctypes.c_double)
+    arr = (pd * len(Bs))(*[b.ctypes.data_as(pd) for b in Bs])
+    rc = L.rtcur_get_tucker(h.ptr, core.ctypes.data_as(pd), arr)
+    if rc != OK:
+        raise RTCURError(rc, h.last_error())
+    return core, Bs

@@ -1,0 +1,240 @@
+// extern "C" entry points of librtcur (declared in include/rtcur.h):
+// argument validation, handle lifetime, status strings and host copies.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "internal.h"
+
+using rtcur::Shape;
+
+namespace {
+
+int fail(rtcur_t h, int status, const char* msg) {
+    if (h) h->last_error = msg;
+    return status;
+}
+
+// Checks of the Algorithm 1 inputs; fills the shape.
+int validate(rtcur_t h, int32_t n, const int64_t* dims, const int32_t* ranks,
+             const int64_t* I_sizes, const int64_t* J_sizes, double gamma, double tol,
+             int32_t max_iter, int x_dtype, Shape& sh) {
+    if (n < 2 || n > rtcur::kMaxModes)
+        return fail(h, RTCUR_E_INVAL, "number of modes must be 2..4");
+    if (!dims || !ranks || !I_sizes) return fail(h, RTCUR_E_INVAL, "null size array");
+    if (x_dtype != RTCUR_F64 && x_dtype != RTCUR_F32)
+        return fail(h, RTCUR_E_INVAL, "x_dtype must be RTCUR_F64 or RTCUR_F32");
+    if (!(gamma > 0.0 && gamma < 1.0)) return fail(h, RTCUR_E_INVAL, "gamma must lie in (0,1)");
+    if (!(tol >= 0.0)) return fail(h, RTCUR_E_INVAL, "tol must be >= 0");
+    if (max_iter < 1) return fail(h, RTCUR_E_INVAL, "max_iter must be >= 1");
+    sh.n = n;
+    sh.chidori = (J_sizes == nullptr);
+    int64_t core = 1;
+    for (int i = 0; i < n; ++i) {
+        sh.d[i] = dims[i];
+        sh.r[i] = ranks[i];
+        sh.s[i] = I_sizes[i];
+        if (dims[i] < 1 || dims[i] > (int64_t)1 << 30)
+            return fail(h, RTCUR_E_INVAL, "dims out of range");
+        if (ranks[i] < 1 || ranks[i] > rtcur::kMaxRank)
+            return fail(h, RTCUR_E_INVAL, "ranks must be 1..16");
+        if (I_sizes[i] < ranks[i] || I_sizes[i] > dims[i])
+            return fail(h, RTCUR_E_INVAL, "need r_i <= |I_i| <= d_i");
+        if (I_sizes[i] > rtcur::kMaxS) return fail(h, RTCUR_E_INVAL, "|I_i| must be <= 256");
+        core *= ranks[i];
+    }
+    if (core > rtcur::kMaxCore) return fail(h, RTCUR_E_INVAL, "prod(r_i) must be <= 4096");
+    int64_t total = 1;
+    for (int i = 0; i < n; ++i) total *= sh.d[i];
+    if (total > ((int64_t)1 << 40)) return fail(h, RTCUR_E_INVAL, "tensor too large");
+    int64_t nblk = 1;
+    for (int i = 1; i < n; ++i) nblk *= sh.s[i];
+    nblk *= sh.s[0];
+    for (int i = 0; i < n; ++i) {
+        int64_t P = 1, m = 1;
+        for (int j = 0; j < n; ++j) {
+            if (j == i) continue;
+            P *= sh.d[j];
+            m *= sh.s[j];
+        }
+        if (J_sizes) m = J_sizes[i];
+        if (m < ranks[i] || m > P) return fail(h, RTCUR_E_INVAL, "need r_i <= |J_i| <= prod of other dims");
+        if (m > ((int64_t)1 << 31) - 1) return fail(h, RTCUR_E_INVAL, "|J_i| too large");
+        sh.m[i] = m;
+        nblk += sh.d[i] * m;
+    }
+    if (nblk > ((int64_t)1 << 36)) return fail(h, RTCUR_E_INVAL, "sampled blocks too large");
+    return RTCUR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rtcur_create(rtcur_t* out, int device, void* hip_stream, int variant, int compute_dtype) {
+    if (!out) return RTCUR_E_INVAL;
+    *out = nullptr;
+    if (variant != RTCUR_FIXED && variant != RTCUR_RESAMPLE) return RTCUR_E_INVAL;
+    if (compute_dtype != RTCUR_F64 && compute_dtype != RTCUR_F32) return RTCUR_E_INVAL;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return RTCUR_E_HIP;
+    if (device < 0 || device >= count) return RTCUR_E_INVAL;
+    if (hipSetDevice(device) != hipSuccess) return RTCUR_E_HIP;
+    rtcur_t h = new (std::nothrow) rtcur_s();
+    if (!h) return RTCUR_E_NOMEM;
+    h->device = device;
+    h->stream = static_cast<hipStream_t>(hip_stream);
+    h->variant = variant;
+    h->dtype = compute_dtype;
+    *out = h;
+    return RTCUR_OK;
+}
+
+int rtcur_solve(rtcur_t h, const void* X, int x_dtype, int32_t n, const int64_t* dims,
+                const int32_t* ranks, const int64_t* I_sizes, const int64_t* J_sizes,
+                double zeta0, double gamma, double tol, int32_t max_iter, uint64_t seed,
+                rtcur_info* info) {
+    if (!h) return RTCUR_E_INVAL;
+    h->have_result = false;
+    if (!X) return fail(h, RTCUR_E_INVAL, "X is null");
+    if (std::isnan(zeta0) || std::isinf(zeta0)) return fail(h, RTCUR_E_INVAL, "zeta0 not finite");
+    Shape sh;
+    int rc = validate(h, n, dims, ranks, I_sizes, J_sizes, gamma, tol, max_iter, x_dtype, sh);
+    if (rc != RTCUR_OK) {
+        h->info.status = rc;
+        if (info) *info = h->info;
+        return rc;
+    }
+    try {
+        rc = rtcur::solve(h, X, x_dtype, sh, zeta0, gamma, tol, max_iter, seed);
+    } catch (const std::bad_alloc&) {
+        rc = fail(h, RTCUR_E_NOMEM, "host allocation failed");
+    } catch (...) {
+        rc = fail(h, RTCUR_E_STATE, "internal error");
+    }
+    if (rc < 0) {
+        std::memset(&h->info, 0, sizeof(h->info));
+        h->info.status = rc;
+    }
+    if (info) *info = h->info;
+    return rc;
+}
+
+int rtcur_reconstruct(rtcur_t h, void* L_out, int out_dtype) {
+    if (!h) return RTCUR_E_INVAL;
+    if (!L_out) return fail(h, RTCUR_E_INVAL, "L_out is null");
+    if (out_dtype != RTCUR_F64 && out_dtype != RTCUR_F32)
+        return fail(h, RTCUR_E_INVAL, "out_dtype must be RTCUR_F64 or RTCUR_F32");
+    return rtcur::reconstruct(h, L_out, out_dtype);
+}
+
+int rtcur_destroy(rtcur_t h) {
+    if (!h) return RTCUR_OK;
+    rtcur::release(h);
+    delete h;
+    return RTCUR_OK;
+}
+
+int rtcur_get_indices(rtcur_t h, int32_t mode, int32_t which, int64_t* out, int64_t cap,
+                      int64_t* len) {
+    if (!h) return RTCUR_E_INVAL;
+    if (!h->have_result) return fail(h, RTCUR_E_STATE, "no successful solve");
+    if (mode < 0 || mode >= h->shape.n || (which != 0 && which != 1))
+        return fail(h, RTCUR_E_INVAL, "mode or which out of range");
+    const std::vector<int64_t>& v = which == 0 ? h->sample.I[mode] : h->sample.Jcols[mode];
+    if (len) *len = (int64_t)v.size();
+    if (out) {
+        const int64_t k = cap < (int64_t)v.size() ? cap : (int64_t)v.size();
+        if (k > 0) std::memcpy(out, v.data(), sizeof(int64_t) * k);
+    }
+    return RTCUR_OK;
+}
+
+int rtcur_get_history(rtcur_t h, double* err, double* zeta, int32_t cap, int32_t* len) {
+    if (!h) return RTCUR_E_INVAL;
+    if (!h->have_result) return fail(h, RTCUR_E_STATE, "no successful solve");
+    const int32_t k = (int32_t)h->err_hist.size();
+    if (len) *len = k;
+    const int32_t q = cap < k ? cap : k;
+    for (int32_t j = 0; j < q; ++j) {
+        if (err) err[j] = h->err_hist[j];
+        if (zeta) zeta[j] = h->zeta_hist[j];
+    }
+    return RTCUR_OK;
+}
+
+int rtcur_get_block(rtcur_t h, int32_t block, int32_t what, double* out, int64_t cap,
+                    int64_t* len) {
+    if (!h) return RTCUR_E_INVAL;
+    return rtcur::get_block(h, block, what, out, cap, len);
+}
+
+int rtcur_get_tucker(rtcur_t h, double* core, double* const* B) {
+    if (!h) return RTCUR_E_INVAL;
+    return rtcur::get_tucker(h, core, B);
+}
+
+int rtcur_sample(uint64_t seed, int64_t t, int32_t n, const int64_t* dims,
+                 const int64_t* I_sizes, const int64_t* J_sizes, int32_t mode, int32_t which,
+                 int64_t* out, int64_t cap, int64_t* len) {
+    if (n < 2 || n > rtcur::kMaxModes || !dims || !I_sizes) return RTCUR_E_INVAL;
+    if (mode < 0 || mode >= n || (which != 0 && which != 1) || t < 0) return RTCUR_E_INVAL;
+    Shape sh;
+    sh.n = n;
+    sh.chidori = (J_sizes == nullptr);
+    for (int i = 0; i < n; ++i) {
+        if (dims[i] < 1 || I_sizes[i] < 0 || I_sizes[i] > dims[i]) return RTCUR_E_INVAL;
+        sh.d[i] = dims[i];
+        sh.s[i] = I_sizes[i];
+        sh.r[i] = 1;
+    }
+    for (int i = 0; i < n; ++i) {
+        int64_t P = 1, m = 1;
+        for (int j = 0; j < n; ++j)
+            if (j != i) {
+                P *= dims[j];
+                m *= I_sizes[j];
+            }
+        if (J_sizes) {
+            if (J_sizes[i] < 0 || J_sizes[i] > P) return RTCUR_E_INVAL;
+            m = J_sizes[i];
+        }
+        sh.m[i] = m;
+    }
+    rtcur::SampleHost smp;
+    try {
+        rtcur::draw_sample(seed, t, sh, sh.chidori, smp);
+    } catch (...) {
+        return RTCUR_E_NOMEM;
+    }
+    const std::vector<int64_t>& v = which == 0 ? smp.I[mode] : smp.Jcols[mode];
+    if (len) *len = (int64_t)v.size();
+    if (out) {
+        const int64_t k = cap < (int64_t)v.size() ? cap : (int64_t)v.size();
+        if (k > 0) std::memcpy(out, v.data(), sizeof(int64_t) * k);
+    }
+    return RTCUR_OK;
+}
+
+const char* rtcur_strerror(int status) {
+    switch (status) {
+        case RTCUR_OK: return "ok";
+        case RTCUR_NOT_CONVERGED: return "not converged within max_iter";
+        case RTCUR_E_INVAL: return "invalid argument";
+        case RTCUR_E_NOMEM: return "out of memory";
+        case RTCUR_E_HIP: return "HIP runtime error";
+        case RTCUR_E_RANK: return "rank-deficient U_i";
+        case RTCUR_E_NONFINITE: return "non-finite value";
+        case RTCUR_E_STATE: return "invalid call order";
+        default: return "unknown status";
+    }
+}
+
+const char* rtcur_last_error(rtcur_t h) {
+    if (!h) return "null handle";
+    return h->last_error.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,132 @@
+// Internal declarations of librtcur: problem shape, host sample, the device
+// problem descriptor passed to kernels, the device-side loop state, and the
+// handle.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "rtcur.h"
+
+namespace rtcur {
+
+constexpr int kMaxModes = 4;
+constexpr int kMaxBlocks = kMaxModes + 1;
+constexpr int kMaxRank = 16;
+constexpr int kMaxCore = 4096;   // prod(r_i), the Tucker core held in LDS
+constexpr int kMaxS = 256;       // |I_i|, the eigensolver's matrix side
+
+// ---------------------------------------------------------------- host side
+
+struct Shape {
+    int n = 0;
+    int64_t d[kMaxModes] = {};
+    int r[kMaxModes] = {};
+    int64_t s[kMaxModes] = {};   // |I_i|
+    int64_t m[kMaxModes] = {};   // |J_i| (chidori: prod_{j != i} s_j)
+    bool chidori = true;
+};
+
+struct SampleHost {
+    std::vector<std::vector<int64_t>> I;      // per mode, sorted
+    std::vector<std::vector<int64_t>> Jcols;  // per mode: unfolding columns
+    std::vector<std::vector<int32_t>> Jtup;   // per mode: [m_i][n-1] tuples
+};
+
+void draw_sample(uint64_t seed, int64_t t, const Shape& sh, bool chidori,
+                 SampleHost& out);
+
+// ------------------------------------------------------- device descriptors
+
+// One sampled block.  Block 0 is R (rows I_0, columns the product of
+// I_1..I_{n-1}); block 1+i is C_i (rows all of mode i, columns J_i).  Blocks
+// are stored row-major, one after another, in every block-sized buffer.
+struct BlockDev {
+    int mode;                 // mode that indexes the block's rows
+    int r;                    // rank of that mode
+    int nrows;
+    int ncols;
+    int64_t off;              // element offset of the block
+    int64_t hoff;             // element offset of the block's H (RP x ncols)
+    int64_t moff;             // 64-bit word offset of the support bitmask
+    int words;                // bitmask words per row
+    int tile0, tile1;         // range of the block's tiles in the tile table
+    const int32_t* rowidx;    // row -> index in `mode` (nullptr: identity)
+    const int64_t* colx;      // column -> X offset of the other modes' indices
+    const int32_t* cidx;      // [n-1][ncols] other-mode index of each column
+};
+
+struct Prob {
+    int n;
+    int nblk;
+    int rp;                   // padded rank: 4, 8 or 16
+    int core;                 // prod r_i
+    int d[kMaxModes];
+    int r[kMaxModes];
+    int s[kMaxModes];
+    int m[kMaxModes];
+    int64_t xstride[kMaxModes];
+    int64_t boff[kMaxModes];  // offset of B_i (d_i x rp) in the factor buffer
+    int64_t woff[kMaxModes];  // offset of W_i / Y_i (s_i x rp), float64
+    int64_t goff[kMaxModes];  // offset of the Gram of mode i (s_i x s_i)
+    int64_t zoff[kMaxModes];  // offset of Z_i (rp x m_i), float64
+    int64_t loff[kMaxModes];  // offset of lambda_i (rp)
+    const int32_t* I[kMaxModes];   // sampled rows of each mode (device)
+    BlockDev blk[kMaxBlocks];
+};
+
+// Loop state that lives on the device so that iterations can be queued ahead
+// of the host: every iteration kernel returns at once when `stop` is set.
+struct DevState {
+    int stop;            // 1: stop (converged, zero data, or error)
+    int status;          // rtcur_status of the stop
+    int final_iter;      // k of the returned iterate
+    int converged;
+    double zeta0;
+    double den;          // denominator of e^(k) on the current sample
+    int eig_steps;
+    int eig_unconverged;
+    unsigned counter[4]; // last-workgroup counters (gather, ht, spare)
+};
+
+// ------------------------------------------------------------------ handle
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+struct rtcur_handle_impl;  // fwd
+
+}  // namespace rtcur
+
+struct rtcur_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int variant = RTCUR_FIXED;
+    int dtype = RTCUR_F64;
+    std::string last_error;
+    // results of the last solve
+    bool have_result = false;
+    rtcur::Shape shape;
+    rtcur::SampleHost sample;
+    std::vector<double> err_hist, zeta_hist;
+    rtcur_info info{};
+    // device workspace (owned; grown on demand, freed by destroy)
+    std::vector<rtcur::DevBuf> bufs;
+    void* impl = nullptr;      // solver-private state (see solver.hip)
+};
+
+namespace rtcur {
+int solve(rtcur_s* h, const void* X, int x_dtype, const Shape& sh,
+          double zeta0, double gamma, double tol, int max_iter,
+          uint64_t seed);
+int reconstruct(rtcur_s* h, void* out, int out_dtype);
+int get_block(rtcur_s* h, int block, int what, double* out, int64_t cap,
+              int64_t* len);
+int get_tucker(rtcur_s* h, double* core, double* const* B);
+void release(rtcur_s* h);
+}  // namespace rtcur

@@ -1,0 +1,874 @@
+// Host orchestration of the RTCUR hot loop on one gfx950 device.
+//
+// Per iteration (RTCUR-F), all on the handle's stream and queued ahead of
+// the host (kernels return at once after the device-side stop flag is set):
+//   k_ht     fused residual, e^(k) numerator, hard threshold, support bits
+//   k_gram   Gram_i = U_i U_i^T on the float64 matrix cores
+//   k_eig    top-r_i eigenpairs -> W_i, lambda_i, Y_i = W_i / lambda_i
+//   k_zmat   Z_i = Y_i^T U_i                  (V_i S_i^-1 = Z_i^T)
+//   k_contract x n   core G = R x_i W_i^T
+//   k_bfac   B_i = C_i Z_i^T
+//   k_hexp   H_b = G x_{j != mode} B_j on each block's columns
+// so that the next k_ht forms L on the blocks as B_mode H_b (Section 3.3).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <vector>
+
+#include "internal.h"
+#include "kernels.h"
+
+namespace rtcur {
+
+#define HIPCHK(expr)                                                       \
+    do {                                                                   \
+        hipError_t e_ = (expr);                                            \
+        if (e_ != hipSuccess) {                                            \
+            h->last_error = std::string(#expr) + ": " + hipGetErrorString(e_); \
+            return RTCUR_E_HIP;                                            \
+        }                                                                  \
+    } while (0)
+
+namespace {
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+int pad_rank(int r) { return r <= 4 ? 4 : (r <= 8 ? 8 : 16); }
+
+// A carve-out plan: bytes per named region, laid out in one device arena.
+struct Arena {
+    size_t total = 0;
+    size_t add(size_t bytes) {
+        size_t off = total;
+        total = align_up(total + std::max<size_t>(bytes, 1), 256);
+        return off;
+    }
+};
+
+}  // namespace
+
+// Solver-private state kept in the handle between calls.
+struct Impl {
+    void* arena = nullptr;
+    size_t arena_bytes = 0;
+    void* scratch = nullptr;        // getters / reconstruct temporaries
+    size_t scratch_bytes = 0;
+    DevState* st_host = nullptr;    // pinned mirror of the device state
+    int max_dyn_lds = 65536;
+
+    // layout of the current solve
+    Prob P{};
+    int esize = 8;                  // element size of the compute dtype
+    int64_t nblk_elems = 0;
+    int64_t h_elems = 0, mask_words = 0, bf_elems = 0, w_elems = 0, z_elems = 0,
+            g_elems = 0, l_elems = 0, ctmp_elems = 0;
+    std::vector<int4> ht_tiles, gram_items, bfac_items;
+    std::vector<int2> z_tiles, h_tiles;
+    int n_gram_pairs = 0, n_bfac_groups = 0;
+
+    // device regions (inside the arena)
+    void *XO = nullptr, *C[2] = {nullptr, nullptr}, *Bf = nullptr, *H = nullptr;
+    uint64_t* mask[2] = {nullptr, nullptr};
+    double *W = nullptr, *Y = nullptr, *lam = nullptr, *Z = nullptr, *gram = nullptr,
+           *gpart = nullptr, *bpart = nullptr, *Bd = nullptr, *Gd = nullptr,
+           *ctmp[2] = {nullptr, nullptr}, *part = nullptr, *err_hist = nullptr;
+    unsigned *gcnt = nullptr, *bcnt = nullptr;
+    DevState* st = nullptr;
+    int4 *d_ht_tiles = nullptr, *d_gram_items = nullptr, *d_bfac_items = nullptr;
+    int2 *d_z_tiles = nullptr, *d_h_tiles = nullptr;
+    char* d_idx = nullptr;          // sample-dependent index data
+    size_t idx_bytes = 0;
+    size_t hist_len = 0;
+
+    // result bookkeeping
+    int final_iter = 0;
+    int cur = 0;                    // which C / mask buffer holds C^k
+};
+
+static Impl* impl_of(rtcur_s* h) {
+    if (!h->impl) h->impl = new Impl();
+    return static_cast<Impl*>(h->impl);
+}
+
+void release(rtcur_s* h) {
+    Impl* im = static_cast<Impl*>(h->impl);
+    if (!im) return;
+    (void)hipSetDevice(h->device);
+    if (im->arena) (void)hipFree(im->arena);
+    if (im->scratch) (void)hipFree(im->scratch);
+    if (im->st_host) (void)hipHostFree(im->st_host);
+    delete im;
+    h->impl = nullptr;
+}
+
+// --------------------------------------------------------------- layout
+
+// Host-side index data for one sample, packed for a single upload.
+struct IdxPack {
+    std::vector<char> bytes;
+    size_t I_off[kMaxModes], rowidx_off, colx_off[kMaxBlocks], cidx_off[kMaxBlocks];
+};
+
+static void pack_indices(const Shape& sh, const SampleHost& smp, IdxPack& pk) {
+    const int n = sh.n;
+    size_t off = 0;
+    auto reserve = [&](size_t bytes) {
+        size_t o = off;
+        off = align_up(off + bytes, 256);
+        return o;
+    };
+    for (int i = 0; i < n; ++i) pk.I_off[i] = reserve(sizeof(int32_t) * sh.s[i]);
+    pk.rowidx_off = pk.I_off[0];  // the R block's rows are I_0
+    int64_t ncol[kMaxBlocks];
+    ncol[0] = 1;
+    for (int j = 1; j < n; ++j) ncol[0] *= sh.s[j];
+    for (int i = 0; i < n; ++i) ncol[1 + i] = sh.m[i];
+    for (int b = 0; b <= n; ++b) {
+        pk.colx_off[b] = reserve(sizeof(int64_t) * ncol[b]);
+        pk.cidx_off[b] = reserve(sizeof(int32_t) * ncol[b] * (n - 1));
+    }
+    pk.bytes.assign(off, 0);
+    char* base = pk.bytes.data();
+    for (int i = 0; i < n; ++i) {
+        int32_t* p = reinterpret_cast<int32_t*>(base + pk.I_off[i]);
+        for (int64_t a = 0; a < sh.s[i]; ++a) p[a] = (int32_t)smp.I[i][a];
+    }
+    int64_t xstride[kMaxModes];
+    xstride[n - 1] = 1;
+    for (int j = n - 2; j >= 0; --j) xstride[j] = xstride[j + 1] * sh.d[j + 1];
+    // R block: columns = product of I_1..I_{n-1}, last fastest
+    {
+        int64_t* cx = reinterpret_cast<int64_t*>(base + pk.colx_off[0]);
+        int32_t* ci = reinterpret_cast<int32_t*>(base + pk.cidx_off[0]);
+        for (int64_t c = 0; c < ncol[0]; ++c) {
+            int64_t rem = c, off2 = 0;
+            for (int j = n - 1; j >= 1; --j) {
+                const int64_t a = rem % sh.s[j];
+                rem /= sh.s[j];
+                const int64_t v = smp.I[j][a];
+                off2 += v * xstride[j];
+                ci[(int64_t)(j - 1) * ncol[0] + c] = (int32_t)v;
+            }
+            cx[c] = off2;
+        }
+    }
+    for (int i = 0; i < n; ++i) {
+        int64_t* cx = reinterpret_cast<int64_t*>(base + pk.colx_off[1 + i]);
+        int32_t* ci = reinterpret_cast<int32_t*>(base + pk.cidx_off[1 + i]);
+        const int64_t m = sh.m[i];
+        const std::vector<int32_t>& tup = smp.Jtup[i];
+        for (int64_t c = 0; c < m; ++c) {
+            int64_t off2 = 0;
+            int q = 0;
+            for (int j = 0; j < n; ++j) {
+                if (j == i) continue;
+                const int64_t v = tup[(size_t)c * (n - 1) + q];
+                off2 += v * xstride[j];
+                ci[(int64_t)q * m + c] = (int32_t)v;
+                ++q;
+            }
+            cx[c] = off2;
+        }
+    }
+}
+
+// Build block descriptors, offsets and work lists; size the arena.
+static void plan(Impl& im, const Shape& sh, int esize, Arena& ar,
+                 size_t& o_XO, size_t& o_C0, size_t& o_C1, size_t& o_m0,
+                 size_t& o_m1, size_t& o_Bf, size_t& o_H, size_t& o_W, size_t& o_Y,
+                 size_t& o_lam, size_t& o_Z, size_t& o_gram, size_t& o_gpart,
+                 size_t& o_bpart, size_t& o_Bd, size_t& o_Gd, size_t& o_ct0,
+                 size_t& o_ct1, size_t& o_part, size_t& o_hist, size_t& o_gcnt,
+                 size_t& o_bcnt, size_t& o_st, size_t& o_tiles, size_t& o_idx,
+                 size_t idx_bytes, int max_iter) {
+    const int n = sh.n;
+    Prob& P = im.P;
+    std::memset(&P, 0, sizeof(P));
+    P.n = n;
+    P.nblk = n + 1;
+    int rmax = 1;
+    P.core = 1;
+    for (int i = 0; i < n; ++i) {
+        P.d[i] = (int)sh.d[i];
+        P.r[i] = sh.r[i];
+        P.s[i] = (int)sh.s[i];
+        P.m[i] = (int)sh.m[i];
+        rmax = std::max(rmax, sh.r[i]);
+        P.core *= sh.r[i];
+    }
+    const int RP = pad_rank(rmax);
+    P.rp = RP;
+    P.xstride[n - 1] = 1;
+    for (int j = n - 2; j >= 0; --j) P.xstride[j] = P.xstride[j + 1] * sh.d[j + 1];
+    int64_t off = 0, hoff = 0, moff = 0;
+    im.ht_tiles.clear();
+    for (int b = 0; b <= n; ++b) {
+        BlockDev& bd = P.blk[b];
+        if (b == 0) {
+            bd.mode = 0;
+            bd.nrows = (int)sh.s[0];
+            int64_t nc = 1;
+            for (int j = 1; j < n; ++j) nc *= sh.s[j];
+            bd.ncols = (int)nc;
+        } else {
+            bd.mode = b - 1;
+            bd.nrows = (int)sh.d[b - 1];
+            bd.ncols = (int)sh.m[b - 1];
+        }
+        bd.r = sh.r[bd.mode];
+        bd.off = off;
+        bd.hoff = hoff;
+        bd.moff = moff;
+        bd.words = (bd.ncols + 63) / 64;
+        off += (int64_t)bd.nrows * bd.ncols;
+        hoff += (int64_t)RP * bd.ncols;
+        moff += (int64_t)bd.nrows * bd.words;
+        bd.tile0 = (int)im.ht_tiles.size();
+        for (int r0 = 0; r0 < bd.nrows; r0 += kTileRows)
+            for (int c0 = 0; c0 < bd.ncols; c0 += kTileCols)
+                im.ht_tiles.push_back(make_int4(b, r0, c0, 0));
+        bd.tile1 = (int)im.ht_tiles.size();
+    }
+    im.nblk_elems = off;
+    im.h_elems = hoff;
+    im.mask_words = moff;
+    im.bf_elems = im.w_elems = im.z_elems = im.g_elems = im.l_elems = 0;
+    for (int i = 0; i < n; ++i) {
+        P.boff[i] = im.bf_elems;
+        im.bf_elems += (int64_t)sh.d[i] * RP;
+        P.woff[i] = im.w_elems;
+        im.w_elems += sh.s[i] * RP;
+        P.goff[i] = im.g_elems;
+        im.g_elems += sh.s[i] * sh.s[i];
+        P.zoff[i] = im.z_elems;
+        im.z_elems += (int64_t)RP * sh.m[i];
+        P.loff[i] = im.l_elems;
+        im.l_elems += RP;
+    }
+    // Gram work: upper-triangular 16x16 tile pairs x 1024-column chunks
+    im.gram_items.clear();
+    int pid = 0;
+    for (int i = 0; i < n; ++i) {
+        const int nt = (int)((sh.s[i] + 15) / 16);
+        const int nkc = (int)((sh.m[i] + kGramKCW - 1) / kGramKCW);
+        for (int ta = 0; ta < nt; ++ta)
+            for (int tb = ta; tb < nt; ++tb, ++pid)
+                for (int kc = 0; kc < nkc; ++kc)
+                    im.gram_items.push_back(make_int4(i, ta | (tb << 16), kc | (nkc << 16), pid));
+    }
+    im.n_gram_pairs = pid;
+    // B_i work: 16-row blocks x 1024-column chunks
+    im.bfac_items.clear();
+    int gid = 0;
+    for (int i = 0; i < n; ++i) {
+        const int nrb = (int)((sh.d[i] + kBfacRows - 1) / kBfacRows);
+        const int nkc = (int)((sh.m[i] + kBfacKC - 1) / kBfacKC);
+        for (int rb = 0; rb < nrb; ++rb, ++gid)
+            for (int kc = 0; kc < nkc; ++kc)
+                im.bfac_items.push_back(make_int4(i, rb, kc | (nkc << 16), gid));
+    }
+    im.n_bfac_groups = gid;
+    im.z_tiles.clear();
+    for (int i = 0; i < n; ++i)
+        for (int64_t c0 = 0; c0 < sh.m[i]; c0 += kThreads)
+            im.z_tiles.push_back(make_int2(i, (int)c0));
+    im.h_tiles.clear();
+    for (int b = 0; b <= n; ++b)
+        for (int cb = 0; cb * kThreads < P.blk[b].ncols; ++cb)
+            im.h_tiles.push_back(make_int2(b, cb));
+    // core-stage temporaries: the largest intermediate of G = R x_i W_i^T
+    int64_t big = 0, lead = 1;
+    for (int j = 0; j < n; ++j) {
+        const int q = n - 1 - j;
+        lead *= sh.r[q];
+        int64_t rest = 1;
+        for (int l = 0; l < q; ++l) rest *= sh.s[l];
+        big = std::max(big, lead * rest);
+    }
+    im.ctmp_elems = big;
+
+    const size_t nb = (size_t)im.nblk_elems;
+    o_XO = ar.add(nb * esize);
+    o_C0 = ar.add(nb * esize);
+    o_C1 = ar.add(nb * esize);
+    o_m0 = ar.add(sizeof(uint64_t) * im.mask_words);
+    o_m1 = ar.add(sizeof(uint64_t) * im.mask_words);
+    o_Bf = ar.add(im.bf_elems * esize);
+    o_H = ar.add(im.h_elems * esize);
+    o_W = ar.add(sizeof(double) * im.w_elems);
+    o_Y = ar.add(sizeof(double) * im.w_elems);
+    o_lam = ar.add(sizeof(double) * im.l_elems);
+    o_Z = ar.add(sizeof(double) * im.z_elems);
+    o_gram = ar.add(sizeof(double) * im.g_elems);
+    o_gpart = ar.add(sizeof(double) * 256 * im.gram_items.size());
+    o_bpart = ar.add(sizeof(double) * kBfacRows * RP * im.bfac_items.size());
+    o_Bd = ar.add(sizeof(double) * im.bf_elems);
+    o_Gd = ar.add(sizeof(double) * P.core);
+    o_ct0 = ar.add(sizeof(double) * im.ctmp_elems);
+    o_ct1 = ar.add(sizeof(double) * im.ctmp_elems);
+    o_part = ar.add(sizeof(double) * 2 * std::max<size_t>(im.ht_tiles.size(), 2048));
+    im.hist_len = (size_t)max_iter + 2;
+    o_hist = ar.add(sizeof(double) * im.hist_len);
+    o_gcnt = ar.add(sizeof(unsigned) * std::max(im.n_gram_pairs, 1));
+    o_bcnt = ar.add(sizeof(unsigned) * std::max(im.n_bfac_groups, 1));
+    o_st = ar.add(sizeof(DevState));
+    o_tiles = ar.add(sizeof(int4) * (im.ht_tiles.size() + im.gram_items.size() +
+                                     im.bfac_items.size()) +
+                     sizeof(int2) * (im.z_tiles.size() + im.h_tiles.size()) + 1024);
+    o_idx = ar.add(idx_bytes);
+}
+
+// ------------------------------------------------------------ the solver
+
+template <typename T, int RP>
+struct Runner {
+    rtcur_s* h;
+    Impl& im;
+    hipStream_t s;
+
+    int gather(const void* X, int xdt, int flags) {
+        const int nt = (int)im.ht_tiles.size();
+        if (xdt == RTCUR_F64)
+            hipLaunchKernelGGL((k_gather<double, T>), dim3(nt), dim3(kThreads), 0, s,
+                               (const double*)X, im.P, im.d_ht_tiles, (T*)im.XO,
+                               im.part, flags, im.st);
+        else
+            hipLaunchKernelGGL((k_gather<float, T>), dim3(nt), dim3(kThreads), 0, s,
+                               (const float*)X, im.P, im.d_ht_tiles, (T*)im.XO,
+                               im.part, flags, im.st);
+        HIPCHK(hipGetLastError());
+        return 0;
+    }
+
+    int ht(int kcur, int flags, const T* Cold, T* Cnew, uint64_t* mask,
+           double gamma, double tol) {
+        const int nt = (int)im.ht_tiles.size();
+        hipLaunchKernelGGL((k_ht<T, RP>), dim3(nt), dim3(kThreads), 0, s, im.P,
+                           im.d_ht_tiles, (const T*)im.XO, Cold, Cnew, mask,
+                           (const T*)im.Bf, (const T*)im.H, gamma, kcur, flags, tol,
+                           im.part, im.err_hist, im.st);
+        HIPCHK(hipGetLastError());
+        return 0;
+    }
+
+    int hexp() {
+        hipLaunchKernelGGL((k_hexp<T, RP>), dim3((int)im.h_tiles.size()), dim3(kThreads),
+                           0, s, im.P, im.d_h_tiles, (const T*)im.Bf, im.Gd, (T*)im.H,
+                           im.st, 0, (int64_t)0);
+        HIPCHK(hipGetLastError());
+        return 0;
+    }
+
+    // Step (II): L-update from C (equations 5-6) into B_i, G, H_b.
+    int lupdate(const T* C, int warm) {
+        const Prob& P = im.P;
+        const int n = P.n;
+        hipLaunchKernelGGL((k_gram<T>), dim3((int)im.gram_items.size()), dim3(kThreads), 0,
+                           s, P, C, im.d_gram_items, im.gpart, im.gcnt, im.gram, im.st);
+        HIPCHK(hipGetLastError());
+        int smax = 0, rmax = 0;
+        for (int i = 0; i < n; ++i) {
+            smax = std::max(smax, P.s[i]);
+            rmax = std::max(rmax, P.r[i]);
+        }
+        size_t lds = sizeof(double) * (size_t)2 * smax * rmax;
+        const size_t lds_g = lds + sizeof(double) * (size_t)smax * smax;
+        int use_lds = 0;
+        if (lds_g <= (size_t)im.max_dyn_lds) {
+            lds = lds_g;
+            use_lds = 1;
+        }
+        hipLaunchKernelGGL(k_eig, dim3(n), dim3(kThreads), lds, s, P, im.gram, im.W,
+                           im.Y, im.lam, warm, 200, 1e-13, use_lds, im.st);
+        HIPCHK(hipGetLastError());
+        hipLaunchKernelGGL((k_zmat<T, RP>), dim3((int)im.z_tiles.size()), dim3(kThreads), 0,
+                           s, P, C, im.Y, im.Z, im.d_z_tiles, im.st);
+        HIPCHK(hipGetLastError());
+        // core G = R x_i W_i^T, last mode first
+        int64_t lead = 1;
+        for (int j = 0; j < n; ++j) {
+            const int q = n - 1 - j;
+            int64_t rest = 1;
+            for (int l = 0; l < q; ++l) rest *= P.s[l];
+            const int M = (int)(lead * rest), K = P.s[q];
+            double* out = (j == n - 1) ? im.Gd : im.ctmp[j % 2];
+            const int nwg = (M + 4 * kContractRowsPerWave - 1) / (4 * kContractRowsPerWave);
+            if (j == 0)
+                hipLaunchKernelGGL((k_contract<T, RP>), dim3(nwg), dim3(kThreads), 0, s,
+                                   C + P.blk[0].off, M, K, im.W + P.woff[q], P.r[q], out,
+                                   im.st);
+            else
+                hipLaunchKernelGGL((k_contract<double, RP>), dim3(nwg), dim3(kThreads), 0, s,
+                                   (const double*)im.ctmp[(j - 1) % 2], M, K,
+                                   im.W + P.woff[q], P.r[q], out, im.st);
+            HIPCHK(hipGetLastError());
+            lead *= P.r[q];
+        }
+        hipLaunchKernelGGL((k_bfac<T, RP>), dim3((int)im.bfac_items.size()), dim3(kThreads),
+                           0, s, P, C, im.Z, im.d_bfac_items, im.bpart, im.bcnt, (T*)im.Bf,
+                           im.Bd, im.st);
+        HIPCHK(hipGetLastError());
+        return hexp();
+    }
+
+    int read_state(DevState& out) {
+        HIPCHK(hipMemcpyAsync(im.st_host, im.st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        out = *im.st_host;
+        return 0;
+    }
+
+    int upload_sample(const SampleHost& smp, const Shape& sh) {
+        IdxPack pk;
+        pack_indices(sh, smp, pk);
+        if (pk.bytes.size() > im.idx_bytes) {
+            h->last_error = "internal: index region too small";
+            return RTCUR_E_STATE;
+        }
+        HIPCHK(hipMemcpyAsync(im.d_idx, pk.bytes.data(), pk.bytes.size(),
+                              hipMemcpyHostToDevice, s));
+        HIPCHK(hipStreamSynchronize(s));
+        Prob& P = im.P;
+        for (int i = 0; i < sh.n; ++i)
+            P.I[i] = reinterpret_cast<const int32_t*>(im.d_idx + pk.I_off[i]);
+        for (int b = 0; b <= sh.n; ++b) {
+            P.blk[b].rowidx = b == 0 ? reinterpret_cast<const int32_t*>(im.d_idx + pk.rowidx_off)
+                                     : nullptr;
+            P.blk[b].colx = reinterpret_cast<const int64_t*>(im.d_idx + pk.colx_off[b]);
+            P.blk[b].cidx = reinterpret_cast<const int32_t*>(im.d_idx + pk.cidx_off[b]);
+        }
+        return 0;
+    }
+
+    int run(const void* X, int xdt, const Shape& sh, double zeta0, double gamma,
+            double tol, int max_iter, uint64_t seed) {
+        const bool resample = h->variant == RTCUR_RESAMPLE;
+        int rc;
+        draw_sample(seed, 0, sh, sh.chidori, h->sample);
+        if ((rc = upload_sample(h->sample, sh))) return rc;
+        hipLaunchKernelGGL(k_init_state, dim3(1), dim3(64), 0, s, im.st, zeta0 > 0 ? zeta0 : 0.0);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemsetAsync(im.gcnt, 0, sizeof(unsigned) * std::max(im.n_gram_pairs, 1), s));
+        HIPCHK(hipMemsetAsync(im.bcnt, 0, sizeof(unsigned) * std::max(im.n_bfac_groups, 1), s));
+        // zero factors so that a k = 0 result reconstructs to L = 0
+        HIPCHK(hipMemsetAsync(im.Bf, 0, im.bf_elems * sizeof(T), s));
+        HIPCHK(hipMemsetAsync(im.Bd, 0, im.bf_elems * sizeof(double), s));
+        HIPCHK(hipMemsetAsync(im.Gd, 0, im.P.core * sizeof(double), s));
+        HIPCHK(hipMemsetAsync(im.err_hist, 0, im.hist_len * sizeof(double), s));
+        if (!(zeta0 > 0)) {
+            int64_t N = 1;
+            for (int i = 0; i < sh.n; ++i) N *= sh.d[i];
+            const int nwg = 2048;
+            if (xdt == RTCUR_F64)
+                hipLaunchKernelGGL((k_absmax<double>), dim3(nwg), dim3(kThreads), 0, s,
+                                   (const double*)X, N, im.part, im.st);
+            else
+                hipLaunchKernelGGL((k_absmax<float>), dim3(nwg), dim3(kThreads), 0, s,
+                                   (const float*)X, N, im.part, im.st);
+            HIPCHK(hipGetLastError());
+        }
+        if ((rc = gather(X, xdt, kFirstGather))) return rc;
+        DevState ds;
+        if ((rc = read_state(ds))) return rc;
+        int K = 0;
+        bool stopped = ds.stop != 0;
+        if (!stopped && tol >= 1.0) stopped = true;  // e^(0) = 1 <= tol
+        if (!stopped) {
+            if (!resample) {
+                rc = loop_fixed(gamma, tol, max_iter, ds);
+            } else {
+                rc = loop_resample(X, xdt, sh, gamma, tol, max_iter, seed, ds);
+            }
+            if (rc) return rc;
+        }
+        if (ds.status < 0) {
+            h->last_error = ds.status == RTCUR_E_RANK ? "U_i has numerical rank below r_i"
+                                                      : "non-finite value in X or e^(k)";
+            h->have_result = false;
+            return ds.status;
+        }
+        K = ds.stop ? ds.final_iter : max_iter;
+        if (tol >= 1.0 && !ds.stop) K = 0;
+        im.final_iter = K;
+        im.cur = K % 2;
+        // histories
+        h->err_hist.assign(K, 0.0);
+        if (K > 0) {
+            std::vector<double> eh(K + 1);
+            HIPCHK(hipMemcpy(eh.data(), im.err_hist, sizeof(double) * (K + 1),
+                             hipMemcpyDeviceToHost));
+            for (int j = 1; j <= K; ++j) h->err_hist[j - 1] = eh[j];
+        }
+        h->zeta_hist.assign(K, 0.0);
+        double z = ds.zeta0;
+        for (int j = 0; j < K; ++j) {
+            z *= gamma;
+            h->zeta_hist[j] = z;
+        }
+        rtcur_info& info = h->info;
+        info.iters = K;
+        info.err = K > 0 ? h->err_hist[K - 1] : (ds.den == 0.0 ? 0.0 : 1.0);
+        info.converged = (K > 0 ? info.err <= tol : (tol >= 1.0 || ds.den == 0.0)) ? 1 : 0;
+        info.zeta = K > 0 ? h->zeta_hist[K - 1] : ds.zeta0;
+        info.zeta0 = ds.zeta0;
+        info.eig_steps = ds.eig_steps;
+        info.status = info.converged ? RTCUR_OK : RTCUR_NOT_CONVERGED;
+        h->have_result = true;
+        return info.status;
+    }
+
+    // C^j lives in C[j % 2]; C^0 is X_Omega itself.
+    T* cbuf(int j) { return j == 0 ? (T*)im.XO : (T*)im.C[j % 2]; }
+
+    int loop_fixed(double gamma, double tol, int max_iter, DevState& ds) {
+        int done = 0;
+        int rc;
+        double e_prev = -1.0, e_last = -1.0;
+        std::vector<double> eh(2);
+        while (done < max_iter) {
+            int chunk = 8;
+            if (done < 2) chunk = 2;
+            if (e_last > 0 && e_prev > 0 && e_last < e_prev) {
+                const double rate = e_last / e_prev;
+                const double need = std::log(tol / e_last) / std::log(rate);
+                if (std::isfinite(need)) chunk = (int)std::min(8.0, std::max(1.0, std::ceil(need)));
+            }
+            chunk = std::min(chunk, max_iter - done);
+            for (int q = 0; q < chunk; ++q) {
+                const int j = done + 1 + q;  // iteration j computes S^j, L^j
+                const int flags = kDoHT | (j > 1 ? (kHaveL | kDoE | kDecide) : 0);
+                if ((rc = ht(j - 1, flags, cbuf(j - 1), cbuf(j), im.mask[j % 2], gamma, tol)))
+                    return rc;
+                if ((rc = lupdate(cbuf(j), j > 1 ? 1 : 0))) return rc;
+            }
+            done += chunk;
+            if ((rc = read_state(ds))) return rc;
+            if (ds.stop) return 0;
+            if (done >= 2) {
+                HIPCHK(hipMemcpy(eh.data(), im.err_hist + (done - 2), 2 * sizeof(double),
+                                 hipMemcpyDeviceToHost));
+                e_prev = eh[0];
+                e_last = eh[1];
+            }
+        }
+        // e^(max_iter): one error-only pass
+        if ((rc = ht(max_iter, kHaveL | kDoE | kDecide, cbuf(max_iter), nullptr, nullptr,
+                     gamma, tol)))
+            return rc;
+        return read_state(ds);
+    }
+
+    int loop_resample(const void* X, int xdt, const Shape& sh, double gamma, double tol,
+                      int max_iter, uint64_t seed, DevState& ds) {
+        int rc;
+        for (int j = 1; j <= max_iter; ++j) {
+            if (j > 1) {
+                // new sample (t = j-1), gather there, L^(j-1) on its columns
+                draw_sample(seed, j - 1, sh, sh.chidori, h->sample);
+                if ((rc = upload_sample(h->sample, sh))) return rc;
+                if ((rc = gather(X, xdt, 0))) return rc;
+                if ((rc = hexp())) return rc;
+            }
+            const int flags = kDoHT | (j > 1 ? kHaveL : 0);
+            if ((rc = ht(j - 1, flags, nullptr, cbuf(j), im.mask[j % 2], gamma, tol))) return rc;
+            if ((rc = lupdate(cbuf(j), 0))) return rc;
+            // e^(j) on this sample
+            if ((rc = ht(j, kHaveL | kDoE | kDecide, cbuf(j), nullptr, nullptr, gamma, tol)))
+                return rc;
+            if ((rc = read_state(ds))) return rc;
+            if (ds.stop) return 0;
+        }
+        return 0;
+    }
+};
+
+// Lay out the arena for this problem and point every region into it.
+template <typename T>
+static int prepare(rtcur_s* h, Impl& im, const Shape& sh, int max_iter) {
+    IdxPack pk;
+    // index bytes depend only on sizes: size them with a zero sample
+    SampleHost zero;
+    zero.I.assign(sh.n, {});
+    zero.Jtup.assign(sh.n, {});
+    for (int i = 0; i < sh.n; ++i) {
+        zero.I[i].assign(sh.s[i], 0);
+        zero.Jtup[i].assign((size_t)sh.m[i] * (sh.n - 1), 0);
+    }
+    pack_indices(sh, zero, pk);
+    Arena ar;
+    size_t o[25];
+    plan(im, sh, sizeof(T), ar, o[0], o[1], o[2], o[3], o[4], o[5], o[6], o[7], o[8], o[9],
+         o[10], o[11], o[12], o[13], o[14], o[15], o[16], o[17], o[18], o[19], o[20], o[21],
+         o[22], o[23], o[24], pk.bytes.size(), max_iter);
+    if (ar.total > im.arena_bytes) {
+        if (im.arena) HIPCHK(hipFree(im.arena));
+        im.arena = nullptr;
+        im.arena_bytes = 0;
+        hipError_t e = hipMalloc(&im.arena, ar.total);
+        if (e != hipSuccess) {
+            im.arena = nullptr;
+            h->last_error = "device workspace allocation failed";
+            return RTCUR_E_NOMEM;
+        }
+        im.arena_bytes = ar.total;
+    }
+    char* a = static_cast<char*>(im.arena);
+    im.esize = sizeof(T);
+    im.XO = a + o[0];
+    im.C[0] = a + o[1];
+    im.C[1] = a + o[2];
+    im.mask[0] = reinterpret_cast<uint64_t*>(a + o[3]);
+    im.mask[1] = reinterpret_cast<uint64_t*>(a + o[4]);
+    im.Bf = a + o[5];
+    im.H = a + o[6];
+    im.W = reinterpret_cast<double*>(a + o[7]);
+    im.Y = reinterpret_cast<double*>(a + o[8]);
+    im.lam = reinterpret_cast<double*>(a + o[9]);
+    im.Z = reinterpret_cast<double*>(a + o[10]);
+    im.gram = reinterpret_cast<double*>(a + o[11]);
+    im.gpart = reinterpret_cast<double*>(a + o[12]);
+    im.bpart = reinterpret_cast<double*>(a + o[13]);
+    im.Bd = reinterpret_cast<double*>(a + o[14]);
+    im.Gd = reinterpret_cast<double*>(a + o[15]);
+    im.ctmp[0] = reinterpret_cast<double*>(a + o[16]);
+    im.ctmp[1] = reinterpret_cast<double*>(a + o[17]);
+    im.part = reinterpret_cast<double*>(a + o[18]);
+    im.err_hist = reinterpret_cast<double*>(a + o[19]);
+    im.gcnt = reinterpret_cast<unsigned*>(a + o[20]);
+    im.bcnt = reinterpret_cast<unsigned*>(a + o[21]);
+    im.st = reinterpret_cast<DevState*>(a + o[22]);
+    char* t = a + o[23];
+    im.d_ht_tiles = reinterpret_cast<int4*>(t);
+    t += sizeof(int4) * im.ht_tiles.size();
+    im.d_gram_items = reinterpret_cast<int4*>(t);
+    t += sizeof(int4) * im.gram_items.size();
+    im.d_bfac_items = reinterpret_cast<int4*>(t);
+    t += sizeof(int4) * im.bfac_items.size();
+    im.d_z_tiles = reinterpret_cast<int2*>(t);
+    t += sizeof(int2) * im.z_tiles.size();
+    im.d_h_tiles = reinterpret_cast<int2*>(t);
+    im.d_idx = a + o[24];
+    im.idx_bytes = pk.bytes.size();
+    // work lists (one upload)
+    std::vector<char> tb(sizeof(int4) * (im.ht_tiles.size() + im.gram_items.size() +
+                                         im.bfac_items.size()) +
+                         sizeof(int2) * (im.z_tiles.size() + im.h_tiles.size()));
+    char* q = tb.data();
+    auto put = [&](const void* src, size_t bytes) {
+        if (bytes) std::memcpy(q, src, bytes);
+        q += bytes;
+    };
+    put(im.ht_tiles.data(), sizeof(int4) * im.ht_tiles.size());
+    put(im.gram_items.data(), sizeof(int4) * im.gram_items.size());
+    put(im.bfac_items.data(), sizeof(int4) * im.bfac_items.size());
+    put(im.z_tiles.data(), sizeof(int2) * im.z_tiles.size());
+    put(im.h_tiles.data(), sizeof(int2) * im.h_tiles.size());
+    HIPCHK(hipMemcpyAsync(a + o[23], tb.data(), tb.size(), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return 0;
+}
+
+template <typename T, int RP>
+static int run_rp(rtcur_s* h, Impl& im, const void* X, int xdt, const Shape& sh,
+                  double zeta0, double gamma, double tol, int max_iter, uint64_t seed) {
+    Runner<T, RP> R{h, im, h->stream};
+    return R.run(X, xdt, sh, zeta0, gamma, tol, max_iter, seed);
+}
+
+template <typename T>
+static int run_t(rtcur_s* h, Impl& im, const void* X, int xdt, const Shape& sh,
+                 double zeta0, double gamma, double tol, int max_iter, uint64_t seed) {
+    int rc = prepare<T>(h, im, sh, max_iter);
+    if (rc) return rc;
+    switch (im.P.rp) {
+        case 4: return run_rp<T, 4>(h, im, X, xdt, sh, zeta0, gamma, tol, max_iter, seed);
+        case 8: return run_rp<T, 8>(h, im, X, xdt, sh, zeta0, gamma, tol, max_iter, seed);
+        default: return run_rp<T, 16>(h, im, X, xdt, sh, zeta0, gamma, tol, max_iter, seed);
+    }
+}
+
+int solve(rtcur_s* h, const void* X, int x_dtype, const Shape& sh, double zeta0,
+          double gamma, double tol, int max_iter, uint64_t seed) {
+    Impl& im = *impl_of(h);
+    h->have_result = false;
+    HIPCHK(hipSetDevice(h->device));
+    if (!im.st_host) {
+        HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&im.st_host), sizeof(DevState),
+                             hipHostMallocDefault));
+        hipDeviceProp_t prop;
+        HIPCHK(hipGetDeviceProperties(&prop, h->device));
+        // k_eig keeps the Gram in dynamic LDS when it fits beside its
+        // static arrays (about 10 KB)
+        im.max_dyn_lds = (int)prop.sharedMemPerBlock - 16 * 1024;
+        if (im.max_dyn_lds > 65536 - 16 * 1024) {
+            if (hipFuncSetAttribute(reinterpret_cast<const void*>(k_eig),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    im.max_dyn_lds) != hipSuccess) {
+                (void)hipGetLastError();  // clear the sticky error
+                im.max_dyn_lds = 65536 - 16 * 1024;
+            }
+        }
+    }
+    h->shape = sh;
+    if (h->dtype == RTCUR_F64)
+        return run_t<double>(h, im, X, x_dtype, sh, zeta0, gamma, tol, max_iter, seed);
+    return run_t<float>(h, im, X, x_dtype, sh, zeta0, gamma, tol, max_iter, seed);
+}
+
+// ------------------------------------------------------------ outputs
+
+static int ensure_scratch(rtcur_s* h, Impl& im, size_t bytes) {
+    if (bytes <= im.scratch_bytes) return 0;
+    if (im.scratch) HIPCHK(hipFree(im.scratch));
+    im.scratch = nullptr;
+    im.scratch_bytes = 0;
+    if (hipMalloc(&im.scratch, bytes) != hipSuccess) {
+        h->last_error = "scratch allocation failed";
+        return RTCUR_E_NOMEM;
+    }
+    im.scratch_bytes = bytes;
+    return 0;
+}
+
+template <typename T, typename TO, int RP>
+static int recon_t(rtcur_s* h, Impl& im, void* out) {
+    const Prob& P = im.P;
+    int64_t ncols = 1;
+    for (int j = 1; j < P.n; ++j) ncols *= P.d[j];
+    const int64_t total = ncols * P.d[0];
+    if (im.final_iter == 0) {
+        HIPCHK(hipMemsetAsync(out, 0, total * sizeof(TO), h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        return 0;
+    }
+    const int64_t ntile = (ncols + kThreads - 1) / kThreads;
+    size_t need = sizeof(T) * RP * ncols + sizeof(int2) * ntile + 256;
+    int rc = ensure_scratch(h, im, need);
+    if (rc) return rc;
+    T* Hf = static_cast<T*>(im.scratch);
+    int2* tiles = reinterpret_cast<int2*>(static_cast<char*>(im.scratch) +
+                                          align_up(sizeof(T) * RP * ncols, 256));
+    std::vector<int2> tl(ntile);
+    for (int64_t q = 0; q < ntile; ++q) tl[q] = make_int2(-1, (int)q);
+    HIPCHK(hipMemcpyAsync(tiles, tl.data(), sizeof(int2) * ntile, hipMemcpyHostToDevice,
+                          h->stream));
+    hipLaunchKernelGGL((k_hexp<T, RP>), dim3((unsigned)ntile), dim3(kThreads), 0, h->stream,
+                       P, tiles, (const T*)im.Bf, im.Gd, Hf, (DevState*)nullptr, 0, ncols);
+    HIPCHK(hipGetLastError());
+    dim3 grid((unsigned)ntile, (unsigned)((P.d[0] + kTileRows - 1) / kTileRows));
+    hipLaunchKernelGGL((k_recon<T, TO, RP>), grid, dim3(kThreads), 0, h->stream, P.d[0],
+                       ncols, (const T*)im.Bf + P.boff[0], (const T*)Hf, (TO*)out);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return 0;
+}
+
+template <typename T>
+static int recon_rp(rtcur_s* h, Impl& im, void* out, int odt) {
+    switch (im.P.rp) {
+        case 4: return odt == RTCUR_F64 ? recon_t<T, double, 4>(h, im, out) : recon_t<T, float, 4>(h, im, out);
+        case 8: return odt == RTCUR_F64 ? recon_t<T, double, 8>(h, im, out) : recon_t<T, float, 8>(h, im, out);
+        default: return odt == RTCUR_F64 ? recon_t<T, double, 16>(h, im, out) : recon_t<T, float, 16>(h, im, out);
+    }
+}
+
+int reconstruct(rtcur_s* h, void* out, int out_dtype) {
+    Impl* im = static_cast<Impl*>(h->impl);
+    if (!h->have_result || !im) {
+        h->last_error = "no successful solve to reconstruct";
+        return RTCUR_E_STATE;
+    }
+    HIPCHK(hipSetDevice(h->device));
+    if (h->dtype == RTCUR_F64) return recon_rp<double>(h, *im, out, out_dtype);
+    return recon_rp<float>(h, *im, out, out_dtype);
+}
+
+template <typename T, int RP>
+static int block_t(rtcur_s* h, Impl& im, int b, int what, double* dst, int64_t len) {
+    const Prob& P = im.P;
+    const BlockDev& bd = P.blk[b];
+    int rc = ensure_scratch(h, im, sizeof(double) * len + 256);
+    if (rc) return rc;
+    double* tmp = static_cast<double*>(im.scratch);
+    const unsigned nwg = (unsigned)((len + kThreads - 1) / kThreads);
+    const int K = im.final_iter;
+    if (what == RTCUR_BLOCK_X || (what == RTCUR_BLOCK_C && K == 0)) {
+        hipLaunchKernelGGL((k_to_double<T>), dim3(nwg), dim3(kThreads), 0, h->stream,
+                           (const T*)im.XO + bd.off, len, tmp);
+    } else if (what == RTCUR_BLOCK_C) {
+        hipLaunchKernelGGL((k_to_double<T>), dim3(nwg), dim3(kThreads), 0, h->stream,
+                           (const T*)im.C[im.cur] + bd.off, len, tmp);
+    } else if (K == 0) {
+        HIPCHK(hipMemsetAsync(tmp, 0, sizeof(double) * len, h->stream));
+    } else if (what == RTCUR_BLOCK_L) {
+        hipLaunchKernelGGL((k_evalblock<T, RP>), dim3(nwg), dim3(kThreads), 0, h->stream, P, b,
+                           (const T*)im.Bf, (const T*)im.H, tmp);
+    } else {
+        hipLaunchKernelGGL(k_unpack_mask, dim3(nwg), dim3(kThreads), 0, h->stream,
+                           im.mask[im.cur], bd.moff, bd.words, bd.nrows, bd.ncols, tmp);
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(dst, tmp, sizeof(double) * len, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return 0;
+}
+
+int get_block(rtcur_s* h, int block, int what, double* out, int64_t cap, int64_t* len) {
+    Impl* im = static_cast<Impl*>(h->impl);
+    if (!h->have_result || !im) {
+        h->last_error = "no successful solve";
+        return RTCUR_E_STATE;
+    }
+    if (block < 0 || block > im->P.n || what < 0 || what > 3) {
+        h->last_error = "block or what out of range";
+        return RTCUR_E_INVAL;
+    }
+    const BlockDev& bd = im->P.blk[block];
+    const int64_t n = (int64_t)bd.nrows * bd.ncols;
+    if (len) *len = n;
+    if (!out) return 0;
+    if (cap < n) {
+        h->last_error = "output buffer too small";
+        return RTCUR_E_INVAL;
+    }
+    HIPCHK(hipSetDevice(h->device));
+    const int rp = im->P.rp;
+    if (h->dtype == RTCUR_F64) {
+        if (rp == 4) return block_t<double, 4>(h, *im, block, what, out, n);
+        if (rp == 8) return block_t<double, 8>(h, *im, block, what, out, n);
+        return block_t<double, 16>(h, *im, block, what, out, n);
+    }
+    if (rp == 4) return block_t<float, 4>(h, *im, block, what, out, n);
+    if (rp == 8) return block_t<float, 8>(h, *im, block, what, out, n);
+    return block_t<float, 16>(h, *im, block, what, out, n);
+}
+
+int get_tucker(rtcur_s* h, double* core, double* const* B) {
+    Impl* im = static_cast<Impl*>(h->impl);
+    if (!h->have_result || !im) {
+        h->last_error = "no successful solve";
+        return RTCUR_E_STATE;
+    }
+    HIPCHK(hipSetDevice(h->device));
+    const Prob& P = im->P;
+    if (core)
+        HIPCHK(hipMemcpy(core, im->Gd, sizeof(double) * P.core, hipMemcpyDeviceToHost));
+    if (B) {
+        std::vector<double> tmp((size_t)im->bf_elems);
+        HIPCHK(hipMemcpy(tmp.data(), im->Bd, sizeof(double) * im->bf_elems,
+                         hipMemcpyDeviceToHost));
+        for (int i = 0; i < P.n; ++i) {
+            if (!B[i]) continue;
+            for (int x = 0; x < P.d[i]; ++x)
+                for (int p = 0; p < P.r[i]; ++p)
+                    B[i][(size_t)x * P.r[i] + p] =
+                        im->final_iter == 0 ? 0.0 : tmp[P.boff[i] + (size_t)x * P.rp + p];
+        }
+    }
+    return 0;
+}
+
+}  // namespace rtcur

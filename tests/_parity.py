@@ -1,0 +1,78 @@
+"""Helpers that run the oracle and the HIP library on the same seeded input
+and compare them (GPU tests only)."""
+import sys
+
+import numpy as np
+
+import paper_2108_10448_amd as rt
+from oracle import rtcur as oracle_rtcur
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def run_gpu(X, ranks, I, J=None, zeta0=None, gamma=0.7, tol=1e-5, max_iter=100,
+            seed=0, variant="F", dtype=None, check=True):
+    import torch
+    dtype = dtype or torch.float64
+    h = rt.create(0, variant=variant, dtype=dtype)
+    Xd = torch.from_numpy(np.ascontiguousarray(X)).to("cuda:0")
+    info = rt.solve(h, Xd, ranks, I, J, zeta0=zeta0, gamma=gamma, tol=tol,
+                    max_iter=max_iter, seed=seed, check=check)
+    torch.cuda.synchronize()
+    if info.status < 0:
+        print(f"[gpu] status {info.status}: {h.last_error()}", flush=True)
+    return h, info, Xd
+
+
+def compare(res, h, info, *, fp64=True, label=""):
+    """Compare a GPU solve with the oracle result; returns a dict of figures
+    and asserts the parity bar (bit-exact indices and history of zeta,
+    support exact (FP64) or >= 99.99 % (FP32), L to 1e-10 / 1e-4)."""
+    import torch
+    print(f"[parity] {label} iters gpu={info.iters} oracle={res.iters} "
+          f"err gpu={info.err:.6e} oracle={res.err:.6e}", flush=True)
+    n = len(res.dims)
+    out = {}
+    for i in range(n):
+        assert np.array_equal(rt.get_indices(h, i, 0), res.sample.I[i]), f"I_{i}"
+        assert np.array_equal(rt.get_indices(h, i, 1), res.sample.J_cols[i]), f"J_{i}"
+    e, z = rt.get_history(h)
+    assert len(e) == info.iters
+    k = min(info.iters, res.iters)
+    etol = 1e-9 if fp64 else 2e-3
+    for j in range(k):
+        assert abs(e[j] - res.err_hist[j]) <= etol * res.err_hist[j] + 1e-15, (j, e[j], res.err_hist[j])
+        assert z[j] == res.zeta_hist[j], (j, z[j], res.zeta_hist[j])
+    supp_agree = []
+    for b in range(n + 1):
+        Xb = rt.get_block(h, b, rt.BLOCK_X).reshape(res.XB[b].shape)
+        if fp64:
+            assert np.array_equal(Xb, res.XB[b]), f"X block {b}"
+        else:
+            assert rel(Xb, res.XB[b]) < 1e-7, f"X block {b}"
+        if info.iters == res.iters:
+            sup = rt.get_block(h, b, rt.BLOCK_SUPPORT).reshape(res.XB[b].shape) != 0
+            agree = float(np.mean(sup == res.support[b]))
+            supp_agree.append(agree)
+            Lb = rt.get_block(h, b, rt.BLOCK_L).reshape(res.XB[b].shape)
+            Cb = rt.get_block(h, b, rt.BLOCK_C).reshape(res.XB[b].shape)
+            out[f"L{b}"] = rel(Lb, res.LB[b])
+            out[f"C{b}"] = rel(Cb, res.CB[b])
+    if info.iters == res.iters:
+        Lfull = rt.reconstruct(h, dtype=torch.float64).cpu().numpy()
+        out["Lfull"] = rel(Lfull, res.reconstruct())
+        out["support_min"] = min(supp_agree)
+    print(f"[parity] {label} {out}", flush=True)
+    if info.iters == res.iters:
+        ltol = 1e-10 if fp64 else 1e-4
+        for key, v in out.items():
+            if key.startswith("L") or key.startswith("C"):
+                assert v <= ltol, (key, v)
+        if fp64:
+            assert out["support_min"] == 1.0
+        else:
+            assert out["support_min"] >= 0.9999
+    return out

@@ -1,0 +1,175 @@
+"""GPU parity: the HIP library through its C ABI against the FP64 oracle on
+the same seeded inputs.  Bars: indices bit-exact; zeta history exact; e^(k)
+to 1e-9 relative; support exact and L (sampled blocks and full grid) to
+1e-10 in FP64; support >= 99.99 % and L to 1e-4 in FP32."""
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import OracleError
+from oracle import rtcur as oracle_rtcur
+
+from _parity import compare, rel, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    import paper_2108_10448_amd as rt
+    assert os.path.exists(rt.LIB_PATH), "librtcur.so is not built"
+    assert torch.cuda.is_available(), "no HIP device"
+    rt.lib()
+
+
+@pytest.fixture(scope="module")
+def cube100():
+    inst = synth.config_instance("cube100_r3")
+    I, _ = synth.sample_sizes(inst.dims, inst.ranks, 3.0)
+    return inst, I
+
+
+@pytest.mark.parametrize("K", [1, 2, 5])
+def test_fixed_iterations_fp64_cube100(cube100, K):
+    inst, I = cube100
+    res = oracle_rtcur(inst.X, inst.ranks, I, None, None, 0.7, 0.0, K, 0, "F")
+    h, info, _ = run_gpu(inst.X, inst.ranks, I, tol=0.0, max_iter=K, check=False)
+    assert info.iters == K
+    compare(res, h, info, label=f"cube100 F K={K}")
+
+
+@pytest.mark.parametrize("variant", ["F", "R"])
+def test_to_tolerance_fp64_cube100(cube100, variant):
+    inst, I = cube100
+    res = oracle_rtcur(inst.X, inst.ranks, I, None, None, 0.7, 1e-5, 100, 0, variant)
+    h, info, _ = run_gpu(inst.X, inst.ranks, I, variant=variant)
+    assert info.iters == res.iters and info.converged
+    compare(res, h, info, label=f"cube100 {variant} tol")
+
+
+def test_fp32_compute_cube100(cube100):
+    inst, I = cube100
+    res = oracle_rtcur(inst.X, inst.ranks, I, None, None, 0.7, 1e-5, 100, 0, "F")
+    h, info, _ = run_gpu(inst.X.astype(np.float32), inst.ranks, I, dtype=torch.float32)
+    assert abs(info.iters - res.iters) <= 1 and info.converged
+    res2 = oracle_rtcur(inst.X.astype(np.float32), inst.ranks, I, None, None, 0.7, 0.0,
+                        info.iters, 0, "F")
+    compare(res2, h, info, fp64=False, label="cube100 F fp32")
+
+
+def test_fiber_sampling_fp64():
+    inst = synth.tucker_plus_sparse((60, 50, 40), (3, 2, 3), alpha=0.15, seed=3)
+    I, J = synth.sample_sizes(inst.dims, inst.ranks, 3.0, fiber=True)
+    res = oracle_rtcur(inst.X, inst.ranks, I, J, None, 0.7, 0.0, 6, 9, "F")
+    h, info, _ = run_gpu(inst.X, inst.ranks, I, J, tol=0.0, max_iter=6, seed=9, check=False)
+    compare(res, h, info, label="fiber 60x50x40")
+
+
+def test_four_modes_ragged_fp64():
+    inst = synth.tucker_plus_sparse((23, 19, 3, 17), (3, 2, 2, 2), alpha=0.1, seed=5)
+    I = (9, 8, 3, 7)
+    res = oracle_rtcur(inst.X, inst.ranks, I, None, None, 0.7, 0.0, 8, 2, "F")
+    h, info, _ = run_gpu(inst.X, inst.ranks, I, tol=0.0, max_iter=8, seed=2, check=False)
+    compare(res, h, info, label="4-mode ragged")
+
+
+def test_two_modes_fp64():
+    inst = synth.tucker_plus_sparse((300, 257), (4, 4), alpha=0.1, seed=8)
+    I = (40, 37)
+    res = oracle_rtcur(inst.X, inst.ranks, I, None, None, 0.7, 1e-8, 60, 4, "F")
+    h, info, _ = run_gpu(inst.X, inst.ranks, I, tol=1e-8, max_iter=60, seed=4, check=False)
+    assert info.iters == res.iters
+    compare(res, h, info, label="2-mode")
+
+
+def test_full_sampling_and_given_zeta0():
+    inst = synth.tucker_plus_sparse((20, 18, 16), (2, 2, 2), alpha=0.1, seed=6)
+    res = oracle_rtcur(inst.X, inst.ranks, inst.dims, None, 3.0, 0.8, 0.0, 7, 1, "F")
+    h, info, _ = run_gpu(inst.X, inst.ranks, inst.dims, zeta0=3.0, gamma=0.8, tol=0.0,
+                         max_iter=7, seed=1, check=False)
+    assert info.zeta0 == 3.0
+    compare(res, h, info, label="full sampling")
+
+
+def test_not_converged_status():
+    import paper_2108_10448_amd as rt
+    inst = synth.tucker_plus_sparse((30, 30, 30), (2, 2, 2), alpha=0.5, seed=1)
+    res = oracle_rtcur(inst.X, inst.ranks, (15, 15, 15), None, None, 0.7, 1e-12, 4, 0, "F")
+    h, info, _ = run_gpu(inst.X, inst.ranks, (15, 15, 15), tol=1e-12, max_iter=4, check=False)
+    assert info.status == rt.NOT_CONVERGED and info.iters == 4
+    compare(res, h, info, label="not converged")
+
+
+def test_zero_tensor_and_tol_one():
+    import paper_2108_10448_amd as rt
+    X = np.zeros((12, 10, 8))
+    h, info, _ = run_gpu(X, (1, 1, 1), (4, 4, 4), check=False)
+    assert info.status == rt.OK and info.iters == 0
+    L = rt.reconstruct(h).cpu().numpy()
+    assert not np.any(L)
+    inst = synth.tucker_plus_sparse((12, 10, 8), (2, 2, 2), alpha=0.1, seed=1)
+    h, info, _ = run_gpu(inst.X, inst.ranks, (6, 6, 6), tol=1.0, check=False)
+    assert info.status == rt.OK and info.iters == 0
+
+
+def test_rank_deficient_and_nonfinite():
+    import paper_2108_10448_amd as rt
+    inst = synth.tucker_plus_sparse((16, 16, 16), (1, 1, 1), alpha=0.0, seed=1)
+    with pytest.raises(OracleError):
+        oracle_rtcur(inst.X, (2, 2, 2), (8, 8, 8), None, None, 0.7, 1e-5, 5, 0, "F")
+    h, info, _ = run_gpu(inst.X, (2, 2, 2), (8, 8, 8), max_iter=5, check=False)
+    assert info.status == rt.E_RANK
+    X = np.ones((8, 8, 8))
+    X[1, 2, 3] = np.nan
+    h, info, _ = run_gpu(X, (1, 1, 1), (8, 8, 8), check=False)
+    assert info.status == rt.E_NONFINITE
+    # the handle stays usable after an error
+    inst = synth.tucker_plus_sparse((16, 16, 16), (2, 2, 2), alpha=0.1, seed=2)
+    info = rt.solve(h, torch.from_numpy(inst.X).cuda(), (2, 2, 2), (8, 8, 8), check=False)
+    assert info.status in (rt.OK, rt.NOT_CONVERGED)
+
+
+def test_bitwise_deterministic(cube100):
+    import paper_2108_10448_amd as rt
+    inst, I = cube100
+    h1, i1, _ = run_gpu(inst.X, inst.ranks, I)
+    h2, i2, _ = run_gpu(inst.X, inst.ranks, I)
+    assert i1.iters == i2.iters
+    assert np.array_equal(rt.get_history(h1)[0], rt.get_history(h2)[0])
+    for b in range(4):
+        assert np.array_equal(rt.get_block(h1, b, rt.BLOCK_C), rt.get_block(h2, b, rt.BLOCK_C))
+
+
+@pytest.fixture(scope="module")
+def cube300():
+    inst = synth.config_instance("cube300_r5")
+    I, _ = synth.sample_sizes(inst.dims, inst.ranks, 3.0)
+    return inst, I
+
+
+@pytest.mark.parametrize("variant", ["F", "R"])
+def test_cube300_fp64_compute(cube300, variant):
+    # headline workload: 300^3 float32 storage, rank 5, alpha 0.3, FP64 compute
+    inst, I = cube300
+    res = oracle_rtcur(inst.X, inst.ranks, I, None, None, 0.7, 1e-5, 100, 0, variant)
+    h, info, _ = run_gpu(inst.X, inst.ranks, I, variant=variant)
+    assert info.iters == res.iters and info.converged
+    compare(res, h, info, label=f"cube300 {variant} fp64")
+
+
+def test_cube300_fp32_compute(cube300):
+    inst, I = cube300
+    h, info, _ = run_gpu(inst.X, inst.ranks, I, dtype=torch.float32)
+    assert info.converged
+    res = oracle_rtcur(inst.X, inst.ranks, I, None, None, 0.7, 0.0, info.iters, 0, "F")
+    assert abs(info.iters - oracle_rtcur(inst.X, inst.ranks, I, None, None, 0.7, 1e-5,
+                                         100, 0, "F").iters) <= 1
+    out = compare(res, h, info, fp64=False, label="cube300 F fp32")
+    L = torch.empty(inst.dims, dtype=torch.float32, device="cuda:0")
+    import paper_2108_10448_amd as rt
+    rt.reconstruct(h, out=L)
+    assert rel(L.cpu().numpy().astype(np.float64), res.reconstruct()) < 1e-4
