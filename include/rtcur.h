@@ -29,7 +29,8 @@
  *   - A handle is not thread-safe.  All device work runs on the stream given
  *     to rtcur_create, in stream order; rtcur_solve returns after its device
  *     work has finished.
- *   - Limits: 2 <= n <= 4; 1 <= r_i <= 16; prod(r_i) <= 4096; s_i <= 256.
+ *   - Limits: 2 <= n <= 4; 1 <= r_i <= 16 (r_i <= 8 when n = 4);
+ *     prod(r_i) <= 4096; s_i <= 256.
  */
 #ifndef RTCUR_H
 #define RTCUR_H
@@ -140,6 +141,20 @@ int rtcur_get_tucker(rtcur_t h, double* core, double* const* B);
 int rtcur_sample(uint64_t seed, int64_t t, int32_t n, const int64_t* dims,
                  const int64_t* I_sizes, const int64_t* J_sizes, int32_t mode,
                  int32_t which, int64_t* out, int64_t cap, int64_t* len);
+
+/* Kernel timing for diagnostics and roofline figures.  With enable = 1 the
+ * following solves record a pair of HIP events on the handle's stream around
+ * every kernel launch; only launches that did work (not those skipped after
+ * the stop flag was raised) are accumulated.  Timing adds a few microseconds
+ * per launch, so time throughput with profiling off.  enable = 0 stops
+ * recording; the totals persist until the next enable = 1. */
+int rtcur_set_profiling(rtcur_t h, int32_t enable);
+
+/* Totals for kernel kind `kind` (0 .. count-1): its name (NUL-terminated,
+ * truncated to name_cap), summed event time in ms and launch count.
+ * RTCUR_E_INVAL when kind is out of range. */
+int rtcur_get_profile(rtcur_t h, int32_t kind, char* name, int32_t name_cap,
+                      double* total_ms, int64_t* launches);
 
 const char* rtcur_strerror(int status);
 const char* rtcur_last_error(rtcur_t h);

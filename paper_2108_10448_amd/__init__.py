@@ -36,8 +36,8 @@ BLOCK_X, BLOCK_C, BLOCK_L, BLOCK_SUPPORT = 0, 1, 2, 3
 
 SYMBOLS = ["rtcur_create", "rtcur_solve", "rtcur_reconstruct", "rtcur_destroy",
            "rtcur_get_indices", "rtcur_get_history", "rtcur_get_block",
-           "rtcur_get_tucker", "rtcur_sample", "rtcur_strerror",
-           "rtcur_last_error"]
+           "rtcur_get_tucker", "rtcur_sample", "rtcur_set_profiling",
+           "rtcur_get_profile", "rtcur_strerror", "rtcur_last_error"]
 
 
 class RtcurInfo(ctypes.Structure):
@@ -81,6 +81,9 @@ def lib() -> ctypes.CDLL:
     L.rtcur_get_block.argtypes = [vp, i32, i32, pd, i64, p64]
     L.rtcur_get_tucker.argtypes = [vp, pd, ctypes.POINTER(pd)]
     L.rtcur_sample.argtypes = [u64, i64, i32, p64, p64, p64, i32, i32, p64, i64, p64]
+    L.rtcur_set_profiling.argtypes = [vp, i32]
+    L.rtcur_get_profile.argtypes = [vp, i32, ctypes.c_char_p, i32, pd,
+                                    ctypes.POINTER(ctypes.c_int64)]
     L.rtcur_strerror.argtypes = [ctypes.c_int]
     L.rtcur_strerror.restype = ctypes.c_char_p
     L.rtcur_last_error.argtypes = [vp]
@@ -296,3 +299,26 @@ def get_tucker(h: Handle):
     if rc != OK:
         raise RTCURError(rc, h.last_error())
     return core, Bs
+
+
+def set_profiling(h: Handle, enable: bool) -> None:
+    """rtcur_set_profiling: HIP-event timing of every kernel launch."""
+    rc = lib().rtcur_set_profiling(h.ptr, 1 if enable else 0)
+    if rc != OK:
+        raise RTCURError(rc, h.last_error())
+
+
+def get_profile(h: Handle) -> dict:
+    """{kernel name: (total ms, launches)} accumulated while profiling."""
+    L = lib()
+    out = {}
+    kind = 0
+    while True:
+        name = ctypes.create_string_buffer(64)
+        ms = ctypes.c_double(0.0)
+        cnt = ctypes.c_int64(0)
+        if L.rtcur_get_profile(h.ptr, kind, name, 64, ctypes.byref(ms), ctypes.byref(cnt)) != OK:
+            break
+        out[name.value.decode()] = (ms.value, cnt.value)
+        kind += 1
+    return out

@@ -46,6 +46,16 @@ int validate(rtcur_t h, int32_t n, const int64_t* dims, const int32_t* ranks,
         core *= ranks[i];
     }
     if (core > rtcur::kMaxCore) return fail(h, RTCUR_E_INVAL, "prod(r_i) must be <= 4096");
+    if (n == 4) {
+        for (int i = 0; i < n; ++i)
+            if (ranks[i] > 8) return fail(h, RTCUR_E_INVAL, "4-mode tensors need r_i <= 8");
+    }
+    {
+        // one slice of the core, r_{n-1} x prod_{0 < l < n-1} |I_l|, fits in LDS
+        int64_t slice = ranks[n - 1];
+        for (int l = 1; l < n - 1; ++l) slice *= I_sizes[l];
+        if (slice > 2048) return fail(h, RTCUR_E_INVAL, "sampled core slice too large");
+    }
     int64_t total = 1;
     for (int i = 0; i < n; ++i) total *= sh.d[i];
     if (total > ((int64_t)1 << 40)) return fail(h, RTCUR_E_INVAL, "tensor too large");
@@ -215,6 +225,31 @@ int rtcur_sample(uint64_t seed, int64_t t, int32_t n, const int64_t* dims,
         const int64_t k = cap < (int64_t)v.size() ? cap : (int64_t)v.size();
         if (k > 0) std::memcpy(out, v.data(), sizeof(int64_t) * k);
     }
+    return RTCUR_OK;
+}
+
+int rtcur_set_profiling(rtcur_t h, int32_t enable) {
+    if (!h) return RTCUR_E_INVAL;
+    if (enable && !h->profiling) {
+        for (int k = 0; k < rtcur::kProfKinds; ++k) {
+            h->prof_ms[k] = 0.0;
+            h->prof_count[k] = 0;
+        }
+    }
+    h->profiling = enable != 0;
+    return RTCUR_OK;
+}
+
+int rtcur_get_profile(rtcur_t h, int32_t kind, char* name, int32_t name_cap,
+                      double* total_ms, int64_t* launches) {
+    if (!h) return RTCUR_E_INVAL;
+    if (kind < 0 || kind >= rtcur::kProfKinds) return RTCUR_E_INVAL;
+    if (name && name_cap > 0) {
+        std::strncpy(name, rtcur::kProfNames[kind], (size_t)name_cap - 1);
+        name[name_cap - 1] = 0;
+    }
+    if (total_ms) *total_ms = h->prof_ms[kind];
+    if (launches) *launches = h->prof_count[kind];
     return RTCUR_OK;
 }
 

@@ -74,6 +74,11 @@ struct Prob {
     int64_t goff[kMaxModes];  // offset of the Gram of mode i (s_i x s_i)
     int64_t zoff[kMaxModes];  // offset of Z_i (rp x m_i), float64
     int64_t loff[kMaxModes];  // offset of lambda_i (rp)
+    int gitem0[kMaxModes];    // first Gram work item of mode i
+    int gnkc[kMaxModes];      // Gram column chunks per output tile of mode i
+    int gchunk[kMaxModes];    // columns per Gram chunk (multiple of 256)
+    int bitem0[kMaxModes];    // first B-factor work item of mode i
+    int bnkc[kMaxModes];      // B-factor column chunks per row block of mode i
     const int32_t* I[kMaxModes];   // sampled rows of each mode (device)
     BlockDev blk[kMaxBlocks];
 };
@@ -118,6 +123,10 @@ struct rtcur_s {
     // device workspace (owned; grown on demand, freed by destroy)
     std::vector<rtcur::DevBuf> bufs;
     void* impl = nullptr;      // solver-private state (see solver.hip)
+    // kernel timing (rtcur_set_profiling)
+    bool profiling = false;
+    double prof_ms[16] = {};
+    int64_t prof_count[16] = {};
 };
 
 namespace rtcur {
@@ -129,4 +138,6 @@ int get_block(rtcur_s* h, int block, int what, double* out, int64_t cap,
               int64_t* len);
 int get_tucker(rtcur_s* h, double* core, double* const* B);
 void release(rtcur_s* h);
+constexpr int kProfKinds = 10;
+extern const char* const kProfNames[kProfKinds];
 }  // namespace rtcur

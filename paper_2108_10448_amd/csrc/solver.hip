@@ -1,13 +1,17 @@
 // Host orchestration of the RTCUR hot loop on one gfx950 device.
 //
 // Per iteration (RTCUR-F), all on the handle's stream and queued ahead of
-// the host (kernels return at once after the device-side stop flag is set):
-//   k_ht     fused residual, e^(k) numerator, hard threshold, support bits
-//   k_gram   Gram_i = U_i U_i^T on the float64 matrix cores
-//   k_eig    top-r_i eigenpairs -> W_i, lambda_i, Y_i = W_i / lambda_i
-//   k_zmat   Z_i = Y_i^T U_i                  (V_i S_i^-1 = Z_i^T)
-//   k_contract x n   core G = R x_i W_i^T
-//   k_bfac   B_i = C_i Z_i^T
+// the host (every kernel returns at once after the device-side stop flag is
+// raised, so the host only checks the flag every few iterations):
+//   k_ht     fused residual, e^(k) numerator partials, hard threshold,
+//            support bits (Step I, equations 8-11)
+//   k_gram   Gram_i = U_i U_i^T tiles on the float64 matrix cores, plus the
+//            e^(k) decision from k_ht's partials
+//   k_eig    Gram assembly, top-r_i eigenpairs -> W_i, lambda_i, Y_i
+//   k_zcore  Z_i = U_i^T Y_i (so V_i S_i^-1 = Z_i) and, per slice a of R,
+//            T[a] = R(a, ..) x_{l >= 1} W_l^T
+//   k_bfac   B_i = C_i Z_i partials over column chunks
+//   k_bred   B_i from the partials; the core G = sum_a W_0[a]^T T[a]
 //   k_hexp   H_b = G x_{j != mode} B_j on each block's columns
 // so that the next k_ht forms L on the blocks as B_mode H_b (Section 3.3).
 #include <hip/hip_runtime.h>
@@ -23,13 +27,13 @@
 
 namespace rtcur {
 
-#define HIPCHK(expr)                                                       \
-    do {                                                                   \
-        hipError_t e_ = (expr);                                            \
-        if (e_ != hipSuccess) {                                            \
+#define HIPCHK(expr)                                                           \
+    do {                                                                       \
+        hipError_t e_ = (expr);                                                \
+        if (e_ != hipSuccess) {                                                \
             h->last_error = std::string(#expr) + ": " + hipGetErrorString(e_); \
-            return RTCUR_E_HIP;                                            \
-        }                                                                  \
+            return RTCUR_E_HIP;                                                \
+        }                                                                      \
     } while (0)
 
 namespace {
@@ -38,7 +42,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 int pad_rank(int r) { return r <= 4 ? 4 : (r <= 8 ? 8 : 16); }
 
-// A carve-out plan: bytes per named region, laid out in one device arena.
+// Offsets of named regions inside one device arena.
 struct Arena {
     size_t total = 0;
     size_t add(size_t bytes) {
@@ -48,10 +52,24 @@ struct Arena {
     }
 };
 
+constexpr int kAbsmaxWG = 2048;
+
 }  // namespace
+
+enum ProfKind { PK_ABSMAX = 0, PK_GATHER, PK_HT, PK_GRAM, PK_EIG, PK_ZCORE, PK_BFAC,
+                PK_BRED, PK_HEXP, PK_DECIDE };
+const char* const kProfNames[kProfKinds] = {"absmax", "gather", "ht",   "gram", "eig",
+                                            "zcore",  "bfac",   "bred", "hexp", "decide"};
+
+struct ProfRec {
+    int kind, iter, a, b;  // a, b: indices into the event pool
+};
 
 // Solver-private state kept in the handle between calls.
 struct Impl {
+    std::vector<hipEvent_t> events;  // pool for kernel timing
+    std::vector<ProfRec> recs;
+    size_t ev_used = 0;
     void* arena = nullptr;
     size_t arena_bytes = 0;
     void* scratch = nullptr;        // getters / reconstruct temporaries
@@ -61,21 +79,19 @@ struct Impl {
 
     // layout of the current solve
     Prob P{};
-    int esize = 8;                  // element size of the compute dtype
     int64_t nblk_elems = 0;
     int64_t h_elems = 0, mask_words = 0, bf_elems = 0, w_elems = 0, z_elems = 0,
-            g_elems = 0, l_elems = 0, ctmp_elems = 0;
+            g_elems = 0, l_elems = 0, t_elems = 0;
     std::vector<int4> ht_tiles, gram_items, bfac_items;
     std::vector<int2> z_tiles, h_tiles;
-    int n_gram_pairs = 0, n_bfac_groups = 0;
+    int n_bred_wg = 0;
 
     // device regions (inside the arena)
     void *XO = nullptr, *C[2] = {nullptr, nullptr}, *Bf = nullptr, *H = nullptr;
     uint64_t* mask[2] = {nullptr, nullptr};
     double *W = nullptr, *Y = nullptr, *lam = nullptr, *Z = nullptr, *gram = nullptr,
-           *gpart = nullptr, *bpart = nullptr, *Bd = nullptr, *Gd = nullptr,
-           *ctmp[2] = {nullptr, nullptr}, *part = nullptr, *err_hist = nullptr;
-    unsigned *gcnt = nullptr, *bcnt = nullptr;
+           *gpart = nullptr, *bpart = nullptr, *Bd = nullptr, *Gd = nullptr, *Tc = nullptr,
+           *part = nullptr, *hpart = nullptr, *err_hist = nullptr;
     DevState* st = nullptr;
     int4 *d_ht_tiles = nullptr, *d_gram_items = nullptr, *d_bfac_items = nullptr;
     int2 *d_z_tiles = nullptr, *d_h_tiles = nullptr;
@@ -100,6 +116,7 @@ void release(rtcur_s* h) {
     if (im->arena) (void)hipFree(im->arena);
     if (im->scratch) (void)hipFree(im->scratch);
     if (im->st_host) (void)hipHostFree(im->st_host);
+    for (hipEvent_t e : im->events) (void)hipEventDestroy(e);
     delete im;
     h->impl = nullptr;
 }
@@ -175,15 +192,15 @@ static void pack_indices(const Shape& sh, const SampleHost& smp, IdxPack& pk) {
     }
 }
 
-// Build block descriptors, offsets and work lists; size the arena.
-static void plan(Impl& im, const Shape& sh, int esize, Arena& ar,
-                 size_t& o_XO, size_t& o_C0, size_t& o_C1, size_t& o_m0,
-                 size_t& o_m1, size_t& o_Bf, size_t& o_H, size_t& o_W, size_t& o_Y,
-                 size_t& o_lam, size_t& o_Z, size_t& o_gram, size_t& o_gpart,
-                 size_t& o_bpart, size_t& o_Bd, size_t& o_Gd, size_t& o_ct0,
-                 size_t& o_ct1, size_t& o_part, size_t& o_hist, size_t& o_gcnt,
-                 size_t& o_bcnt, size_t& o_st, size_t& o_tiles, size_t& o_idx,
-                 size_t idx_bytes, int max_iter) {
+// Region offsets of one solve's arena.
+struct Regions {
+    size_t XO, C0, C1, m0, m1, Bf, H, W, Y, lam, Z, gram, gpart, bpart, Bd, Gd, Tc, part,
+        hpart, hist, st, tiles, idx;
+};
+
+// Block descriptors, offsets and work lists for this shape; sizes the arena.
+static void plan(Impl& im, const Shape& sh, int esize, size_t idx_bytes, int max_iter,
+                 Arena& ar, Regions& rg) {
     const int n = sh.n;
     Prob& P = im.P;
     std::memset(&P, 0, sizeof(P));
@@ -248,77 +265,70 @@ static void plan(Impl& im, const Shape& sh, int esize, Arena& ar,
         P.loff[i] = im.l_elems;
         im.l_elems += RP;
     }
-    // Gram work: upper-triangular 16x16 tile pairs x 1024-column chunks
+    // Gram work: upper-triangular 16x16 tile pairs x column chunks
     im.gram_items.clear();
-    int pid = 0;
     for (int i = 0; i < n; ++i) {
         const int nt = (int)((sh.s[i] + 15) / 16);
-        const int nkc = (int)((sh.m[i] + kGramKCW - 1) / kGramKCW);
+        int nkc = (int)std::min<int64_t>(kGramMaxKC, (sh.m[i] + kGramMinChunk - 1) / kGramMinChunk);
+        nkc = std::max(nkc, 1);
+        int chunk = (int)align_up((size_t)((sh.m[i] + nkc - 1) / nkc), 256);
+        P.gitem0[i] = (int)im.gram_items.size();
+        P.gnkc[i] = nkc;
+        P.gchunk[i] = chunk;
         for (int ta = 0; ta < nt; ++ta)
-            for (int tb = ta; tb < nt; ++tb, ++pid)
+            for (int tb = ta; tb < nt; ++tb)
                 for (int kc = 0; kc < nkc; ++kc)
-                    im.gram_items.push_back(make_int4(i, ta | (tb << 16), kc | (nkc << 16), pid));
+                    im.gram_items.push_back(make_int4(i, ta | (tb << 16), kc, 0));
     }
-    im.n_gram_pairs = pid;
-    // B_i work: 16-row blocks x 1024-column chunks
-    im.bfac_items.clear();
-    int gid = 0;
-    for (int i = 0; i < n; ++i) {
-        const int nrb = (int)((sh.d[i] + kBfacRows - 1) / kBfacRows);
-        const int nkc = (int)((sh.m[i] + kBfacKC - 1) / kBfacKC);
-        for (int rb = 0; rb < nrb; ++rb, ++gid)
-            for (int kc = 0; kc < nkc; ++kc)
-                im.bfac_items.push_back(make_int4(i, rb, kc | (nkc << 16), gid));
-    }
-    im.n_bfac_groups = gid;
+    // Z_i: 64 columns per work item; B_i: 16 rows x column chunks
     im.z_tiles.clear();
-    for (int i = 0; i < n; ++i)
-        for (int64_t c0 = 0; c0 < sh.m[i]; c0 += kThreads)
-            im.z_tiles.push_back(make_int2(i, (int)c0));
+    im.bfac_items.clear();
+    const int bkc = RP <= 8 ? kBfacKC : kBfacKC / 2;
+    for (int i = 0; i < n; ++i) {
+        for (int64_t c0 = 0; c0 < sh.m[i]; c0 += 64) im.z_tiles.push_back(make_int2(i, (int)c0));
+        const int nkc = (int)((sh.m[i] + bkc - 1) / bkc);
+        P.bitem0[i] = (int)im.bfac_items.size();
+        P.bnkc[i] = nkc;
+        for (int rb = 0; rb * kBfacRows < sh.d[i]; ++rb)
+            for (int kc = 0; kc < nkc; ++kc) im.bfac_items.push_back(make_int4(i, rb, kc, 0));
+    }
+    int64_t bent = 0;
+    for (int i = 0; i < n; ++i) bent += sh.d[i] * RP;
+    im.n_bred_wg = (int)((bent + kThreads - 1) / kThreads);
     im.h_tiles.clear();
     for (int b = 0; b <= n; ++b)
         for (int cb = 0; cb * kThreads < P.blk[b].ncols; ++cb)
             im.h_tiles.push_back(make_int2(b, cb));
-    // core-stage temporaries: the largest intermediate of G = R x_i W_i^T
-    int64_t big = 0, lead = 1;
-    for (int j = 0; j < n; ++j) {
-        const int q = n - 1 - j;
-        lead *= sh.r[q];
-        int64_t rest = 1;
-        for (int l = 0; l < q; ++l) rest *= sh.s[l];
-        big = std::max(big, lead * rest);
-    }
-    im.ctmp_elems = big;
+    // core slices T[a] = R(a, ..) x_{l >= 1} W_l^T: s_0 x prod_{l >= 1} r_l
+    im.t_elems = sh.s[0] * (P.core / sh.r[0]);
 
     const size_t nb = (size_t)im.nblk_elems;
-    o_XO = ar.add(nb * esize);
-    o_C0 = ar.add(nb * esize);
-    o_C1 = ar.add(nb * esize);
-    o_m0 = ar.add(sizeof(uint64_t) * im.mask_words);
-    o_m1 = ar.add(sizeof(uint64_t) * im.mask_words);
-    o_Bf = ar.add(im.bf_elems * esize);
-    o_H = ar.add(im.h_elems * esize);
-    o_W = ar.add(sizeof(double) * im.w_elems);
-    o_Y = ar.add(sizeof(double) * im.w_elems);
-    o_lam = ar.add(sizeof(double) * im.l_elems);
-    o_Z = ar.add(sizeof(double) * im.z_elems);
-    o_gram = ar.add(sizeof(double) * im.g_elems);
-    o_gpart = ar.add(sizeof(double) * 256 * im.gram_items.size());
-    o_bpart = ar.add(sizeof(double) * kBfacRows * RP * im.bfac_items.size());
-    o_Bd = ar.add(sizeof(double) * im.bf_elems);
-    o_Gd = ar.add(sizeof(double) * P.core);
-    o_ct0 = ar.add(sizeof(double) * im.ctmp_elems);
-    o_ct1 = ar.add(sizeof(double) * im.ctmp_elems);
-    o_part = ar.add(sizeof(double) * 2 * std::max<size_t>(im.ht_tiles.size(), 2048));
+    rg.XO = ar.add(nb * esize);
+    rg.C0 = ar.add(nb * esize);
+    rg.C1 = ar.add(nb * esize);
+    rg.m0 = ar.add(sizeof(uint64_t) * im.mask_words);
+    rg.m1 = ar.add(sizeof(uint64_t) * im.mask_words);
+    rg.Bf = ar.add(im.bf_elems * esize);
+    rg.H = ar.add(im.h_elems * esize);
+    rg.W = ar.add(sizeof(double) * im.w_elems);
+    rg.Y = ar.add(sizeof(double) * im.w_elems);
+    rg.lam = ar.add(sizeof(double) * im.l_elems);
+    rg.Z = ar.add(sizeof(double) * im.z_elems);
+    rg.gram = ar.add(sizeof(double) * im.g_elems);
+    rg.gpart = ar.add(sizeof(double) * 256 * im.gram_items.size());
+    rg.bpart = ar.add(sizeof(double) * kBfacRows * RP * im.bfac_items.size());
+    rg.Bd = ar.add(sizeof(double) * im.bf_elems);
+    rg.Gd = ar.add(sizeof(double) * P.core);
+    rg.Tc = ar.add(sizeof(double) * im.t_elems);
+    rg.part = ar.add(sizeof(double) * 2 * std::max<size_t>(im.ht_tiles.size(), kAbsmaxWG));
+    rg.hpart = ar.add(sizeof(double) * im.ht_tiles.size());
     im.hist_len = (size_t)max_iter + 2;
-    o_hist = ar.add(sizeof(double) * im.hist_len);
-    o_gcnt = ar.add(sizeof(unsigned) * std::max(im.n_gram_pairs, 1));
-    o_bcnt = ar.add(sizeof(unsigned) * std::max(im.n_bfac_groups, 1));
-    o_st = ar.add(sizeof(DevState));
-    o_tiles = ar.add(sizeof(int4) * (im.ht_tiles.size() + im.gram_items.size() +
-                                     im.bfac_items.size()) +
-                     sizeof(int2) * (im.z_tiles.size() + im.h_tiles.size()) + 1024);
-    o_idx = ar.add(idx_bytes);
+    rg.hist = ar.add(sizeof(double) * im.hist_len);
+    rg.st = ar.add(sizeof(DevState));
+    rg.tiles = ar.add(sizeof(int4) * (im.ht_tiles.size() + im.gram_items.size() +
+                                      im.bfac_items.size()) +
+                      sizeof(int2) * (im.z_tiles.size() + im.h_tiles.size()));
+    rg.idx = ar.add(idx_bytes);
 }
 
 // ------------------------------------------------------------ the solver
@@ -328,47 +338,125 @@ struct Runner {
     rtcur_s* h;
     Impl& im;
     hipStream_t s;
+    int tag = 0;    // iteration the next launches belong to (0: set-up)
+    int open = -1;  // pending profile record
 
-    int gather(const void* X, int xdt, int flags) {
-        const int nt = (int)im.ht_tiles.size();
-        if (xdt == RTCUR_F64)
-            hipLaunchKernelGGL((k_gather<double, T>), dim3(nt), dim3(kThreads), 0, s,
-                               (const double*)X, im.P, im.d_ht_tiles, (T*)im.XO,
-                               im.part, flags, im.st);
-        else
-            hipLaunchKernelGGL((k_gather<float, T>), dim3(nt), dim3(kThreads), 0, s,
-                               (const float*)X, im.P, im.d_ht_tiles, (T*)im.XO,
-                               im.part, flags, im.st);
-        HIPCHK(hipGetLastError());
+    // Event pair around one launch when profiling is on.
+    hipError_t pb(int kind) {
+        if (!h->profiling) return hipSuccess;
+        if (im.ev_used + 2 > im.events.size()) {
+            for (int q = 0; q < 64; ++q) {
+                hipEvent_t e;
+                hipError_t err = hipEventCreate(&e);
+                if (err != hipSuccess) return err;
+                im.events.push_back(e);
+            }
+        }
+        const int a = (int)im.ev_used++, b = (int)im.ev_used++;
+        im.recs.push_back(ProfRec{kind, tag, a, b});
+        open = (int)im.recs.size() - 1;
+        return hipEventRecord(im.events[a], s);
+    }
+    hipError_t pe() {
+        if (!h->profiling || open < 0) return hipSuccess;
+        const int b = im.recs[open].b;
+        open = -1;
+        return hipEventRecord(im.events[b], s);
+    }
+    // Accumulate the launches that did work: iteration tags up to K, and up
+    // to K + 1 for the kernels whose pass at K + 1 decides the stop.
+    int prof_collect(int K) {
+        if (!h->profiling) return 0;
+        HIPCHK(hipStreamSynchronize(s));
+        for (const ProfRec& r : im.recs) {
+            const bool deciding = r.kind == PK_HT || r.kind == PK_GRAM || r.kind == PK_DECIDE;
+            if (r.iter > K + (deciding ? 1 : 0)) continue;
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, im.events[r.a], im.events[r.b]));
+            h->prof_ms[r.kind] += ms;
+            h->prof_count[r.kind] += 1;
+        }
+        im.recs.clear();
+        im.ev_used = 0;
         return 0;
     }
 
-    int ht(int kcur, int flags, const T* Cold, T* Cnew, uint64_t* mask,
-           double gamma, double tol) {
+    int gather(const void* X, int xdt, int flags) {
         const int nt = (int)im.ht_tiles.size();
+        HIPCHK(pb(PK_GATHER));
+        if (xdt == RTCUR_F64)
+            hipLaunchKernelGGL((k_gather<double, T>), dim3(nt), dim3(kThreads), 0, s,
+                               (const double*)X, im.P, im.d_ht_tiles, (T*)im.XO, im.part);
+        else
+            hipLaunchKernelGGL((k_gather<float, T>), dim3(nt), dim3(kThreads), 0, s,
+                               (const float*)X, im.P, im.d_ht_tiles, (T*)im.XO, im.part);
+        HIPCHK(hipGetLastError());
+        hipLaunchKernelGGL(k_den, dim3(1), dim3(kThreads), 0, s, im.P, (const double*)im.part,
+                           flags, im.st);
+        HIPCHK(hipGetLastError());
+        HIPCHK(pe());
+        return 0;
+    }
+
+    int ht(int kcur, int flags, const T* Cold, T* Cnew, uint64_t* mask, double gamma) {
+        const int nt = (int)im.ht_tiles.size();
+        HIPCHK(pb(PK_HT));
         hipLaunchKernelGGL((k_ht<T, RP>), dim3(nt), dim3(kThreads), 0, s, im.P,
                            im.d_ht_tiles, (const T*)im.XO, Cold, Cnew, mask,
-                           (const T*)im.Bf, (const T*)im.H, gamma, kcur, flags, tol,
-                           im.part, im.err_hist, im.st);
+                           (const T*)im.Bf, (const T*)im.H, gamma, kcur, flags, im.hpart,
+                           im.st);
         HIPCHK(hipGetLastError());
+        HIPCHK(pe());
+        return 0;
+    }
+
+    int decide(int kcur, double tol) {
+        HIPCHK(pb(PK_DECIDE));
+        hipLaunchKernelGGL(k_decide, dim3(1), dim3(kThreads), 0, s, im.P,
+                           (const double*)im.hpart, kcur, tol, im.err_hist, im.st);
+        HIPCHK(hipGetLastError());
+        HIPCHK(pe());
         return 0;
     }
 
     int hexp() {
-        hipLaunchKernelGGL((k_hexp<T, RP>), dim3((int)im.h_tiles.size()), dim3(kThreads),
-                           0, s, im.P, im.d_h_tiles, (const T*)im.Bf, im.Gd, (T*)im.H,
-                           im.st, 0, (int64_t)0);
+        HIPCHK(pb(PK_HEXP));
+        const unsigned nt = (unsigned)im.h_tiles.size();
+        switch (im.P.n) {
+            case 2:
+                hipLaunchKernelGGL((k_hexp<T, RP, 2>), dim3(nt), dim3(kThreads), 0, s, im.P,
+                                   im.d_h_tiles, (const T*)im.Bf, im.Gd, (T*)im.H, im.st, 0,
+                                   (int64_t)0);
+                break;
+            case 3:
+                hipLaunchKernelGGL((k_hexp<T, RP, 3>), dim3(nt), dim3(kThreads), 0, s, im.P,
+                                   im.d_h_tiles, (const T*)im.Bf, im.Gd, (T*)im.H, im.st, 0,
+                                   (int64_t)0);
+                break;
+            default:
+                if constexpr (RP <= 8)
+                    hipLaunchKernelGGL((k_hexp<T, RP, 4>), dim3(nt), dim3(kThreads), 0, s,
+                                       im.P, im.d_h_tiles, (const T*)im.Bf, im.Gd, (T*)im.H,
+                                       im.st, 0, (int64_t)0);
+                break;
+        }
         HIPCHK(hipGetLastError());
+        HIPCHK(pe());
         return 0;
     }
 
-    // Step (II): L-update from C (equations 5-6) into B_i, G, H_b.
-    int lupdate(const T* C, int warm) {
+    // Step (II): L-update from C (equations 5-6) into B_i, G, H_b.  With
+    // `decide`, the Gram launch also forms e^(kcur) from k_ht's partials.
+    int lupdate(const T* C, int warm, int decide_flag, int kcur, double tol) {
         const Prob& P = im.P;
         const int n = P.n;
-        hipLaunchKernelGGL((k_gram<T>), dim3((int)im.gram_items.size()), dim3(kThreads), 0,
-                           s, P, C, im.d_gram_items, im.gpart, im.gcnt, im.gram, im.st);
+        const int ng = (int)im.gram_items.size();
+        HIPCHK(pb(PK_GRAM));
+        hipLaunchKernelGGL((k_gram<T>), dim3(ng + 1), dim3(kThreads), 0, s, P, C,
+                           im.d_gram_items, ng, im.gpart, decide_flag,
+                           (const double*)im.hpart, kcur, tol, im.err_hist, im.st);
         HIPCHK(hipGetLastError());
+        HIPCHK(pe());
         int smax = 0, rmax = 0;
         for (int i = 0; i < n; ++i) {
             smax = std::max(smax, P.s[i]);
@@ -381,36 +469,30 @@ struct Runner {
             lds = lds_g;
             use_lds = 1;
         }
-        hipLaunchKernelGGL(k_eig, dim3(n), dim3(kThreads), lds, s, P, im.gram, im.W,
-                           im.Y, im.lam, warm, 200, 1e-13, use_lds, im.st);
+        HIPCHK(pb(PK_EIG));
+        hipLaunchKernelGGL(k_eig, dim3(n), dim3(kEigThreads), lds, s, P,
+                           (const double*)im.gpart, im.gram, im.W, im.Y, im.lam, warm, 200,
+                           1e-13, use_lds, im.st);
         HIPCHK(hipGetLastError());
-        hipLaunchKernelGGL((k_zmat<T, RP>), dim3((int)im.z_tiles.size()), dim3(kThreads), 0,
-                           s, P, C, im.Y, im.Z, im.d_z_tiles, im.st);
+        HIPCHK(pe());
+        const int nz = (int)im.z_tiles.size();
+        HIPCHK(pb(PK_ZCORE));
+        hipLaunchKernelGGL((k_zcore<T, RP>), dim3(nz + P.s[0]), dim3(kThreads), 0, s, P, C,
+                           (const double*)im.Y, im.Z, im.d_z_tiles, nz, (const double*)im.W,
+                           im.Tc, im.st);
         HIPCHK(hipGetLastError());
-        // core G = R x_i W_i^T, last mode first
-        int64_t lead = 1;
-        for (int j = 0; j < n; ++j) {
-            const int q = n - 1 - j;
-            int64_t rest = 1;
-            for (int l = 0; l < q; ++l) rest *= P.s[l];
-            const int M = (int)(lead * rest), K = P.s[q];
-            double* out = (j == n - 1) ? im.Gd : im.ctmp[j % 2];
-            const int nwg = (M + 4 * kContractRowsPerWave - 1) / (4 * kContractRowsPerWave);
-            if (j == 0)
-                hipLaunchKernelGGL((k_contract<T, RP>), dim3(nwg), dim3(kThreads), 0, s,
-                                   C + P.blk[0].off, M, K, im.W + P.woff[q], P.r[q], out,
-                                   im.st);
-            else
-                hipLaunchKernelGGL((k_contract<double, RP>), dim3(nwg), dim3(kThreads), 0, s,
-                                   (const double*)im.ctmp[(j - 1) % 2], M, K,
-                                   im.W + P.woff[q], P.r[q], out, im.st);
-            HIPCHK(hipGetLastError());
-            lead *= P.r[q];
-        }
-        hipLaunchKernelGGL((k_bfac<T, RP>), dim3((int)im.bfac_items.size()), dim3(kThreads),
-                           0, s, P, C, im.Z, im.d_bfac_items, im.bpart, im.bcnt, (T*)im.Bf,
-                           im.Bd, im.st);
+        HIPCHK(pe());
+        HIPCHK(pb(PK_BFAC));
+        hipLaunchKernelGGL((k_bfac<T, RP>), dim3((unsigned)im.bfac_items.size()), dim3(kThreads),
+                           0, s, P, C, (const double*)im.Z, im.d_bfac_items, im.bpart, im.st);
         HIPCHK(hipGetLastError());
+        HIPCHK(pe());
+        HIPCHK(pb(PK_BRED));
+        hipLaunchKernelGGL((k_bred<T, RP>), dim3(im.n_bred_wg + 1), dim3(kThreads), 0, s, P,
+                           (const double*)im.bpart, (T*)im.Bf, im.Bd, im.n_bred_wg,
+                           (const double*)im.W, (const double*)im.Tc, im.Gd, im.st);
+        HIPCHK(hipGetLastError());
+        HIPCHK(pe());
         return hexp();
     }
 
@@ -447,12 +529,12 @@ struct Runner {
             double tol, int max_iter, uint64_t seed) {
         const bool resample = h->variant == RTCUR_RESAMPLE;
         int rc;
+        im.recs.clear();
+        im.ev_used = 0;
         draw_sample(seed, 0, sh, sh.chidori, h->sample);
         if ((rc = upload_sample(h->sample, sh))) return rc;
         hipLaunchKernelGGL(k_init_state, dim3(1), dim3(64), 0, s, im.st, zeta0 > 0 ? zeta0 : 0.0);
         HIPCHK(hipGetLastError());
-        HIPCHK(hipMemsetAsync(im.gcnt, 0, sizeof(unsigned) * std::max(im.n_gram_pairs, 1), s));
-        HIPCHK(hipMemsetAsync(im.bcnt, 0, sizeof(unsigned) * std::max(im.n_bfac_groups, 1), s));
         // zero factors so that a k = 0 result reconstructs to L = 0
         HIPCHK(hipMemsetAsync(im.Bf, 0, im.bf_elems * sizeof(T), s));
         HIPCHK(hipMemsetAsync(im.Bd, 0, im.bf_elems * sizeof(double), s));
@@ -461,37 +543,40 @@ struct Runner {
         if (!(zeta0 > 0)) {
             int64_t N = 1;
             for (int i = 0; i < sh.n; ++i) N *= sh.d[i];
-            const int nwg = 2048;
+            HIPCHK(pb(PK_ABSMAX));
             if (xdt == RTCUR_F64)
-                hipLaunchKernelGGL((k_absmax<double>), dim3(nwg), dim3(kThreads), 0, s,
-                                   (const double*)X, N, im.part, im.st);
+                hipLaunchKernelGGL((k_absmax<double>), dim3(kAbsmaxWG), dim3(kThreads), 0, s,
+                                   (const double*)X, N, im.part);
             else
-                hipLaunchKernelGGL((k_absmax<float>), dim3(nwg), dim3(kThreads), 0, s,
-                                   (const float*)X, N, im.part, im.st);
+                hipLaunchKernelGGL((k_absmax<float>), dim3(kAbsmaxWG), dim3(kThreads), 0, s,
+                                   (const float*)X, N, im.part);
             HIPCHK(hipGetLastError());
+            hipLaunchKernelGGL(k_absmax_fin, dim3(1), dim3(kThreads), 0, s,
+                               (const double*)im.part, kAbsmaxWG, im.st);
+            HIPCHK(hipGetLastError());
+            HIPCHK(pe());
         }
         if ((rc = gather(X, xdt, kFirstGather))) return rc;
         DevState ds;
-        if ((rc = read_state(ds))) return rc;
-        int K = 0;
-        bool stopped = ds.stop != 0;
-        if (!stopped && tol >= 1.0) stopped = true;  // e^(0) = 1 <= tol
-        if (!stopped) {
-            if (!resample) {
-                rc = loop_fixed(gamma, tol, max_iter, ds);
-            } else {
-                rc = loop_resample(X, xdt, sh, gamma, tol, max_iter, seed, ds);
-            }
+        const bool skip = tol >= 1.0;  // e^(0) = 1 <= tol: no iteration
+        if (!skip) {
+            rc = resample ? loop_resample(X, xdt, sh, gamma, tol, max_iter, seed, ds)
+                          : loop_fixed(gamma, tol, max_iter, ds);
             if (rc) return rc;
+        } else if ((rc = read_state(ds))) {
+            return rc;
         }
         if (ds.status < 0) {
             h->last_error = ds.status == RTCUR_E_RANK ? "U_i has numerical rank below r_i"
                                                       : "non-finite value in X or e^(k)";
             h->have_result = false;
+            im.recs.clear();
+            im.ev_used = 0;
             return ds.status;
         }
-        K = ds.stop ? ds.final_iter : max_iter;
-        if (tol >= 1.0 && !ds.stop) K = 0;
+        int K = ds.stop ? ds.final_iter : max_iter;
+        if (skip) K = 0;
+        if ((rc = prof_collect(K))) return rc;
         im.final_iter = K;
         im.cur = K % 2;
         // histories
@@ -526,11 +611,12 @@ struct Runner {
     int loop_fixed(double gamma, double tol, int max_iter, DevState& ds) {
         int done = 0;
         int rc;
+        if ((rc = read_state(ds))) return rc;
+        if (ds.stop) return 0;
         double e_prev = -1.0, e_last = -1.0;
         std::vector<double> eh(2);
         while (done < max_iter) {
-            int chunk = 8;
-            if (done < 2) chunk = 2;
+            int chunk = done < 2 ? 2 : 8;
             if (e_last > 0 && e_prev > 0 && e_last < e_prev) {
                 const double rate = e_last / e_prev;
                 const double need = std::log(tol / e_last) / std::log(rate);
@@ -539,10 +625,11 @@ struct Runner {
             chunk = std::min(chunk, max_iter - done);
             for (int q = 0; q < chunk; ++q) {
                 const int j = done + 1 + q;  // iteration j computes S^j, L^j
+                tag = j;
                 const int flags = kDoHT | (j > 1 ? (kHaveL | kDoE | kDecide) : 0);
-                if ((rc = ht(j - 1, flags, cbuf(j - 1), cbuf(j), im.mask[j % 2], gamma, tol)))
+                if ((rc = ht(j - 1, flags, cbuf(j - 1), cbuf(j), im.mask[j % 2], gamma)))
                     return rc;
-                if ((rc = lupdate(cbuf(j), j > 1 ? 1 : 0))) return rc;
+                if ((rc = lupdate(cbuf(j), j > 1 ? 1 : 0, j > 1 ? 1 : 0, j - 1, tol))) return rc;
             }
             done += chunk;
             if ((rc = read_state(ds))) return rc;
@@ -555,16 +642,20 @@ struct Runner {
             }
         }
         // e^(max_iter): one error-only pass
-        if ((rc = ht(max_iter, kHaveL | kDoE | kDecide, cbuf(max_iter), nullptr, nullptr,
-                     gamma, tol)))
+        tag = max_iter + 1;
+        if ((rc = ht(max_iter, kHaveL | kDoE | kDecide, cbuf(max_iter), nullptr, nullptr, gamma)))
             return rc;
+        if ((rc = decide(max_iter, tol))) return rc;
         return read_state(ds);
     }
 
     int loop_resample(const void* X, int xdt, const Shape& sh, double gamma, double tol,
                       int max_iter, uint64_t seed, DevState& ds) {
         int rc;
+        if ((rc = read_state(ds))) return rc;
+        if (ds.stop) return 0;
         for (int j = 1; j <= max_iter; ++j) {
+            tag = j;
             if (j > 1) {
                 // new sample (t = j-1), gather there, L^(j-1) on its columns
                 draw_sample(seed, j - 1, sh, sh.chidori, h->sample);
@@ -573,11 +664,11 @@ struct Runner {
                 if ((rc = hexp())) return rc;
             }
             const int flags = kDoHT | (j > 1 ? kHaveL : 0);
-            if ((rc = ht(j - 1, flags, nullptr, cbuf(j), im.mask[j % 2], gamma, tol))) return rc;
-            if ((rc = lupdate(cbuf(j), 0))) return rc;
+            if ((rc = ht(j - 1, flags, nullptr, cbuf(j), im.mask[j % 2], gamma))) return rc;
+            if ((rc = lupdate(cbuf(j), 0, 0, j - 1, tol))) return rc;
             // e^(j) on this sample
-            if ((rc = ht(j, kHaveL | kDoE | kDecide, cbuf(j), nullptr, nullptr, gamma, tol)))
-                return rc;
+            if ((rc = ht(j, kHaveL | kDoE | kDecide, cbuf(j), nullptr, nullptr, gamma))) return rc;
+            if ((rc = decide(j, tol))) return rc;
             if ((rc = read_state(ds))) return rc;
             if (ds.stop) return 0;
         }
@@ -599,16 +690,15 @@ static int prepare(rtcur_s* h, Impl& im, const Shape& sh, int max_iter) {
     }
     pack_indices(sh, zero, pk);
     Arena ar;
-    size_t o[25];
-    plan(im, sh, sizeof(T), ar, o[0], o[1], o[2], o[3], o[4], o[5], o[6], o[7], o[8], o[9],
-         o[10], o[11], o[12], o[13], o[14], o[15], o[16], o[17], o[18], o[19], o[20], o[21],
-         o[22], o[23], o[24], pk.bytes.size(), max_iter);
+    Regions rg;
+    plan(im, sh, sizeof(T), pk.bytes.size(), max_iter, ar, rg);
     if (ar.total > im.arena_bytes) {
         if (im.arena) HIPCHK(hipFree(im.arena));
         im.arena = nullptr;
         im.arena_bytes = 0;
         hipError_t e = hipMalloc(&im.arena, ar.total);
         if (e != hipSuccess) {
+            (void)hipGetLastError();
             im.arena = nullptr;
             h->last_error = "device workspace allocation failed";
             return RTCUR_E_NOMEM;
@@ -616,31 +706,29 @@ static int prepare(rtcur_s* h, Impl& im, const Shape& sh, int max_iter) {
         im.arena_bytes = ar.total;
     }
     char* a = static_cast<char*>(im.arena);
-    im.esize = sizeof(T);
-    im.XO = a + o[0];
-    im.C[0] = a + o[1];
-    im.C[1] = a + o[2];
-    im.mask[0] = reinterpret_cast<uint64_t*>(a + o[3]);
-    im.mask[1] = reinterpret_cast<uint64_t*>(a + o[4]);
-    im.Bf = a + o[5];
-    im.H = a + o[6];
-    im.W = reinterpret_cast<double*>(a + o[7]);
-    im.Y = reinterpret_cast<double*>(a + o[8]);
-    im.lam = reinterpret_cast<double*>(a + o[9]);
-    im.Z = reinterpret_cast<double*>(a + o[10]);
-    im.gram = reinterpret_cast<double*>(a + o[11]);
-    im.gpart = reinterpret_cast<double*>(a + o[12]);
-    im.bpart = reinterpret_cast<double*>(a + o[13]);
-    im.Bd = reinterpret_cast<double*>(a + o[14]);
-    im.Gd = reinterpret_cast<double*>(a + o[15]);
-    im.ctmp[0] = reinterpret_cast<double*>(a + o[16]);
-    im.ctmp[1] = reinterpret_cast<double*>(a + o[17]);
-    im.part = reinterpret_cast<double*>(a + o[18]);
-    im.err_hist = reinterpret_cast<double*>(a + o[19]);
-    im.gcnt = reinterpret_cast<unsigned*>(a + o[20]);
-    im.bcnt = reinterpret_cast<unsigned*>(a + o[21]);
-    im.st = reinterpret_cast<DevState*>(a + o[22]);
-    char* t = a + o[23];
+    auto dp = [&](size_t off) { return reinterpret_cast<double*>(a + off); };
+    im.XO = a + rg.XO;
+    im.C[0] = a + rg.C0;
+    im.C[1] = a + rg.C1;
+    im.mask[0] = reinterpret_cast<uint64_t*>(a + rg.m0);
+    im.mask[1] = reinterpret_cast<uint64_t*>(a + rg.m1);
+    im.Bf = a + rg.Bf;
+    im.H = a + rg.H;
+    im.W = dp(rg.W);
+    im.Y = dp(rg.Y);
+    im.lam = dp(rg.lam);
+    im.Z = dp(rg.Z);
+    im.gram = dp(rg.gram);
+    im.gpart = dp(rg.gpart);
+    im.bpart = dp(rg.bpart);
+    im.Bd = dp(rg.Bd);
+    im.Gd = dp(rg.Gd);
+    im.Tc = dp(rg.Tc);
+    im.part = dp(rg.part);
+    im.hpart = dp(rg.hpart);
+    im.err_hist = dp(rg.hist);
+    im.st = reinterpret_cast<DevState*>(a + rg.st);
+    char* t = a + rg.tiles;
     im.d_ht_tiles = reinterpret_cast<int4*>(t);
     t += sizeof(int4) * im.ht_tiles.size();
     im.d_gram_items = reinterpret_cast<int4*>(t);
@@ -650,7 +738,7 @@ static int prepare(rtcur_s* h, Impl& im, const Shape& sh, int max_iter) {
     im.d_z_tiles = reinterpret_cast<int2*>(t);
     t += sizeof(int2) * im.z_tiles.size();
     im.d_h_tiles = reinterpret_cast<int2*>(t);
-    im.d_idx = a + o[24];
+    im.d_idx = a + rg.idx;
     im.idx_bytes = pk.bytes.size();
     // work lists (one upload)
     std::vector<char> tb(sizeof(int4) * (im.ht_tiles.size() + im.gram_items.size() +
@@ -666,7 +754,7 @@ static int prepare(rtcur_s* h, Impl& im, const Shape& sh, int max_iter) {
     put(im.bfac_items.data(), sizeof(int4) * im.bfac_items.size());
     put(im.z_tiles.data(), sizeof(int2) * im.z_tiles.size());
     put(im.h_tiles.data(), sizeof(int2) * im.h_tiles.size());
-    HIPCHK(hipMemcpyAsync(a + o[23], tb.data(), tb.size(), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipMemcpyAsync(a + rg.tiles, tb.data(), tb.size(), hipMemcpyHostToDevice, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     return 0;
 }
@@ -726,6 +814,7 @@ static int ensure_scratch(rtcur_s* h, Impl& im, size_t bytes) {
     im.scratch = nullptr;
     im.scratch_bytes = 0;
     if (hipMalloc(&im.scratch, bytes) != hipSuccess) {
+        (void)hipGetLastError();
         h->last_error = "scratch allocation failed";
         return RTCUR_E_NOMEM;
     }
@@ -745,7 +834,7 @@ static int recon_t(rtcur_s* h, Impl& im, void* out) {
         return 0;
     }
     const int64_t ntile = (ncols + kThreads - 1) / kThreads;
-    size_t need = sizeof(T) * RP * ncols + sizeof(int2) * ntile + 256;
+    size_t need = align_up(sizeof(T) * RP * ncols, 256) + sizeof(int2) * ntile + 256;
     int rc = ensure_scratch(h, im, need);
     if (rc) return rc;
     T* Hf = static_cast<T*>(im.scratch);
@@ -755,8 +844,24 @@ static int recon_t(rtcur_s* h, Impl& im, void* out) {
     for (int64_t q = 0; q < ntile; ++q) tl[q] = make_int2(-1, (int)q);
     HIPCHK(hipMemcpyAsync(tiles, tl.data(), sizeof(int2) * ntile, hipMemcpyHostToDevice,
                           h->stream));
-    hipLaunchKernelGGL((k_hexp<T, RP>), dim3((unsigned)ntile), dim3(kThreads), 0, h->stream,
-                       P, tiles, (const T*)im.Bf, im.Gd, Hf, (DevState*)nullptr, 0, ncols);
+    switch (P.n) {
+        case 2:
+            hipLaunchKernelGGL((k_hexp<T, RP, 2>), dim3((unsigned)ntile), dim3(kThreads), 0,
+                               h->stream, P, tiles, (const T*)im.Bf, im.Gd, Hf,
+                               (DevState*)nullptr, 0, ncols);
+            break;
+        case 3:
+            hipLaunchKernelGGL((k_hexp<T, RP, 3>), dim3((unsigned)ntile), dim3(kThreads), 0,
+                               h->stream, P, tiles, (const T*)im.Bf, im.Gd, Hf,
+                               (DevState*)nullptr, 0, ncols);
+            break;
+        default:
+            if constexpr (RP <= 8)
+                hipLaunchKernelGGL((k_hexp<T, RP, 4>), dim3((unsigned)ntile), dim3(kThreads), 0,
+                                   h->stream, P, tiles, (const T*)im.Bf, im.Gd, Hf,
+                                   (DevState*)nullptr, 0, ncols);
+            break;
+    }
     HIPCHK(hipGetLastError());
     dim3 grid((unsigned)ntile, (unsigned)((P.d[0] + kTileRows - 1) / kTileRows));
     hipLaunchKernelGGL((k_recon<T, TO, RP>), grid, dim3(kThreads), 0, h->stream, P.d[0],
