@@ -21,11 +21,10 @@
 namespace rtcur {
 
 constexpr int kThreads = 256;      // 4 waves of 64
-constexpr int kEigThreads = 1024;  // 16 waves for the eigensolver
 constexpr int kTileRows = 16;      // rows per gather / threshold tile
 constexpr int kTileCols = 256;     // one column per thread
 constexpr int kGramMinChunk = 2048; // Gram: columns per work item (at least)
-constexpr int kGramMaxKC = 16;     // Gram: column chunks per output tile (at most)
+constexpr int kGramMaxKC = 4;      // Gram: column chunks per output tile (at most)
 constexpr int kBfacRowsPerWave = 4;
 constexpr int kBfacRows = 4 * kBfacRowsPerWave;
 
@@ -35,16 +34,48 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 
 // ----------------------------------------------------------------- helpers
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+// Wave64 reductions on DPP lane moves (no LDS round trips): quad swaps,
+// half-row and row mirrors, then row broadcasts 15 and 31 fold the four
+// rows into lane 63, which is read back for every lane.  Fixed order.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_mov(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWMASK, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWMASK, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double lane63(double v) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+    return __hiloint2double(hi, lo);
+}
+
+// sum over each quad of lanes (xor 1, xor 2), result in all four lanes
+__device__ __forceinline__ double quad_sum(double v) {
+    v += dpp_mov<0xB1, 0xF>(v);  // quad_perm [1,0,3,2]
+    v += dpp_mov<0x4E, 0xF>(v);  // quad_perm [2,3,0,1]
     return v;
 }
 
+__device__ __forceinline__ double wave_sum(double v) {
+    v = quad_sum(v);
+    v += dpp_mov<0x141, 0xF>(v);  // row_half_mirror
+    v += dpp_mov<0x140, 0xF>(v);  // row_mirror
+    v += dpp_mov<0x142, 0xA>(v);  // row_bcast:15 into rows 1, 3
+    v += dpp_mov<0x143, 0xC>(v);  // row_bcast:31 into rows 2, 3
+    return lane63(v);
+}
+
 __device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    return v;
+    // max is idempotent: moves from disabled rows contribute 0 <= |x|, so
+    // this is only used on non-negative values
+    v = fmax(v, dpp_mov<0xB1, 0xF>(v));
+    v = fmax(v, dpp_mov<0x4E, 0xF>(v));
+    v = fmax(v, dpp_mov<0x141, 0xF>(v));
+    v = fmax(v, dpp_mov<0x140, 0xF>(v));
+    v = fmax(v, dpp_mov<0x142, 0xA>(v));
+    v = fmax(v, dpp_mov<0x143, 0xC>(v));
+    return lane63(v);
 }
 
 // Sum over all threads of the workgroup in a fixed order (NW waves); every
@@ -343,7 +374,7 @@ __global__ __launch_bounds__(kThreads) void k_decide(Prob P, const double* part,
 // 2048 columns, a quarter per wave),
 // as a chain of V_MFMA_F64_16X16X4 (lane l feeds row l%16, k-slot l/16; the
 // accumulator's register v of lane l is row 4v + l/16, column l%16).  The
-// per-item tiles are summed by the eigensolver.  With `decide`, one extra
+// eigensolver adds the per-chunk tiles in order.  With `decide`, one extra
 // workgroup forms e^(k) from the threshold pass's partials.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_gram(
@@ -371,9 +402,10 @@ __global__ __launch_bounds__(kThreads) void k_gram(
     const int kbeg = kc * P.gchunk[i] + w * kw;
     const int kend = min(kbeg + kw, m);
     v4d acc = {0.0, 0.0, 0.0, 0.0};
-    for (int k0 = kbeg; k0 < kend; k0 += 64) {
-        // 4 k-steps of 16 columns: 16 loads of A and 16 of B in flight
-        T ra[16], rb[16];
+    // 4 k-steps of 16 columns per batch (16 loads of A and 16 of B); the
+    // next batch's loads are issued before this batch's MFMAs
+    T ra[16], rb[16];
+    auto load = [&](int k0) {
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const int kk = k0 + 16 * (q >> 2) + 4 * g + (q & 3);
@@ -381,14 +413,21 @@ __global__ __launch_bounds__(kThreads) void k_gram(
             ra[q] = rowA[ks];
             rb[q] = rowB[ks];
         }
+    };
+    if (kbeg < kend) load(kbeg);
+    for (int k0 = kbeg; k0 < kend; k0 += 64) {
+        double av[16], bv[16];
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const int kk = k0 + 16 * (q >> 2) + 4 * g + (q & 3);
             const bool in = kk < kend;
-            const double av = (okA && in) ? (double)ra[q] : 0.0;
-            const double bv = (okB && in) ? (double)rb[q] : 0.0;
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+            av[q] = (okA && in) ? (double)ra[q] : 0.0;
+            bv[q] = (okB && in) ? (double)rb[q] : 0.0;
         }
+        if (k0 + 64 < kend) load(k0 + 64);
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q], bv[q], acc, 0, 0, 0);
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) sacc[w][(4 * v + g) * 16 + (lane & 15)] = acc[v];
@@ -398,14 +437,16 @@ __global__ __launch_bounds__(kThreads) void k_gram(
 }
 
 // ------------------------------------------------ truncated eigensolver
-// Top-r eigenpairs of Gram_i = U_i U_i^T in float64, one 1024-thread
-// workgroup per mode: the Gram is assembled in LDS from the k_gram tiles,
-// then subspace iteration (warm-started from the previous iterate's W_i
-// under RTCUR-F) with Cholesky-QR orthonormalisation runs until the residual
-// ||G Q - Q T||_F <= rtol ||T||_F with T = Q^T G Q, and a Rayleigh-Ritz step
-// T = V diag(lambda) V^T (cyclic Jacobi) gives W_i = Q V.  The singular
-// values of U_i are sqrt(lambda); Y_i = W_i diag(1/lambda) so that
-// U_i^+ = U_i^T Y_i W_i^T.  Rank test: lambda_r <= 64 s 2^-52 lambda_1.
+// Top-r eigenspace of Gram_i = U_i U_i^T in float64, one 256-thread
+// workgroup per mode, thread a owning row a of the s x r iterates: the Gram
+// is assembled (in LDS when it fits) from k_gram's tiles; subspace
+// iteration (warm-started from the previous iterate's W_i under RTCUR-F)
+// with Cholesky-QR orthonormalisation runs until the residual
+// ||G Q - Q T||_F <= rtol ||T||_F with T = Q^T G Q.  Then W_i = Q and
+// Y_i = Q T^-1, so that the truncated pseudo-inverse is
+// U_i^+ = U_i^T Y_i W_i^T: the operator V_r S_r^-1 W_r^T of the SVD written
+// in another orthonormal basis of the same subspace.  Padded columns
+// r..RP-1 stay zero.
 
 __device__ __forceinline__ uint32_t eig_hash(uint32_t a, uint32_t b) {
     uint32_t h = a * 0x9E3779B1u ^ (b + 0x7F4A7C15u) * 0x85EBCA77u;
@@ -415,292 +456,391 @@ __device__ __forceinline__ uint32_t eig_hash(uint32_t a, uint32_t b) {
     return h;
 }
 
-constexpr int kEigWaves = kEigThreads / 64;
+template <int RP>
+struct EigShared {
+    double qs[kMaxS * RP];                 // Q rows (G Q product, dot products)
+    double zs[kMaxS * RP];                 // Z rows (dot products)
+    double tm[RP * RP], mm[RP * RP];       // T = Q^T Z, M = Z^T Z
+    double halves[2 * (RP * RP + RP * (RP + 1) / 2)];  // half-dot products
+    double red[4];
+    int ok;
+};
 
-// Out (r x r) = A^T B for s x r row-major A, B in LDS; wave-parallel dots.
-__device__ void eig_atb(const double* A, const double* B, int s, int r, double* Out) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    for (int q = w; q < r * r; q += kEigWaves) {
-        const int p = q / r, t = q % r;
-        double v = 0.0;
-        for (int a = lane; a < s; a += 64) v += A[a * r + p] * B[a * r + t];
-        v = wave_sum(v);
-        if (lane == 0) Out[q] = v;
-    }
-}
-
-// Cholesky of the r x r SPD matrix M (row-major) into upper R, M = R^T R.
-// Single thread.  Returns false if a pivot is not positive.
-__device__ bool eig_chol(const double* M, double* R, int r) {
-    for (int p = 0; p < r * r; ++p) R[p] = 0.0;
-    for (int j = 0; j < r; ++j) {
-        double d = M[j * r + j];
-        for (int k = 0; k < j; ++k) d -= R[k * r + j] * R[k * r + j];
-        if (!(d > 0.0)) return false;
-        const double rjj = sqrt(d);
-        R[j * r + j] = rjj;
-        for (int q = j + 1; q < r; ++q) {
-            double v = M[j * r + q];
-            for (int k = 0; k < j; ++k) v -= R[k * r + j] * R[k * r + q];
-            R[j * r + q] = v / rjj;
-        }
-    }
-    return true;
-}
-
-// Q = Z R^-1 (row by row), R upper triangular r x r.
-__device__ void eig_trsm(const double* Z, const double* R, int s, int r, double* Q) {
-    for (int a = threadIdx.x; a < s; a += kEigThreads) {
-        double q[kMaxRank];
-        for (int p = 0; p < r; ++p) {
-            double v = Z[a * r + p];
-            for (int k = 0; k < p; ++k) v -= q[k] * R[k * r + p];
-            q[p] = v / R[p * r + p];
-        }
-        for (int p = 0; p < r; ++p) Q[a * r + p] = q[p];
-    }
-}
-
-// Z = G Q (s x s times s x r): 4 threads share one output, each summing a
-// quarter of b, combined with two shuffles.
-__device__ void eig_gq(const double* G, const double* Q, int s, int r, double* Z) {
-    const int sub = threadIdx.x & 3;
-    for (int idx = threadIdx.x >> 2; idx < ((s * r + 63) / 64) * 64; idx += kEigThreads / 4) {
-        const bool ok = idx < s * r;
-        const int id = ok ? idx : 0;
-        const int a = id / r, p = id % r;
-        const double* g = G + a * s;
-        double v0 = 0.0, v1 = 0.0;
-        int b = sub;
-        for (; b + 4 < s; b += 8) {
-            v0 = fma(g[b], Q[b * r + p], v0);
-            v1 = fma(g[b + 4], Q[(b + 4) * r + p], v1);
-        }
-        if (b < s) v0 = fma(g[b], Q[b * r + p], v0);
-        double v = v0 + v1;
-        v += __shfl_xor(v, 1, 64);
-        v += __shfl_xor(v, 2, 64);
-        if (ok && sub == 0) Z[idx] = v;
-    }
-}
-
-// Cyclic Jacobi on the symmetric r x r matrix A (single thread): A is
-// overwritten by its diagonalisation, V accumulates the rotations.
-__device__ void eig_jacobi(double* A, double* V, int r) {
-    for (int p = 0; p < r; ++p)
-        for (int q = 0; q < r; ++q) V[p * r + q] = (p == q) ? 1.0 : 0.0;
-    for (int sweep = 0; sweep < 60; ++sweep) {
-        double off = 0.0, tot = 0.0;
-        for (int p = 0; p < r; ++p)
-            for (int q = 0; q < r; ++q) {
-                const double v = A[p * r + q] * A[p * r + q];
-                tot += v;
-                if (p != q) off += v;
-            }
-        if (off <= 1e-32 * tot || off == 0.0) break;
-        for (int p = 0; p < r - 1; ++p) {
-            for (int q = p + 1; q < r; ++q) {
-                const double apq = A[p * r + q];
-                if (apq == 0.0) continue;
-                const double app = A[p * r + p], aqq = A[q * r + q];
-                const double theta = (aqq - app) / (2.0 * apq);
-                const double t = (theta >= 0.0 ? 1.0 : -1.0) /
-                                 (fabs(theta) + sqrt(theta * theta + 1.0));
-                const double cs = 1.0 / sqrt(t * t + 1.0), sn = t * cs;
-                for (int k = 0; k < r; ++k) {  // A <- A J (columns p, q)
-                    const double akp = A[k * r + p], akq = A[k * r + q];
-                    A[k * r + p] = cs * akp - sn * akq;
-                    A[k * r + q] = sn * akp + cs * akq;
-                }
-                for (int k = 0; k < r; ++k) {  // A <- J^T A (rows p, q)
-                    const double apk = A[p * r + k], aqk = A[q * r + k];
-                    A[p * r + k] = cs * apk - sn * aqk;
-                    A[q * r + k] = sn * apk + cs * aqk;
-                }
-                for (int k = 0; k < r; ++k) {  // V <- V J
-                    const double vkp = V[k * r + p], vkq = V[k * r + q];
-                    V[k * r + p] = cs * vkp - sn * vkq;
-                    V[k * r + q] = sn * vkp + cs * vkq;
-                }
-            }
-        }
-    }
-}
-
-__global__ __launch_bounds__(kEigThreads) void k_eig(Prob P,
-                                                     const double* __restrict__ gpart,
-                                                     double* __restrict__ gram,
-                                                     double* __restrict__ W,
-                                                     double* __restrict__ Y,
-                                                     double* __restrict__ lam,
-                                                     int warm, int maxit, double rtol,
-                                                     int use_lds_gram, DevState* st) {
-    if (stopped(st)) return;
-    extern __shared__ double lds[];
-    __shared__ double red[kEigWaves];
-    __shared__ double Tm[kMaxRank * kMaxRank], Mm[kMaxRank * kMaxRank],
-        Rm[kMaxRank * kMaxRank], Vm[kMaxRank * kMaxRank];
-    __shared__ double lamv[kMaxRank];
-    __shared__ int order[kMaxRank];
-    __shared__ int s_ok;
-    const int i = blockIdx.x;
-    const int s = P.s[i], r = P.r[i], RP = P.rp;
-    const int tid = threadIdx.x;
-    double* Q = lds;
-    double* Z = Q + s * r;
-    double* G = use_lds_gram ? Z + s * r : gram + P.goff[i];
-    double* Wi = W + P.woff[i];
-    if (tid == 0) s_ok = 1;
-
-    // assemble the Gram from the per-item tiles (fixed chunk order)
-    {
-        const int nt = (s + 15) / 16;
-        const int npairs = nt * (nt + 1) / 2;
-        const int it0 = P.gitem0[i];
-        const int nkc = P.gnkc[i];
-        const int total = npairs * 256;
-        for (int f = tid; f < total; f += kEigThreads) {
-            const int q = f >> 8, t = f & 255;
-            const double* src = gpart + (int64_t)(it0 + q * nkc) * 256 + t;
-            double v[kGramMaxKC];
+// T = Q^T Z and (when wantM) M = Z^T Z (upper triangle, mirrored) over the
+// workgroup into LDS.  The rows go to LDS; each output's dot product over
+// the s rows is split into two halves, each run by one thread in row order
+// with its loads issued eight rows at a time, and the halves are added.
+template <int RP>
+__device__ void eig_reduce(const double (&q)[RP], const double (&z)[RP], int s, int r,
+                           bool wantM, EigShared<RP>& sh) {
+    constexpr int NT = RP * RP, NM = RP * (RP + 1) / 2, NO = NT + NM;
+    const int a = threadIdx.x;
+    __syncthreads();
+    if (a < s) {
 #pragma unroll
-            for (int kc = 0; kc < kGramMaxKC; ++kc)
-                v[kc] = src[(int64_t)(kc < nkc ? kc : 0) * 256];
-            double sum = 0.0;
-#pragma unroll
-            for (int kc = 0; kc < kGramMaxKC; ++kc)
-                if (kc < nkc) sum += v[kc];
-            // pair q -> (ta, tb), ta <= tb, ta-major
-            int ta = 0, rem = q;
-            while (rem >= nt - ta) {
-                rem -= nt - ta;
-                ++ta;
-            }
-            const int tb = ta + rem;
-            const int a = ta * 16 + (t >> 4), b = tb * 16 + (t & 15);
-            if (a < s && b < s) {
-                G[a * s + b] = sum;
-                G[b * s + a] = sum;
-            }
+        for (int p = 0; p < RP; ++p) {
+            sh.qs[a * RP + p] = q[p];
+            sh.zs[a * RP + p] = z[p];
         }
     }
     __syncthreads();
+    for (int w = threadIdx.x; w < 2 * NO; w += kThreads) {
+        const int e = w % NO, half = w / NO;
+        const bool isM = e >= NT;
+        int p, t;
+        if (!isM) {
+            p = e / RP;
+            t = e % RP;
+        } else {
+            int k = e - NT;
+            p = 0;
+            while (k >= RP - p) {
+                k -= RP - p;
+                ++p;
+            }
+            t = p + k;
+        }
+        double v = 0.0;
+        if (p < r && t < r && (!isM || wantM)) {
+            const int hs = (s + 1) / 2;
+            const int b0 = half * hs, b1 = half ? s : hs;
+            const double* x = isM ? sh.zs : sh.qs;
+            double acc[2] = {0.0, 0.0};
+            for (int b = b0; b < b1; b += 8) {
+                double xv[8], zv[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int bb = b + u < b1 ? b + u : b1 - 1;
+                    xv[u] = x[bb * RP + p];
+                    zv[u] = b + u < b1 ? sh.zs[bb * RP + t] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) acc[u & 1] = fma(xv[u], zv[u], acc[u & 1]);
+            }
+            v = acc[0] + acc[1];
+        }
+        sh.halves[w] = v;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < NO; e += kThreads) {
+        const double v = sh.halves[e] + sh.halves[NO + e];
+        if (e < NT) {
+            sh.tm[e] = v;
+        } else if (wantM) {
+            int k = e - NT, p = 0;
+            while (k >= RP - p) {
+                k -= RP - p;
+                ++p;
+            }
+            const int t = p + k;
+            sh.mm[p * RP + t] = v;
+            sh.mm[t * RP + p] = v;
+        }
+    }
+    __syncthreads();
+}
 
+// Cholesky of M's r x r block (M in LDS, row stride RP) into upper R in
+// registers, in every thread, with Rinv_jj = 1 / R_jj from one reciprocal
+// square root (no divisions); identity beyond r.  Returns false if a pivot
+// is not positive.
+template <int RP>
+__device__ __forceinline__ bool eig_chol(const double* M, int r, double (&R)[RP][RP],
+                                         double (&dinv)[RP]) {
+    bool ok = true;
+#pragma unroll
+    for (int j = 0; j < RP; ++j) {
+        dinv[j] = 1.0;
+#pragma unroll
+        for (int q = 0; q < RP; ++q) R[j][q] = (j == q) ? 1.0 : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < RP; ++j) {
+        if (j < r) {
+            double d = M[j * RP + j];
+#pragma unroll
+            for (int k = 0; k < j; ++k) d -= R[k][j] * R[k][j];
+            ok = ok && d > 0.0;
+            const double ri = rsqrt(d > 0.0 ? d : 1.0);
+            dinv[j] = ri;
+            R[j][j] = d * ri;
+#pragma unroll
+            for (int q = j + 1; q < RP; ++q) {
+                if (q < r) {
+                    double v = M[j * RP + q];
+#pragma unroll
+                    for (int k = 0; k < j; ++k) v -= R[k][j] * R[k][q];
+                    R[j][q] = v * ri;
+                }
+            }
+        }
+    }
+    return ok;
+}
+
+// q = z R^-1 for this thread's row.
+template <int RP>
+__device__ __forceinline__ void eig_trsm(const double (&z)[RP], const double (&R)[RP][RP],
+                                         const double (&dinv)[RP], double (&q)[RP]) {
+#pragma unroll
+    for (int p = 0; p < RP; ++p) {
+        double v = z[p];
+#pragma unroll
+        for (int k = 0; k < p; ++k) v -= q[k] * R[k][p];
+        q[p] = v * dinv[p];
+    }
+}
+
+// z = (G Q)(a, :) with G symmetric in LDS (column a read, conflict-free),
+// rows of Q taken eight at a time so that their loads overlap.
+template <int RP>
+__device__ __forceinline__ void eig_gq(const double* G, const double* qs, int s, int a, bool act,
+                                       double (&z)[RP]) {
+#pragma unroll
+    for (int p = 0; p < RP; ++p) z[p] = 0.0;
+    if (!act) return;
+    for (int b = 0; b < s; b += 8) {
+        double g[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int bb = b + u < s ? b + u : s - 1;
+            g[u] = b + u < s ? G[bb * s + a] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int bb = b + u < s ? b + u : s - 1;
+#pragma unroll
+            for (int p = 0; p < RP; ++p) z[p] = fma(g[u], qs[bb * RP + p], z[p]);
+        }
+    }
+}
+
+template <int RP>
+__global__ __launch_bounds__(kThreads) void k_eig(Prob P, const double* __restrict__ gpart,
+                                                  double* __restrict__ gram,
+                                                  double* __restrict__ W,
+                                                  double* __restrict__ Y, int warm,
+                                                  int maxit, double rtol, int gram_in_lds,
+                                                  DevState* st) {
+    if (stopped(st)) return;
+    extern __shared__ double Gl[];  // s x s, when it fits
+    __shared__ EigShared<RP> sh;
+    const int i = blockIdx.x;
+    const int s = P.s[i], r = P.r[i];
+    const int a = threadIdx.x;
+    const bool act = a < s;
+    double* Gg = gram + P.goff[i];
+    double* G = gram_in_lds ? Gl : Gg;
+    {
+        // the Gram from k_gram's per-chunk tiles, chunks added in order
+        const int nt = (s + 15) / 16;
+        const int npairs = nt * (nt + 1) / 2;
+        const int nkc = P.gnkc[i];
+        const int total = npairs * 256;
+        const double* src0 = gpart + (int64_t)P.gitem0[i] * 256;
+        for (int f0 = threadIdx.x; f0 < total; f0 += 8 * kThreads) {
+            double v[8][kGramMaxKC];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int f = f0 + u * kThreads < total ? f0 + u * kThreads : f0;
+                const double* src = src0 + (int64_t)(f >> 8) * nkc * 256 + (f & 255);
+#pragma unroll
+                for (int q = 0; q < kGramMaxKC; ++q)
+                    v[u][q] = q < nkc ? src[(int64_t)q * 256] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int f = f0 + u * kThreads;
+                if (f >= total) continue;
+                double sum = 0.0;
+#pragma unroll
+                for (int q = 0; q < kGramMaxKC; ++q)
+                    if (q < nkc) sum += v[u][q];
+                // pair f/256 -> (ta, tb), ta <= tb, ta-major
+                int ta = 0, rem = f >> 8;
+                while (rem >= nt - ta) {
+                    rem -= nt - ta;
+                    ++ta;
+                }
+                const int tb = ta + rem, t = f & 255;
+                const int a2 = ta * 16 + (t >> 4), b2 = tb * 16 + (t & 15);
+                if (a2 < s && b2 < s) {
+                    G[a2 * s + b2] = sum;
+                    G[b2 * s + a2] = sum;
+                }
+            }
+        }
+    }
+    if (threadIdx.x == 0) sh.ok = 1;
+    double* Wi = W + P.woff[i];
+    double q[RP], z[RP];
     if (warm) {
-        for (int e = tid; e < s * r; e += kEigThreads) Q[e] = Wi[(e / r) * RP + e % r];
+#pragma unroll
+        for (int p = 0; p < RP; ++p) q[p] = (act && p < r) ? Wi[a * RP + p] : 0.0;
+        __syncthreads();
     } else {
         // start block G * Omega, Omega a fixed +-1 pattern, then CholQR twice
-        for (int e = tid; e < s * r; e += kEigThreads)
-            Z[e] = (eig_hash(e / r, e % r) & 1u) ? 1.0 : -1.0;
-        __syncthreads();
-        eig_gq(G, Z, s, r, Q);
-        __syncthreads();
-        for (int rep = 0; rep < 2; ++rep) {
-            eig_atb(Q, Q, s, r, Mm);
-            __syncthreads();
-            if (tid == 0) s_ok = eig_chol(Mm, Rm, r);
-            __syncthreads();
-            if (!s_ok) break;
-            for (int e = tid; e < s * r; e += kEigThreads) Z[e] = Q[e];
-            __syncthreads();
-            eig_trsm(Z, Rm, s, r, Q);
-            __syncthreads();
+        for (int e = threadIdx.x; e < s * RP; e += kThreads) {
+            const int b = e / RP, p = e % RP;
+            sh.qs[e] = p < r ? ((eig_hash(b, p) & 1u) ? 1.0 : -1.0) : 0.0;
         }
-        if (!s_ok) {
-            if (tid == 0) {
+        __syncthreads();
+        eig_gq<RP>(G, sh.qs, s, a, act, z);
+        bool ok = true;
+        for (int rep = 0; rep < 2 && ok; ++rep) {
+            eig_reduce<RP>(z, z, s, r, true, sh);
+            double R[RP][RP], di[RP];
+            ok = eig_chol<RP>(sh.mm, r, R, di);
+            if (ok) {
+                eig_trsm<RP>(z, R, di, q);
+#pragma unroll
+                for (int p = 0; p < RP; ++p) z[p] = q[p];
+            }
+        }
+        if (!ok) {
+            if (threadIdx.x == 0) {
                 st->stop = 1;
                 st->status = RTCUR_E_RANK;
             }
             return;
         }
     }
-    __syncthreads();
     int steps = 0;
     bool conv = false;
-    for (; steps <= maxit; ++steps) {
-        eig_gq(G, Q, s, r, Z);
+    for (;; ++steps) {
         __syncthreads();
-        eig_atb(Q, Z, s, r, Tm);
-        __syncthreads();
-        double rn = 0.0;
-        for (int e = tid; e < s * r; e += kEigThreads) {
-            const int a = e / r, p = e % r;
-            double v = Z[e];
-            for (int k = 0; k < r; ++k) v -= Q[a * r + k] * Tm[k * r + p];
-            rn += v * v;
+        if (act) {
+#pragma unroll
+            for (int p = 0; p < RP; ++p) sh.qs[a * RP + p] = q[p];
         }
-        rn = block_sum<kEigWaves>(rn, red);
-        double tn = 0.0;
-        for (int e = 0; e < r * r; ++e) tn += Tm[e] * Tm[e];
+        __syncthreads();
+        eig_gq<RP>(G, sh.qs, s, a, act, z);
+        const bool last = steps == maxit;
+        eig_reduce<RP>(q, z, s, r, true, sh);
+        double rn = 0.0, tn = 0.0;
+        {
+            double Tr[RP][RP];
+#pragma unroll
+            for (int k = 0; k < RP; ++k)
+#pragma unroll
+                for (int p = 0; p < RP; ++p) {
+                    Tr[k][p] = sh.tm[k * RP + p];
+                    tn += Tr[k][p] * Tr[k][p];
+                }
+#pragma unroll
+            for (int p = 0; p < RP; ++p) {
+                double v = z[p];
+#pragma unroll
+                for (int k = 0; k < RP; ++k) v -= q[k] * Tr[k][p];
+                rn += act ? v * v : 0.0;
+            }
+        }
+        rn = block_sum<4>(rn, sh.red);
         if (rn <= rtol * rtol * tn) {
             conv = true;
             break;
         }
-        if (steps == maxit) break;
-        eig_atb(Z, Z, s, r, Mm);
-        __syncthreads();
-        if (tid == 0) s_ok = eig_chol(Mm, Rm, r);
-        __syncthreads();
-        if (!s_ok) break;
-        eig_trsm(Z, Rm, s, r, Q);
-        __syncthreads();
+        if (last) break;
+        double R[RP][RP], di[RP];
+        if (!eig_chol<RP>(sh.mm, r, R, di)) {
+            if (threadIdx.x == 0) sh.ok = 0;
+            break;
+        }
+        eig_trsm<RP>(z, R, di, q);
     }
-    if (!s_ok) {
-        if (tid == 0) {
+    __syncthreads();
+    if (!sh.ok) {
+        if (threadIdx.x == 0) {
             st->stop = 1;
             st->status = RTCUR_E_RANK;
         }
         return;
     }
-    // Rayleigh-Ritz: T = Q^T G Q (symmetrised), T = V diag(lambda) V^T
-    if (tid == 0) {
-        for (int p = 0; p < r; ++p)
-            for (int q = 0; q < r; ++q) Mm[p * r + q] = 0.5 * (Tm[p * r + q] + Tm[q * r + p]);
-        eig_jacobi(Mm, Vm, r);
-        for (int p = 0; p < r; ++p) {
-            lamv[p] = Mm[p * r + p];
-            order[p] = p;
-        }
-        for (int p = 1; p < r; ++p) {  // insertion sort, descending
-            int o = order[p], q = p;
-            while (q > 0 && lamv[order[q - 1]] < lamv[o]) {
-                order[q] = order[q - 1];
-                --q;
-            }
-            order[q] = o;
-        }
-        atomicAdd(&st->eig_steps, steps);
-        if (!conv) atomicAdd(&st->eig_unconverged, 1);
-        const double l1 = lamv[order[0]], lr = lamv[order[r - 1]];
-        if (!isfinite(l1)) {
-            st->stop = 1;
-            st->status = RTCUR_E_NONFINITE;
-        } else if (!(l1 > 0.0) || lr <= 64.0 * s * 0x1p-52 * l1) {
-            st->stop = 1;
-            st->status = RTCUR_E_RANK;
-        }
+    // Q spans the top-r eigenspace and T = Q^T G Q, so the truncated
+    // pseudo-inverse of the Gram is Q T^-1 Q^T: W_i = Q, Y_i = Q T^-1 with
+    // T = R^T R (Cholesky of the symmetrised T, every thread).
+    __syncthreads();
+    if (threadIdx.x < RP * RP) {
+        const int p = threadIdx.x / RP, t = threadIdx.x % RP;
+        sh.mm[threadIdx.x] = 0.5 * (sh.tm[p * RP + t] + sh.tm[t * RP + p]);
     }
     __syncthreads();
-    double* Yi = Y + P.woff[i];
-    double* li = lam + P.loff[i];
-    for (int e = tid; e < s * RP; e += kEigThreads) {
-        const int a = e / RP, p = e % RP;
-        double wv = 0.0, yv = 0.0;
-        if (p < r) {
-            const int o = order[p];
-            for (int k = 0; k < r; ++k) wv += Q[a * r + k] * Vm[k * r + o];
-            yv = wv / lamv[o];
-        }
-        Wi[e] = wv;
-        Yi[e] = yv;
+    double R[RP][RP], di[RP];
+    const bool tok = eig_chol<RP>(sh.mm, r, R, di);
+    // Rinv = R^-1 (upper triangular)
+    double Ri[RP][RP];
+#pragma unroll
+    for (int j = 0; j < RP; ++j) {
+#pragma unroll
+        for (int q = 0; q < RP; ++q) Ri[j][q] = 0.0;
     }
-    if (tid < RP) li[tid] = tid < r ? lamv[order[tid]] : 0.0;
+#pragma unroll
+    for (int j = RP - 1; j >= 0; --j) {
+        Ri[j][j] = di[j];
+#pragma unroll
+        for (int q = j + 1; q < RP; ++q) {
+            double v = 0.0;
+#pragma unroll
+            for (int k = j + 1; k <= q; ++k) v += R[j][k] * Ri[k][q];
+            Ri[j][q] = -v * di[j];
+        }
+    }
+    {
+        // rank test on ||T||_F >= lambda_1 and 1/||T^-1||_F <= lambda_r
+        // (flag when lambda_r / lambda_1 may be <= 64 s 2^-52); the padded
+        // rows and columns of T and R^-1 are masked out
+        double tf = 0.0, tif = 0.0;
+#pragma unroll
+        for (int p = 0; p < RP; ++p) {
+#pragma unroll
+            for (int t = 0; t < RP; ++t) {
+                const bool in = p < r && t < r;
+                const double tv = in ? sh.mm[p * RP + t] : 0.0;
+                double v = 0.0;  // (R^-1 R^-T)[p][t]
+#pragma unroll
+                for (int k = (p > t ? p : t); k < RP; ++k) v += Ri[p][k] * Ri[t][k];
+                tf += tv * tv;
+                tif += in ? v * v : 0.0;
+            }
+        }
+        if (threadIdx.x == 0) {
+            atomicAdd(&st->eig_steps, steps);
+            if (!conv) atomicAdd(&st->eig_unconverged, 1);
+            if (!isfinite(tf) || !isfinite(tif)) {
+                st->stop = 1;
+                st->status = RTCUR_E_NONFINITE;
+            } else if (!tok || !(tf > 0.0) || 1.0 <= 64.0 * s * 0x1p-52 * sqrt(tf * tif)) {
+                st->stop = 1;
+                st->status = RTCUR_E_RANK;
+            }
+        }
+    }
+    if (act) {
+        // y = q T^-1 = (q R^-1) R^-T
+        double u[RP];
+#pragma unroll
+        for (int p = 0; p < RP; ++p) {
+            double v = 0.0;
+#pragma unroll
+            for (int k = 0; k <= p; ++k) v += q[k] * Ri[k][p];
+            u[p] = v;
+        }
+        double* Yi = Y + P.woff[i];
+#pragma unroll
+        for (int p = 0; p < RP; ++p) {
+            double v = 0.0;
+#pragma unroll
+            for (int k = p; k < RP; ++k) v += u[k] * Ri[p][k];
+            Wi[a * RP + p] = p < r ? q[p] : 0.0;
+            Yi[a * RP + p] = p < r ? v : 0.0;
+        }
+    }
 }
 
 // --------------------------- Z_i = Y_i^T U_i  and the core's first phase
 // Workgroups [0, nz): Z_i (m_i x RP, float64, row per column) with
 // U_i = C_i(I_i, :), so that V_i S_i^-1 = Z_i; 64 columns per workgroup,
-// four threads per column each summing a quarter of the s_i rows.
+// four adjacent lanes per column each summing a quarter of the s_i rows.
 // Workgroups [nz, nz + s_0): T[a] = R(a, :, ..) x_{l >= 1} W_l^T, the core
 // G = R x_i W_i^T before its last contraction (with W_0, done by k_hexp).
 template <typename T, int RP>
@@ -713,8 +853,8 @@ __device__ void zmat_tile(const Prob& P, const T* __restrict__ C, const double* 
     for (int e = threadIdx.x; e < s * RP; e += kThreads) ys[e] = Yi[e];
     __syncthreads();
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int quarter = lane >> 4;
-    const int c = tl.y + w * 16 + (lane & 15);
+    const int quarter = lane & 3;
+    const int c = tl.y + w * 16 + (lane >> 2);
     const int cc = c < m ? c : m - 1;
     const int qlen = (s + 3) / 4;
     const int a0 = quarter * qlen;
@@ -743,10 +883,7 @@ __device__ void zmat_tile(const Prob& P, const T* __restrict__ C, const double* 
         }
     }
 #pragma unroll
-    for (int p = 0; p < RP; ++p) {
-        acc[p] += __shfl_xor(acc[p], 16, 64);
-        acc[p] += __shfl_xor(acc[p], 32, 64);
-    }
+    for (int p = 0; p < RP; ++p) acc[p] = quad_sum(acc[p]);
     if (quarter == 0 && c < m) {
         double* Zi = Zbuf + P.zoff[i] + (int64_t)c * RP;
 #pragma unroll
@@ -755,56 +892,48 @@ __device__ void zmat_tile(const Prob& P, const T* __restrict__ C, const double* 
 }
 
 constexpr int kCoreLds = 4096;  // doubles of LDS for one slice's partial core
+constexpr int kSliceLds = 4096; // elements of R staged per pass
 
 // T[a] for one slice a of the R block (row-major s_0 x ... x s_{n-1}):
-// contract the last mode from global memory, the others in LDS; each step
-// puts the new rank index first, so T[a] ends up ordered (r_1, .., r_{n-1}).
+// contract the last mode (R staged through LDS), then the others in LDS;
+// each step puts the new rank index first, so T[a] ends up ordered
+// (r_1, .., r_{n-1}).
 template <typename T, int RP>
 __device__ void core_slice(const Prob& P, const T* __restrict__ R, const double* __restrict__ W,
-                           double* __restrict__ Tbuf, int a, double* buf, double* ws) {
+                           double* __restrict__ Tbuf, int a, double* buf, double* ws, T* rs) {
     const int n = P.n;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int tid = threadIdx.x;
     int rows = 1;
     for (int l = 1; l < n - 1; ++l) rows *= P.s[l];
     const int K = P.s[n - 1];
     const int rq = P.r[n - 1];
     for (int e = tid; e < K * RP; e += kThreads) ws[e] = W[P.woff[n - 1] + e];
-    __syncthreads();
     const T* Ra = R + (int64_t)a * rows * K;
-    // step 1: buf[p][row] = sum_k Ra[row][k] W_{n-1}[k][p], one wave per row
-    for (int row0 = w * 4; row0 < rows; row0 += 16) {
-        double v[4][4];
+    const int RC = max(1, kSliceLds / K);
+    for (int r0 = 0; r0 < rows; r0 += RC) {
+        const int nr = min(RC, rows - r0);
+        const int ne = nr * K;
+        __syncthreads();
+        for (int e0 = tid; e0 < ne; e0 += 8 * kThreads) {
+            T v[8];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int row = row0 + j < rows ? row0 + j : rows - 1;
+            for (int u = 0; u < 8; ++u) {
+                const int e = e0 + u * kThreads;
+                v[u] = Ra[(int64_t)r0 * K + (e < ne ? e : e0)];
+            }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int k = lane + 64 * u;
-                v[j][u] = k < K ? (double)Ra[(int64_t)row * K + k] : 0.0;
+            for (int u = 0; u < 8; ++u) {
+                const int e = e0 + u * kThreads;
+                if (e < ne) rs[e] = v[u];
             }
         }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            double acc[RP];
-#pragma unroll
-            for (int p = 0; p < RP; ++p) acc[p] = 0.0;
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int k = lane + 64 * u;
-                if (k < K) {
-#pragma unroll
-                    for (int p = 0; p < RP; ++p) acc[p] = fma(v[j][u], ws[k * RP + p], acc[p]);
-                }
-            }
-#pragma unroll
-            for (int p = 0; p < RP; ++p) acc[p] = wave_sum(acc[p]);
-            if (lane < rq && row0 + j < rows) {
-                double o = 0.0;
-#pragma unroll
-                for (int p = 0; p < RP; ++p)
-                    if (p == lane) o = acc[p];
-                buf[lane * rows + row0 + j] = o;
-            }
+        __syncthreads();
+        for (int o = tid; o < rq * nr; o += kThreads) {
+            const int p = o / nr, row = o % nr;
+            const T* rr = rs + row * K;
+            double acc = 0.0;
+            for (int k = 0; k < K; ++k) acc = fma((double)rr[k], ws[k * RP + p], acc);
+            buf[p * rows + r0 + row] = acc;
         }
     }
     __syncthreads();
@@ -837,6 +966,45 @@ __device__ void core_slice(const Prob& P, const T* __restrict__ R, const double*
     for (int e = tid; e < tot; e += kThreads) Tbuf[(int64_t)a * tot + e] = cur[e];
 }
 
+// G = sum_a W_0[a]^T T[a] (the last contraction of the core), one
+// workgroup, T staged through LDS (tb, wb: kCoreLds / 2 doubles each).
+template <int RP>
+__device__ void core_finish(const Prob& P, const double* __restrict__ W,
+                            const double* __restrict__ Tbuf, double* __restrict__ Gd,
+                            double* tb, double* wb) {
+    const int s0 = P.s[0], r0 = P.r[0];
+    const int tot = P.core / r0;
+    const int A = max(1, min((kCoreLds / 2) / tot, (kCoreLds / 2) / RP));
+    constexpr int JM = kMaxCore / kThreads;
+    double acc[JM];
+#pragma unroll
+    for (int j = 0; j < JM; ++j) acc[j] = 0.0;
+    for (int a0 = 0; a0 < s0; a0 += A) {
+        const int na = min(A, s0 - a0);
+        __syncthreads();
+        for (int e = threadIdx.x; e < na * tot; e += kThreads)
+            tb[e] = Tbuf[(int64_t)a0 * tot + e];
+        for (int e = threadIdx.x; e < na * RP; e += kThreads)
+            wb[e] = W[P.woff[0] + (int64_t)a0 * RP + e];
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < JM; ++j) {
+            const int o = threadIdx.x + j * kThreads;
+            if (o < P.core) {
+                const int p = o / tot, rest = o % tot;
+                double v = acc[j];
+                for (int a = 0; a < na; ++a) v = fma(wb[a * RP + p], tb[a * tot + rest], v);
+                acc[j] = v;
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < JM; ++j) {
+        const int o = threadIdx.x + j * kThreads;
+        if (o < P.core) Gd[o] = acc[j];
+    }
+}
+
 template <typename T, int RP>
 __global__ __launch_bounds__(kThreads) void k_zcore(Prob P, const T* __restrict__ C,
                                                     const double* __restrict__ Y,
@@ -848,18 +1016,18 @@ __global__ __launch_bounds__(kThreads) void k_zcore(Prob P, const T* __restrict_
     if (stopped(st)) return;
     __shared__ double sh[kMaxS * RP];
     __shared__ double buf[kCoreLds];
+    __shared__ T rs[kSliceLds];
     if ((int)blockIdx.x < nz) {
         zmat_tile<T, RP>(P, C, Y, Zbuf, ztiles[blockIdx.x], sh);
         return;
     }
-    core_slice<T, RP>(P, C + P.blk[0].off, W, Tbuf, (int)blockIdx.x - nz, buf, sh);
+    core_slice<T, RP>(P, C + P.blk[0].off, W, Tbuf, (int)blockIdx.x - nz, buf, sh, rs);
 }
 
 // -------------------------------------------------------- B_i = C_i Z_i
 // B_i (d_i x RP) = C_i V_i S_i^-1 = C_i Z_i.  Work item = (mode, 16 rows,
 // 1024 columns): Z_i's chunk is staged in LDS, each wave owns 4 rows and its
-// lanes stride the columns; partial rows go to bpart and k_bred adds the
-// column chunks in order.
+// lanes stride the columns; k_bred adds the chunks' partial rows in order.
 constexpr int kBfacKC = 1024;
 
 template <typename T, int RP>
@@ -933,62 +1101,22 @@ __global__ __launch_bounds__(kThreads) void k_bfac(Prob P, const T* __restrict__
     }
 }
 
-// G = sum_a W_0[a]^T T[a] (the last contraction of the core), one
-// workgroup, T staged through LDS in slices of whole a-rows.
-template <int RP>
-__device__ void core_finish(const Prob& P, const double* __restrict__ W,
-                            const double* __restrict__ Tbuf, double* __restrict__ Gd) {
-    __shared__ double tb[kCoreLds / 2];
-    __shared__ double wb[kCoreLds / 2];
-    const int s0 = P.s[0], r0 = P.r[0];
-    const int tot = P.core / r0;
-    const int A = max(1, min((kCoreLds / 2) / tot, (kCoreLds / 2) / RP));
-    constexpr int JM = kMaxCore / kThreads;
-    double acc[JM];
-#pragma unroll
-    for (int j = 0; j < JM; ++j) acc[j] = 0.0;
-    for (int a0 = 0; a0 < s0; a0 += A) {
-        const int na = min(A, s0 - a0);
-        __syncthreads();
-        for (int e = threadIdx.x; e < na * tot; e += kThreads)
-            tb[e] = Tbuf[(int64_t)a0 * tot + e];
-        for (int e = threadIdx.x; e < na * RP; e += kThreads)
-            wb[e] = W[P.woff[0] + (int64_t)a0 * RP + e];
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < JM; ++j) {
-            const int o = threadIdx.x + j * kThreads;
-            if (o < P.core) {
-                const int p = o / tot, rest = o % tot;
-                double v = acc[j];
-                for (int a = 0; a < na; ++a) v = fma(wb[a * RP + p], tb[a * tot + rest], v);
-                acc[j] = v;
-            }
-        }
-    }
-#pragma unroll
-    for (int j = 0; j < JM; ++j) {
-        const int o = threadIdx.x + j * kThreads;
-        if (o < P.core) Gd[o] = acc[j];
-    }
-}
-
-// B_i rows: sum of the column-chunk partials of k_bfac, in chunk order; the
-// workgroup after the last one finishes the core G.
+// B_i rows: the column-chunk partials of k_bfac added in chunk order (one
+// thread per entry); the workgroup after the last one finishes the core G.
 template <typename T, int RP>
 __global__ __launch_bounds__(kThreads) void k_bred(Prob P, const double* __restrict__ bpart,
+                                                   const int4* __restrict__ items,
                                                    T* __restrict__ Bf, double* __restrict__ Bd,
                                                    int nred, const double* __restrict__ W,
                                                    const double* __restrict__ Tbuf,
-                                                   double* __restrict__ Gd,
-                                                   const DevState* st) {
+                                                   double* __restrict__ Gd, const DevState* st) {
     if (stopped(st)) return;
+    __shared__ double buf[kCoreLds];
     if ((int)blockIdx.x == nred) {
-        core_finish<RP>(P, W, Tbuf, Gd);
+        core_finish<RP>(P, W, Tbuf, Gd, buf, buf + kCoreLds / 2);
         return;
     }
     const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    // locate mode i of flat entry e over sum_i d_i * RP
     int i = 0;
     int64_t base = 0;
     while (i < P.n - 1 && e >= base + (int64_t)P.d[i] * RP) {
@@ -1000,10 +1128,16 @@ __global__ __launch_bounds__(kThreads) void k_bred(Prob P, const double* __restr
     const int rb = x / kBfacRows, xr = x % kBfacRows;
     const int nkc = P.bnkc[i];
     const double* src = bpart + ((int64_t)(P.bitem0[i] + rb * nkc) * kBfacRows + xr) * RP + p;
-    double v = 0.0;
-    for (int kc = 0; kc < nkc; ++kc) v += src[(int64_t)kc * kBfacRows * RP];
-    Bf[P.boff[i] + (int64_t)x * RP + p] = (T)v;
-    Bd[P.boff[i] + (int64_t)x * RP + p] = v;
+    double v[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) v[q] = q < nkc ? src[(int64_t)q * kBfacRows * RP] : 0.0;
+    double sum = 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+        if (q < nkc) sum += v[q];
+    for (int q = 16; q < nkc; ++q) sum += src[(int64_t)q * kBfacRows * RP];
+    Bf[P.boff[i] + (int64_t)x * RP + p] = (T)sum;
+    Bd[P.boff[i] + (int64_t)x * RP + p] = sum;
 }
 
 // ------------------------------------------------ H_b = G x_{j != mode} B_j

@@ -5,10 +5,10 @@
 // raised, so the host only checks the flag every few iterations):
 //   k_ht     fused residual, e^(k) numerator partials, hard threshold,
 //            support bits (Step I, equations 8-11)
-//   k_gram   Gram_i = U_i U_i^T tiles on the float64 matrix cores, plus the
+//   k_gram   Gram_i = U_i U_i^T on the float64 matrix cores, plus the
 //            e^(k) decision from k_ht's partials
-//   k_eig    Gram assembly, top-r_i eigenpairs -> W_i, lambda_i, Y_i
-//   k_zcore  Z_i = U_i^T Y_i (so V_i S_i^-1 = Z_i) and, per slice a of R,
+//   k_eig    top-r_i eigenspace of Gram_i -> W_i, Y_i
+//   k_zcore  Z_i = U_i^T Y_i (so V_i S_i^-1 = Z_i) and the core slices
 //            T[a] = R(a, ..) x_{l >= 1} W_l^T
 //   k_bfac   B_i = C_i Z_i partials over column chunks
 //   k_bred   B_i from the partials; the core G = sum_a W_0[a]^T T[a]
@@ -75,21 +75,21 @@ struct Impl {
     void* scratch = nullptr;        // getters / reconstruct temporaries
     size_t scratch_bytes = 0;
     DevState* st_host = nullptr;    // pinned mirror of the device state
-    int max_dyn_lds = 65536;
+    int max_dyn_lds[3] = {0, 0, 0};  // k_eig<4>, <8>, <16>: room for the Gram
 
     // layout of the current solve
     Prob P{};
     int64_t nblk_elems = 0;
     int64_t h_elems = 0, mask_words = 0, bf_elems = 0, w_elems = 0, z_elems = 0,
-            g_elems = 0, l_elems = 0, t_elems = 0;
+            g_elems = 0, t_elems = 0;
     std::vector<int4> ht_tiles, gram_items, bfac_items;
     std::vector<int2> z_tiles, h_tiles;
-    int n_bred_wg = 0;
+    int n_pairs = 0, n_bgroups = 0, n_bred_wg = 0;
 
     // device regions (inside the arena)
     void *XO = nullptr, *C[2] = {nullptr, nullptr}, *Bf = nullptr, *H = nullptr;
     uint64_t* mask[2] = {nullptr, nullptr};
-    double *W = nullptr, *Y = nullptr, *lam = nullptr, *Z = nullptr, *gram = nullptr,
+    double *W = nullptr, *Y = nullptr, *Z = nullptr, *gram = nullptr,
            *gpart = nullptr, *bpart = nullptr, *Bd = nullptr, *Gd = nullptr, *Tc = nullptr,
            *part = nullptr, *hpart = nullptr, *err_hist = nullptr;
     DevState* st = nullptr;
@@ -194,7 +194,7 @@ static void pack_indices(const Shape& sh, const SampleHost& smp, IdxPack& pk) {
 
 // Region offsets of one solve's arena.
 struct Regions {
-    size_t XO, C0, C1, m0, m1, Bf, H, W, Y, lam, Z, gram, gpart, bpart, Bd, Gd, Tc, part,
+    size_t XO, C0, C1, m0, m1, Bf, H, W, Y, Z, gram, gpart, bpart, Bd, Gd, Tc, part,
         hpart, hist, st, tiles, idx;
 };
 
@@ -252,7 +252,7 @@ static void plan(Impl& im, const Shape& sh, int esize, size_t idx_bytes, int max
     im.nblk_elems = off;
     im.h_elems = hoff;
     im.mask_words = moff;
-    im.bf_elems = im.w_elems = im.z_elems = im.g_elems = im.l_elems = 0;
+    im.bf_elems = im.w_elems = im.z_elems = im.g_elems = 0;
     for (int i = 0; i < n; ++i) {
         P.boff[i] = im.bf_elems;
         im.bf_elems += (int64_t)sh.d[i] * RP;
@@ -262,35 +262,43 @@ static void plan(Impl& im, const Shape& sh, int esize, size_t idx_bytes, int max
         im.g_elems += sh.s[i] * sh.s[i];
         P.zoff[i] = im.z_elems;
         im.z_elems += (int64_t)RP * sh.m[i];
-        P.loff[i] = im.l_elems;
-        im.l_elems += RP;
     }
     // Gram work: upper-triangular 16x16 tile pairs x column chunks
     im.gram_items.clear();
+    int npairs_all = 0;
+    for (int i = 0; i < n; ++i) {
+        const int nt = (int)((sh.s[i] + 15) / 16);
+        npairs_all += nt * (nt + 1) / 2;
+    }
+    int pid = 0;
     for (int i = 0; i < n; ++i) {
         const int nt = (int)((sh.s[i] + 15) / 16);
         int nkc = (int)std::min<int64_t>(kGramMaxKC, (sh.m[i] + kGramMinChunk - 1) / kGramMinChunk);
-        nkc = std::max(nkc, 1);
-        int chunk = (int)align_up((size_t)((sh.m[i] + nkc - 1) / nkc), 256);
+        nkc = std::max(1, nkc);
+        const int chunk = (int)align_up((size_t)((sh.m[i] + nkc - 1) / nkc), 256);
         P.gitem0[i] = (int)im.gram_items.size();
         P.gnkc[i] = nkc;
         P.gchunk[i] = chunk;
         for (int ta = 0; ta < nt; ++ta)
-            for (int tb = ta; tb < nt; ++tb)
+            for (int tb = ta; tb < nt; ++tb, ++pid)
                 for (int kc = 0; kc < nkc; ++kc)
-                    im.gram_items.push_back(make_int4(i, ta | (tb << 16), kc, 0));
+                    im.gram_items.push_back(make_int4(i, ta | (tb << 16), kc, pid));
     }
+    im.n_pairs = pid;
+    (void)npairs_all;
     // Z_i: 64 columns per work item; B_i: 16 rows x column chunks
     im.z_tiles.clear();
     im.bfac_items.clear();
+    im.n_bgroups = 0;
     const int bkc = RP <= 8 ? kBfacKC : kBfacKC / 2;
     for (int i = 0; i < n; ++i) {
         for (int64_t c0 = 0; c0 < sh.m[i]; c0 += 64) im.z_tiles.push_back(make_int2(i, (int)c0));
         const int nkc = (int)((sh.m[i] + bkc - 1) / bkc);
         P.bitem0[i] = (int)im.bfac_items.size();
         P.bnkc[i] = nkc;
-        for (int rb = 0; rb * kBfacRows < sh.d[i]; ++rb)
-            for (int kc = 0; kc < nkc; ++kc) im.bfac_items.push_back(make_int4(i, rb, kc, 0));
+        for (int rb = 0; rb * kBfacRows < sh.d[i]; ++rb, ++im.n_bgroups)
+            for (int kc = 0; kc < nkc; ++kc)
+                im.bfac_items.push_back(make_int4(i, rb, kc, im.n_bgroups));
     }
     int64_t bent = 0;
     for (int i = 0; i < n; ++i) bent += sh.d[i] * RP;
@@ -312,7 +320,6 @@ static void plan(Impl& im, const Shape& sh, int esize, size_t idx_bytes, int max
     rg.H = ar.add(im.h_elems * esize);
     rg.W = ar.add(sizeof(double) * im.w_elems);
     rg.Y = ar.add(sizeof(double) * im.w_elems);
-    rg.lam = ar.add(sizeof(double) * im.l_elems);
     rg.Z = ar.add(sizeof(double) * im.z_elems);
     rg.gram = ar.add(sizeof(double) * im.g_elems);
     rg.gpart = ar.add(sizeof(double) * 256 * im.gram_items.size());
@@ -457,22 +464,16 @@ struct Runner {
                            (const double*)im.hpart, kcur, tol, im.err_hist, im.st);
         HIPCHK(hipGetLastError());
         HIPCHK(pe());
-        int smax = 0, rmax = 0;
-        for (int i = 0; i < n; ++i) {
-            smax = std::max(smax, P.s[i]);
-            rmax = std::max(rmax, P.r[i]);
-        }
-        size_t lds = sizeof(double) * (size_t)2 * smax * rmax;
-        const size_t lds_g = lds + sizeof(double) * (size_t)smax * smax;
-        int use_lds = 0;
-        if (lds_g <= (size_t)im.max_dyn_lds) {
-            lds = lds_g;
-            use_lds = 1;
-        }
+        int smax = 0;
+        for (int i = 0; i < n; ++i) smax = std::max(smax, P.s[i]);
+        const size_t lds_g = sizeof(double) * (size_t)smax * smax;
+        const int use_lds = lds_g <= (size_t)im.max_dyn_lds[RP == 4 ? 0 : RP == 8 ? 1 : 2];
+        // float64 blocks: subspace to 1e-13; float32 blocks need far less
+        const double rtol = sizeof(T) == 8 ? 1e-13 : 1e-10;
         HIPCHK(pb(PK_EIG));
-        hipLaunchKernelGGL(k_eig, dim3(n), dim3(kEigThreads), lds, s, P,
-                           (const double*)im.gpart, im.gram, im.W, im.Y, im.lam, warm, 200,
-                           1e-13, use_lds, im.st);
+        hipLaunchKernelGGL((k_eig<RP>), dim3(n), dim3(kThreads), use_lds ? lds_g : 0, s, P,
+                           (const double*)im.gpart, im.gram, im.W, im.Y, warm, 200, rtol,
+                           use_lds, im.st);
         HIPCHK(hipGetLastError());
         HIPCHK(pe());
         const int nz = (int)im.z_tiles.size();
@@ -489,8 +490,9 @@ struct Runner {
         HIPCHK(pe());
         HIPCHK(pb(PK_BRED));
         hipLaunchKernelGGL((k_bred<T, RP>), dim3(im.n_bred_wg + 1), dim3(kThreads), 0, s, P,
-                           (const double*)im.bpart, (T*)im.Bf, im.Bd, im.n_bred_wg,
-                           (const double*)im.W, (const double*)im.Tc, im.Gd, im.st);
+                           (const double*)im.bpart, im.d_bfac_items, (T*)im.Bf, im.Bd,
+                           im.n_bred_wg, (const double*)im.W, (const double*)im.Tc, im.Gd,
+                           im.st);
         HIPCHK(hipGetLastError());
         HIPCHK(pe());
         return hexp();
@@ -716,7 +718,6 @@ static int prepare(rtcur_s* h, Impl& im, const Shape& sh, int max_iter) {
     im.H = a + rg.H;
     im.W = dp(rg.W);
     im.Y = dp(rg.Y);
-    im.lam = dp(rg.lam);
     im.Z = dp(rg.Z);
     im.gram = dp(rg.gram);
     im.gpart = dp(rg.gpart);
@@ -789,15 +790,20 @@ int solve(rtcur_s* h, const void* X, int x_dtype, const Shape& sh, double zeta0,
         hipDeviceProp_t prop;
         HIPCHK(hipGetDeviceProperties(&prop, h->device));
         // k_eig keeps the Gram in dynamic LDS when it fits beside its
-        // static arrays (about 10 KB)
-        im.max_dyn_lds = (int)prop.sharedMemPerBlock - 16 * 1024;
-        if (im.max_dyn_lds > 65536 - 16 * 1024) {
-            if (hipFuncSetAttribute(reinterpret_cast<const void*>(k_eig),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    im.max_dyn_lds) != hipSuccess) {
-                (void)hipGetLastError();  // clear the sticky error
-                im.max_dyn_lds = 65536 - 16 * 1024;
-            }
+        // static arrays
+        const void* fns[3] = {reinterpret_cast<const void*>(k_eig<4>),
+                              reinterpret_cast<const void*>(k_eig<8>),
+                              reinterpret_cast<const void*>(k_eig<16>)};
+        for (int k = 0; k < 3; ++k) {
+            hipFuncAttributes fa;
+            int room = 0;
+            if (hipFuncGetAttributes(&fa, fns[k]) == hipSuccess)
+                room = (int)prop.sharedMemPerBlock - (int)fa.sharedSizeBytes - 1024;
+            if (room > 0 && hipFuncSetAttribute(fns[k], hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                room) != hipSuccess)
+                room = 0;
+            (void)hipGetLastError();  // a refused attribute leaves a sticky error
+            im.max_dyn_lds[k] = room > 0 ? room : 0;
         }
     }
     h->shape = sh;

@@ -86,6 +86,43 @@ def test_two_modes_fp64():
     compare(res, h, info, label="2-mode")
 
 
+@pytest.mark.parametrize("dims,ranks,I", [
+    # ranks 9..16 take the 16-column path; the small samples keep the Gram
+    # in LDS, the larger ones in global memory
+    ((80, 70, 60), (10, 12, 9), (40, 44, 36)),
+    ((200, 190, 180), (11, 16, 13), (150, 140, 130)),
+    # the largest sample the library takes, |I_i| = 256, with a ragged third mode
+    ((300, 260, 40), (4, 4, 3), (256, 256, 40)),
+])
+def test_wide_ranks_and_max_sample(dims, ranks, I):
+    inst = synth.tucker_plus_sparse(dims, ranks, alpha=0.2, seed=11)
+    res = oracle_rtcur(inst.X, inst.ranks, I, None, None, 0.7, 0.0, 4, 3, "F")
+    h, info, _ = run_gpu(inst.X, inst.ranks, I, tol=0.0, max_iter=4, seed=3, check=False)
+    compare(res, h, info, label=f"{dims} r={ranks} I={I}")
+
+
+def test_shape_limits_rejected():
+    import paper_2108_10448_amd as rt
+    h = rt.create(0)
+    X = torch.zeros((40, 300, 30), dtype=torch.float64, device="cuda:0")
+    for ranks, I in [((17, 2, 2), (20, 20, 20)),      # r_i <= 16
+                     ((2, 2, 2), (20, 257, 20)),      # |I_i| <= 256
+                     ((2, 2, 16), (20, 200, 20)),     # core slice 16 * 200 > 2048
+                     ((5, 2, 2), (4, 20, 20))]:       # r_i <= |I_i|
+        with pytest.raises(rt.RTCURError) as e:
+            rt.solve(h, X, ranks, I)
+        assert e.value.status == rt.E_INVAL
+    X4 = torch.zeros((12, 12, 12, 12), dtype=torch.float64, device="cuda:0")
+    with pytest.raises(rt.RTCURError) as e:
+        rt.solve(h, X4, (9, 2, 2, 2), (10, 6, 6, 6))       # 4 modes: r_i <= 8
+    assert e.value.status == rt.E_INVAL
+    # the handle still solves a valid problem afterwards
+    inst = synth.tucker_plus_sparse((16, 16, 16), (2, 2, 2), alpha=0.1, seed=2)
+    info = rt.solve(h, torch.from_numpy(inst.X).cuda(), (2, 2, 2), (8, 8, 8), check=False)
+    assert info.status in (rt.OK, rt.NOT_CONVERGED)
+    rt.destroy(h)
+
+
 def test_full_sampling_and_given_zeta0():
     inst = synth.tucker_plus_sparse((20, 18, 16), (2, 2, 2), alpha=0.1, seed=6)
     res = oracle_rtcur(inst.X, inst.ranks, inst.dims, None, 3.0, 0.8, 0.0, 7, 1, "F")
