@@ -64,6 +64,9 @@ def lib() -> ctypes.CDLL:
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is not built; run "
                            "`python -m paper_2108_10448_amd.build`")
+    # torch first: its HIP runtime is the one both sides must share (the
+    # library resolves libamdhip64 against what is already loaded)
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     vp, i32, i64, u64, dbl = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
                               ctypes.c_uint64, ctypes.c_double)

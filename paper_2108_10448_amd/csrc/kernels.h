@@ -369,19 +369,26 @@ __global__ __launch_bounds__(kThreads) void k_decide(Prob P, const double* part,
 
 // -------------------------------------------------------- Gram of U_i rows
 // Gram_i = U_i U_i^T, U_i = C_i(I_i, :) (the matrix whose truncated SVD gives
-// U_i^+, equation 6), in float64 on the matrix cores: one work item is a
-// 16x16 output tile (upper triangle only) over one column chunk (at least
-// 2048 columns, a quarter per wave),
-// as a chain of V_MFMA_F64_16X16X4 (lane l feeds row l%16, k-slot l/16; the
-// accumulator's register v of lane l is row 4v + l/16, column l%16).  The
-// eigensolver adds the per-chunk tiles in order.  With `decide`, one extra
-// workgroup forms e^(k) from the threshold pass's partials.
+// U_i^+, equation 6), in float64 on the matrix cores.  One work item is a
+// 16x16 output tile (upper triangle only) over one column chunk: the tile's
+// 16 + 16 rows are staged through LDS in panels of 256 columns with
+// coalesced loads (the next panel's loads in flight during this panel's
+// products), and each wave runs a chain of V_MFMA_F64_16X16X4 over its 64
+// columns of the panel (lane l feeds row l%16 at column 4q + l/16 of
+// product q; the accumulator's register v of lane l is row 4v + l/16,
+// column l%16).  The eigensolver adds the per-chunk tiles in order.  With
+// `decide`, one extra workgroup forms e^(k) from the threshold pass's
+// partials.
+constexpr int kGramPanel = 256;
+
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_gram(
     Prob P, const T* __restrict__ C, const int4* __restrict__ items, int nitems,
     double* __restrict__ gpart, int decide, const double* hpart, int kcur, double tol,
     double* err_hist, DevState* st) {
     if (stopped(st)) return;
+    constexpr int LD = kGramPanel + (sizeof(T) == 8 ? 1 : 2);  // bank-spread row stride
+    __shared__ T pan[32 * LD];
     __shared__ double sacc[4][256];
     if ((int)blockIdx.x == nitems) {
         if (decide) decide_block(P, hpart, kcur, tol, err_hist, st, &sacc[0][0]);
@@ -390,47 +397,51 @@ __global__ __launch_bounds__(kThreads) void k_gram(
     const int4 it = items[blockIdx.x];
     const int i = it.x, ta = it.y & 0xffff, tb = it.y >> 16;
     const int kc = it.z & 0xffff;
+    const bool same = ta == tb;  // diagonal tile: B rows are the A rows
     const BlockDev& bd = P.blk[1 + i];
     const int s = P.s[i], m = bd.ncols;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int ia = ta * 16 + (lane & 15), ib = tb * 16 + (lane & 15);
-    const int g = lane >> 4;
-    const bool okA = ia < s, okB = ib < s;
-    const T* rowA = C + bd.off + (int64_t)P.I[i][okA ? ia : s - 1] * m;
-    const T* rowB = C + bd.off + (int64_t)P.I[i][okB ? ib : s - 1] * m;
-    const int kw = P.gchunk[i] / 4;
-    const int kbeg = kc * P.gchunk[i] + w * kw;
-    const int kend = min(kbeg + kw, m);
-    v4d acc = {0.0, 0.0, 0.0, 0.0};
-    // 4 k-steps of 16 columns per batch (16 loads of A and 16 of B); the
-    // next batch's loads are issued before this batch's MFMAs
-    T ra[16], rb[16];
-    auto load = [&](int k0) {
+    const int g = lane >> 4, rr = lane & 15;
+    const int cb = kc * P.gchunk[i], ce = min(cb + P.gchunk[i], m);
+    // this thread loads column (panel + tid) of the tile's rows
+    const T* rowp[32];
+    bool rowok[32];
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int kk = k0 + 16 * (q >> 2) + 4 * g + (q & 3);
-            const int ks = kk < kend ? kk : kbeg;
-            ra[q] = rowA[ks];
-            rb[q] = rowB[ks];
-        }
+    for (int j = 0; j < 32; ++j) {
+        const int a = (j < 16 ? ta : tb) * 16 + (j & 15);
+        rowok[j] = a < s && (j < 16 || !same);
+        rowp[j] = C + bd.off + (int64_t)P.I[i][a < s ? a : s - 1] * m;
+    }
+    T v[32];
+    // unconditional loads at clamped addresses (a branch per load would
+    // serialise them); the mask is applied when the panel goes to LDS, so
+    // the next panel's loads stay in flight during this panel's products
+    bool vin = false;
+    auto load = [&](int p0) {
+        const int c = p0 + tid;
+        vin = c < ce;
+        const int cs = vin ? c : cb;
+#pragma unroll
+        for (int j = 0; j < 32; ++j) v[j] = rowp[j][cs];
     };
-    if (kbeg < kend) load(kbeg);
-    for (int k0 = kbeg; k0 < kend; k0 += 64) {
-        double av[16], bv[16];
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
+    const int boff = same ? 0 : 16;
+    load(cb);
+    for (int p0 = cb; p0 < ce; p0 += kGramPanel) {
+        __syncthreads();
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int kk = k0 + 16 * (q >> 2) + 4 * g + (q & 3);
-            const bool in = kk < kend;
-            av[q] = (okA && in) ? (double)ra[q] : 0.0;
-            bv[q] = (okB && in) ? (double)rb[q] : 0.0;
-        }
-        if (k0 + 64 < kend) load(k0 + 64);
+        for (int j = 0; j < 32; ++j) pan[j * LD + tid] = (vin && rowok[j]) ? v[j] : T(0);
+        __syncthreads();
+        if (p0 + kGramPanel < ce) load(p0 + kGramPanel);
+        const T* pa = pan + rr * LD + 64 * w + g;
+        const T* pb = pan + (boff + rr) * LD + 64 * w + g;
 #pragma unroll
         for (int q = 0; q < 16; ++q)
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q], bv[q], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64((double)pa[4 * q], (double)pb[4 * q], acc,
+                                                       0, 0, 0);
     }
 #pragma unroll
-    for (int v = 0; v < 4; ++v) sacc[w][(4 * v + g) * 16 + (lane & 15)] = acc[v];
+    for (int u = 0; u < 4; ++u) sacc[w][(4 * u + g) * 16 + rr] = acc[u];
     __syncthreads();
     gpart[(int64_t)blockIdx.x * 256 + tid] =
         ((sacc[0][tid] + sacc[1][tid]) + sacc[2][tid]) + sacc[3][tid];
@@ -512,7 +523,8 @@ __device__ void eig_reduce(const double (&q)[RP], const double (&z)[RP], int s, 
                 for (int u = 0; u < 8; ++u) {
                     const int bb = b + u < b1 ? b + u : b1 - 1;
                     xv[u] = x[bb * RP + p];
-                    zv[u] = b + u < b1 ? sh.zs[bb * RP + t] : 0.0;
+                    zv[u] = sh.zs[bb * RP + t];
+                    zv[u] = b + u < b1 ? zv[u] : 0.0;
                 }
 #pragma unroll
                 for (int u = 0; u < 8; ++u) acc[u & 1] = fma(xv[u], zv[u], acc[u & 1]);
@@ -547,32 +559,30 @@ __device__ void eig_reduce(const double (&q)[RP], const double (&z)[RP], int s, 
 template <int RP>
 __device__ __forceinline__ bool eig_chol(const double* M, int r, double (&R)[RP][RP],
                                          double (&dinv)[RP]) {
+    // straight-line code (selects, no branches on r) so that the LDS reads
+    // of M are not serialised
     bool ok = true;
 #pragma unroll
     for (int j = 0; j < RP; ++j) {
-        dinv[j] = 1.0;
 #pragma unroll
-        for (int q = 0; q < RP; ++q) R[j][q] = (j == q) ? 1.0 : 0.0;
+        for (int q = 0; q < RP; ++q) R[j][q] = 0.0;
     }
 #pragma unroll
     for (int j = 0; j < RP; ++j) {
-        if (j < r) {
-            double d = M[j * RP + j];
+        const bool jin = j < r;
+        double d = M[j * RP + j];
 #pragma unroll
-            for (int k = 0; k < j; ++k) d -= R[k][j] * R[k][j];
-            ok = ok && d > 0.0;
-            const double ri = rsqrt(d > 0.0 ? d : 1.0);
-            dinv[j] = ri;
-            R[j][j] = d * ri;
+        for (int k = 0; k < j; ++k) d -= R[k][j] * R[k][j];
+        ok = ok && (!jin || d > 0.0);
+        const double ri = rsqrt((jin && d > 0.0) ? d : 1.0);
+        dinv[j] = ri;
+        R[j][j] = jin ? d * ri : 1.0;
 #pragma unroll
-            for (int q = j + 1; q < RP; ++q) {
-                if (q < r) {
-                    double v = M[j * RP + q];
+        for (int q = j + 1; q < RP; ++q) {
+            double v = M[j * RP + q];
 #pragma unroll
-                    for (int k = 0; k < j; ++k) v -= R[k][j] * R[k][q];
-                    R[j][q] = v * ri;
-                }
-            }
+            for (int k = 0; k < j; ++k) v -= R[k][j] * R[k][q];
+            R[j][q] = (jin && q < r) ? v * ri : 0.0;
         }
     }
     return ok;
@@ -591,37 +601,68 @@ __device__ __forceinline__ void eig_trsm(const double (&z)[RP], const double (&R
     }
 }
 
-// z = (G Q)(a, :) with G symmetric in LDS (column a read, conflict-free),
-// rows of Q taken eight at a time so that their loads overlap.
+// z = (G Q)(a, :) with G symmetric (column a read, conflict-free in LDS).
+// The sum over the s rows of Q is split into NG = min(4, 256 / s) ranges,
+// one per group of s threads, with loads issued eight rows at a time; the
+// partial rows meet in zp (NG * s * RP doubles of LDS) and are added in
+// group order by the row's owner.
 template <int RP>
-__device__ __forceinline__ void eig_gq(const double* G, const double* qs, int s, int a, bool act,
-                                       double (&z)[RP]) {
+__device__ __forceinline__ void eig_gq(const double* G, const double* qs, double* zp, int s, int a,
+                                       bool act, double (&z)[RP]) {
+    const int NG = s <= 64 ? 4 : s <= 85 ? 3 : s <= 128 ? 2 : 1;
+    const int t = threadIdx.x;
+    const int ga = t % s, gg = t / s;
+    double acc[RP];
+#pragma unroll
+    for (int p = 0; p < RP; ++p) acc[p] = 0.0;
+    if (gg < NG) {
+        const int len = (s + NG - 1) / NG;
+        const int b0 = gg * len, b1 = min(s, b0 + len);
+        for (int b = b0; b < b1; b += 8) {
+            double g[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int bb = b + u < b1 ? b + u : b1 - 1;
+                g[u] = G[bb * s + ga];  // unconditional: a branch would serialise the loads
+                g[u] = b + u < b1 ? g[u] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int bb = b + u < b1 ? b + u : b1 - 1;
+#pragma unroll
+                for (int p = 0; p < RP; ++p) acc[p] = fma(g[u], qs[bb * RP + p], acc[p]);
+            }
+        }
+    }
+    if (NG == 1) {
+#pragma unroll
+        for (int p = 0; p < RP; ++p) z[p] = act ? acc[p] : 0.0;
+        return;
+    }
+    if (gg < NG) {
+#pragma unroll
+        for (int p = 0; p < RP; ++p) zp[(gg * s + ga) * RP + p] = acc[p];
+    }
+    __syncthreads();
 #pragma unroll
     for (int p = 0; p < RP; ++p) z[p] = 0.0;
-    if (!act) return;
-    for (int b = 0; b < s; b += 8) {
-        double g[8];
+    if (act) {
+        for (int g2 = 0; g2 < NG; ++g2) {
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int bb = b + u < s ? b + u : s - 1;
-            g[u] = b + u < s ? G[bb * s + a] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int bb = b + u < s ? b + u : s - 1;
-#pragma unroll
-            for (int p = 0; p < RP; ++p) z[p] = fma(g[u], qs[bb * RP + p], z[p]);
+            for (int p = 0; p < RP; ++p) z[p] += zp[(g2 * s + a) * RP + p];
         }
     }
 }
 
-template <int RP>
+// kLdsGram: the Gram sits in dynamic LDS (else in `gram`); a compile-time
+// choice so that its accesses compile to LDS (or global) instructions rather
+// than generic ones.
+template <int RP, bool kLdsGram>
 __global__ __launch_bounds__(kThreads) void k_eig(Prob P, const double* __restrict__ gpart,
                                                   double* __restrict__ gram,
                                                   double* __restrict__ W,
                                                   double* __restrict__ Y, int warm,
-                                                  int maxit, double rtol, int gram_in_lds,
-                                                  DevState* st) {
+                                                  int maxit, double rtol, DevState* st) {
     if (stopped(st)) return;
     extern __shared__ double Gl[];  // s x s, when it fits
     __shared__ EigShared<RP> sh;
@@ -630,7 +671,7 @@ __global__ __launch_bounds__(kThreads) void k_eig(Prob P, const double* __restri
     const int a = threadIdx.x;
     const bool act = a < s;
     double* Gg = gram + P.goff[i];
-    double* G = gram_in_lds ? Gl : Gg;
+    double* G = kLdsGram ? Gl : Gg;
     {
         // the Gram from k_gram's per-chunk tiles, chunks added in order
         const int nt = (s + 15) / 16;
@@ -638,18 +679,20 @@ __global__ __launch_bounds__(kThreads) void k_eig(Prob P, const double* __restri
         const int nkc = P.gnkc[i];
         const int total = npairs * 256;
         const double* src0 = gpart + (int64_t)P.gitem0[i] * 256;
-        for (int f0 = threadIdx.x; f0 < total; f0 += 8 * kThreads) {
-            double v[8][kGramMaxKC];
+        // up to 24 entries x kGramMaxKC partials per thread in flight at once
+        constexpr int E = 24;
+        for (int f0 = threadIdx.x; f0 < total; f0 += E * kThreads) {
+            double v[E][kGramMaxKC];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
+            for (int u = 0; u < E; ++u) {
                 const int f = f0 + u * kThreads < total ? f0 + u * kThreads : f0;
                 const double* src = src0 + (int64_t)(f >> 8) * nkc * 256 + (f & 255);
 #pragma unroll
                 for (int q = 0; q < kGramMaxKC; ++q)
-                    v[u][q] = q < nkc ? src[(int64_t)q * 256] : 0.0;
+                    v[u][q] = src[(int64_t)(q < nkc ? q : 0) * 256];  // masked in the sum
             }
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
+            for (int u = 0; u < E; ++u) {
                 const int f = f0 + u * kThreads;
                 if (f >= total) continue;
                 double sum = 0.0;
@@ -676,7 +719,9 @@ __global__ __launch_bounds__(kThreads) void k_eig(Prob P, const double* __restri
     double q[RP], z[RP];
     if (warm) {
 #pragma unroll
-        for (int p = 0; p < RP; ++p) q[p] = (act && p < r) ? Wi[a * RP + p] : 0.0;
+        for (int p = 0; p < RP; ++p) q[p] = Wi[(act ? a : 0) * RP + p];
+#pragma unroll
+        for (int p = 0; p < RP; ++p) q[p] = (act && p < r) ? q[p] : 0.0;
         __syncthreads();
     } else {
         // start block G * Omega, Omega a fixed +-1 pattern, then CholQR twice
@@ -685,7 +730,7 @@ __global__ __launch_bounds__(kThreads) void k_eig(Prob P, const double* __restri
             sh.qs[e] = p < r ? ((eig_hash(b, p) & 1u) ? 1.0 : -1.0) : 0.0;
         }
         __syncthreads();
-        eig_gq<RP>(G, sh.qs, s, a, act, z);
+        eig_gq<RP>(G, sh.qs, sh.zs, s, a, act, z);
         bool ok = true;
         for (int rep = 0; rep < 2 && ok; ++rep) {
             eig_reduce<RP>(z, z, s, r, true, sh);
@@ -714,7 +759,7 @@ __global__ __launch_bounds__(kThreads) void k_eig(Prob P, const double* __restri
             for (int p = 0; p < RP; ++p) sh.qs[a * RP + p] = q[p];
         }
         __syncthreads();
-        eig_gq<RP>(G, sh.qs, s, a, act, z);
+        eig_gq<RP>(G, sh.qs, sh.zs, s, a, act, z);
         const bool last = steps == maxit;
         eig_reduce<RP>(q, z, s, r, true, sh);
         double rn = 0.0, tn = 0.0;
@@ -891,6 +936,26 @@ __device__ void zmat_tile(const Prob& P, const T* __restrict__ C, const double* 
     }
 }
 
+// sum_k x[k * xs] * y[k * ys] over LDS operands, in a fixed order: loads
+// issued eight terms at a time, alternate terms into two accumulators.
+template <typename TX>
+__device__ __forceinline__ double lds_dot(const TX* x, int xs, const double* y, int ys, int K) {
+    double acc[2] = {0.0, 0.0};
+    for (int k = 0; k < K; k += 8) {
+        double xv[8], yv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int kk = k + u < K ? k + u : K - 1;
+            xv[u] = (double)x[kk * xs];
+            yv[u] = y[kk * ys];
+            xv[u] = k + u < K ? xv[u] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc[u & 1] = fma(xv[u], yv[u], acc[u & 1]);
+    }
+    return acc[0] + acc[1];
+}
+
 constexpr int kCoreLds = 4096;  // doubles of LDS for one slice's partial core
 constexpr int kSliceLds = 4096; // elements of R staged per pass
 
@@ -930,10 +995,7 @@ __device__ void core_slice(const Prob& P, const T* __restrict__ R, const double*
         __syncthreads();
         for (int o = tid; o < rq * nr; o += kThreads) {
             const int p = o / nr, row = o % nr;
-            const T* rr = rs + row * K;
-            double acc = 0.0;
-            for (int k = 0; k < K; ++k) acc = fma((double)rr[k], ws[k * RP + p], acc);
-            buf[p * rows + r0 + row] = acc;
+            buf[p * rows + r0 + row] = lds_dot<T>(rs + row * K, 1, ws + p, RP, K);
         }
     }
     __syncthreads();
@@ -951,9 +1013,7 @@ __device__ void core_slice(const Prob& P, const T* __restrict__ R, const double*
         __syncthreads();
         for (int o = tid; o < rl * M; o += kThreads) {
             const int p = o / M, row = o % M;
-            double acc = 0.0;
-            for (int k = 0; k < Kl; ++k) acc = fma(cur[row * Kl + k], ws[k * RP + p], acc);
-            nxt[o] = acc;
+            nxt[o] = lds_dot<double>(cur + row * Kl, 1, ws + p, RP, Kl);
         }
         __syncthreads();
         double* t = cur;
@@ -992,9 +1052,7 @@ __device__ void core_finish(const Prob& P, const double* __restrict__ W,
             const int o = threadIdx.x + j * kThreads;
             if (o < P.core) {
                 const int p = o / tot, rest = o % tot;
-                double v = acc[j];
-                for (int a = 0; a < na; ++a) v = fma(wb[a * RP + p], tb[a * tot + rest], v);
-                acc[j] = v;
+                acc[j] += lds_dot<double>(wb + p, RP, tb + rest, tot, na);
             }
         }
     }
@@ -1130,7 +1188,7 @@ __global__ __launch_bounds__(kThreads) void k_bred(Prob P, const double* __restr
     const double* src = bpart + ((int64_t)(P.bitem0[i] + rb * nkc) * kBfacRows + xr) * RP + p;
     double v[16];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) v[q] = q < nkc ? src[(int64_t)q * kBfacRows * RP] : 0.0;
+    for (int q = 0; q < 16; ++q) v[q] = src[(int64_t)(q < nkc ? q : 0) * kBfacRows * RP];
     double sum = 0.0;
 #pragma unroll
     for (int q = 0; q < 16; ++q)
@@ -1180,7 +1238,8 @@ __global__ __launch_bounds__(kThreads) void k_hexp(
             ok = ok && idx[q] < P.r[others[q]];
             off += idx[q] * gstr[others[q]];
         }
-        gp[e] = ok ? Gd[off] : 0.0;
+        const double gv = Gd[ok ? off : 0];
+        gp[e] = ok ? gv : 0.0;
     }
     const int tid = threadIdx.x;
     const int64_t c = (int64_t)tl.y * kThreads + tid;

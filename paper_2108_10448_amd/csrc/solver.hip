@@ -75,7 +75,7 @@ struct Impl {
     void* scratch = nullptr;        // getters / reconstruct temporaries
     size_t scratch_bytes = 0;
     DevState* st_host = nullptr;    // pinned mirror of the device state
-    int max_dyn_lds[3] = {0, 0, 0};  // k_eig<4>, <8>, <16>: room for the Gram
+    int max_dyn_lds[3] = {0, 0, 0};  // k_eig<4|8|16, true>: room for the Gram
 
     // layout of the current solve
     Prob P{};
@@ -471,9 +471,14 @@ struct Runner {
         // float64 blocks: subspace to 1e-13; float32 blocks need far less
         const double rtol = sizeof(T) == 8 ? 1e-13 : 1e-10;
         HIPCHK(pb(PK_EIG));
-        hipLaunchKernelGGL((k_eig<RP>), dim3(n), dim3(kThreads), use_lds ? lds_g : 0, s, P,
-                           (const double*)im.gpart, im.gram, im.W, im.Y, warm, 200, rtol,
-                           use_lds, im.st);
+        if (use_lds)
+            hipLaunchKernelGGL((k_eig<RP, true>), dim3(n), dim3(kThreads), lds_g, s, P,
+                               (const double*)im.gpart, im.gram, im.W, im.Y, warm, 200, rtol,
+                               im.st);
+        else
+            hipLaunchKernelGGL((k_eig<RP, false>), dim3(n), dim3(kThreads), 0, s, P,
+                               (const double*)im.gpart, im.gram, im.W, im.Y, warm, 200, rtol,
+                               im.st);
         HIPCHK(hipGetLastError());
         HIPCHK(pe());
         const int nz = (int)im.z_tiles.size();
@@ -791,9 +796,9 @@ int solve(rtcur_s* h, const void* X, int x_dtype, const Shape& sh, double zeta0,
         HIPCHK(hipGetDeviceProperties(&prop, h->device));
         // k_eig keeps the Gram in dynamic LDS when it fits beside its
         // static arrays
-        const void* fns[3] = {reinterpret_cast<const void*>(k_eig<4>),
-                              reinterpret_cast<const void*>(k_eig<8>),
-                              reinterpret_cast<const void*>(k_eig<16>)};
+        const void* fns[3] = {reinterpret_cast<const void*>(k_eig<4, true>),
+                              reinterpret_cast<const void*>(k_eig<8, true>),
+                              reinterpret_cast<const void*>(k_eig<16, true>)};
         for (int k = 0; k < 3; ++k) {
             hipFuncAttributes fa;
             int room = 0;
