@@ -144,13 +144,16 @@ int rtcur_sample(uint64_t seed, int64_t t, int32_t n, const int64_t* dims,
                  const int64_t* I_sizes, const int64_t* J_sizes, int32_t mode,
                  int32_t which, int64_t* out, int64_t cap, int64_t* len);
 
-/* Kernel timing for diagnostics and roofline figures.  With enable = 1 the
+/* Kernel timing for diagnostics and roofline figures.  With mask != 0 the
  * following solves record a pair of HIP events on the handle's stream around
- * every kernel launch; only launches that did work (not those skipped after
- * the stop flag was raised) are accumulated.  Timing adds a few microseconds
- * per launch, so time throughput with profiling off.  enable = 0 stops
- * recording; the totals persist until the next enable = 1. */
-int rtcur_set_profiling(rtcur_t h, int32_t enable);
+ * every launch of the selected kernel kinds (bit k selects kind k, as
+ * numbered by rtcur_get_profile; a negative mask selects all of them); only
+ * launches that did work (not those skipped after the stop flag was raised)
+ * are accumulated.  Each event pair makes its launch wait for the one
+ * before, which costs a few microseconds, so time throughput with few kinds
+ * (or none) selected.  mask = 0 stops recording; the totals persist until
+ * recording is next switched on from off. */
+int rtcur_set_profiling(rtcur_t h, int32_t mask);
 
 /* Totals for kernel kind `kind` (0 .. count-1): its name (NUL-terminated,
  * truncated to name_cap), summed event time in ms and launch count.

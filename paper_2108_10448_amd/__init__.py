@@ -304,9 +304,22 @@ def get_tucker(h: Handle):
     return core, Bs
 
 
-def set_profiling(h: Handle, enable: bool) -> None:
-    """rtcur_set_profiling: HIP-event timing of every kernel launch."""
-    rc = lib().rtcur_set_profiling(h.ptr, 1 if enable else 0)
+PROFILE_KINDS = ("absmax", "gather", "ht", "gram", "eig", "zcore", "bfac", "bred", "hexp",
+                 "decide")
+
+
+def set_profiling(h: Handle, enable: bool, kinds=None) -> None:
+    """rtcur_set_profiling: HIP-event timing of the launches of `kinds`
+    (names from PROFILE_KINDS; None: every kernel)."""
+    if not enable:
+        mask = 0
+    elif kinds is None:
+        mask = -1
+    else:
+        mask = 0
+        for k in kinds:
+            mask |= 1 << PROFILE_KINDS.index(k)
+    rc = lib().rtcur_set_profiling(h.ptr, mask)
     if rc != OK:
         raise RTCURError(rc, h.last_error())
 

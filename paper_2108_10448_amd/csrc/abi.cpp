@@ -228,15 +228,17 @@ int rtcur_sample(uint64_t seed, int64_t t, int32_t n, const int64_t* dims,
     return RTCUR_OK;
 }
 
-int rtcur_set_profiling(rtcur_t h, int32_t enable) {
+int rtcur_set_profiling(rtcur_t h, int32_t mask) {
     if (!h) return RTCUR_E_INVAL;
-    if (enable && !h->profiling) {
+    const uint32_t all = (1u << rtcur::kProfKinds) - 1u;
+    const uint32_t m = mask < 0 ? all : ((uint32_t)mask & all);
+    if (m && !h->prof_mask) {
         for (int k = 0; k < rtcur::kProfKinds; ++k) {
             h->prof_ms[k] = 0.0;
             h->prof_count[k] = 0;
         }
     }
-    h->profiling = enable != 0;
+    h->prof_mask = m;
     return RTCUR_OK;
 }
 

@@ -123,7 +123,7 @@ struct rtcur_s {
     std::vector<rtcur::DevBuf> bufs;
     void* impl = nullptr;      // solver-private state (see solver.hip)
     // kernel timing (rtcur_set_profiling)
-    bool profiling = false;
+    uint32_t prof_mask = 0;   // bit k: time kernel kind k
     double prof_ms[16] = {};
     int64_t prof_count[16] = {};
 };

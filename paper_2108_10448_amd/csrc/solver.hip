@@ -350,7 +350,8 @@ struct Runner {
 
     // Event pair around one launch when profiling is on.
     hipError_t pb(int kind) {
-        if (!h->profiling) return hipSuccess;
+        open = -1;
+        if (!(h->prof_mask & (1u << kind))) return hipSuccess;
         if (im.ev_used + 2 > im.events.size()) {
             for (int q = 0; q < 64; ++q) {
                 hipEvent_t e;
@@ -365,7 +366,7 @@ struct Runner {
         return hipEventRecord(im.events[a], s);
     }
     hipError_t pe() {
-        if (!h->profiling || open < 0) return hipSuccess;
+        if (open < 0) return hipSuccess;
         const int b = im.recs[open].b;
         open = -1;
         return hipEventRecord(im.events[b], s);
@@ -373,7 +374,7 @@ struct Runner {
     // Accumulate the launches that did work: iteration tags up to K, and up
     // to K + 1 for the kernels whose pass at K + 1 decides the stop.
     int prof_collect(int K) {
-        if (!h->profiling) return 0;
+        if (im.recs.empty()) return 0;
         HIPCHK(hipStreamSynchronize(s));
         for (const ProfRec& r : im.recs) {
             const bool deciding = r.kind == PK_HT || r.kind == PK_GRAM || r.kind == PK_DECIDE;
