@@ -10,12 +10,12 @@
  *   - Omega: index sets I_i (rows of mode i, |I_i| = s_i) and J_i (columns of
  *     the mode-i unfolding, |J_i| = m_i).  The sampled blocks are the core
  *     subtensor R = X(I_1, ..., I_n) and the fiber blocks C_i = X_(i)(:, J_i).
- *   - Step (I), equations 8-10: S = HT_zeta(X - L) on the blocks, with
- *     zeta_{k+1} = gamma * zeta_k (equation 9) and HT keeping |x| > zeta.
- *   - Step (II), equations 5-6: L = R x_i (C_i U_i^+) with U_i = C_i(I_i, :)
+ *   - Step (I), equations 11-13: S = HT_zeta(X - L) on the blocks, with
+ *     zeta_{k+1} = gamma * zeta_k (equation 12) and HT keeping |x| > zeta.
+ *   - Step (II), equations 8-9: L = R x_i (C_i U_i^+) with U_i = C_i(I_i, :)
  *     truncated to rank r_i; only the factors are kept (Section 3.3).
  *   - Stop when e^(k) <= tol, e^(k) the sampled relative error of
- *     equation 11.
+ *     equation 14.
  *   - RTCUR-F keeps one sample; RTCUR-R draws a new one before every iteration
  *     after the first (Section 3.4).
  *
@@ -64,7 +64,7 @@ enum rtcur_block_what { RTCUR_BLOCK_X = 0, RTCUR_BLOCK_C = 1, RTCUR_BLOCK_L = 2,
 typedef struct {
     int32_t iters;       /* number of L-updates done (k)                      */
     int32_t converged;   /* 1 if e^(k) <= tol                                 */
-    double err;          /* e^(k), equation 11, of the returned iterate       */
+    double err;          /* e^(k), equation 14, of the returned iterate       */
     double zeta;         /* zeta_k, the last threshold used                   */
     double zeta0;        /* zeta_0 used (given, or max|X|)                    */
     int32_t eig_steps;   /* total subspace-iteration steps of the eigensolver */
@@ -87,8 +87,8 @@ int rtcur_create(rtcur_t* out, int device, void* hip_stream, int variant,
  *   J_sizes    NULL: chidori sampling, J_i = product of I_j (j != i);
  *              else m_i = |J_i| fiber columns, r_i <= m_i <= prod_{j!=i} d_j
  *   zeta0      initial threshold; <= 0 means max|X| over the whole tensor
- *   gamma      threshold decay, 0 < gamma < 1 (equation 9)
- *   tol        target e^(k) (equation 11), >= 0; stop when e^(k) <= tol
+ *   gamma      threshold decay, 0 < gamma < 1 (equation 12)
+ *   tol        target e^(k) (equation 14), >= 0; stop when e^(k) <= tol
  *   max_iter   >= 1 L-updates at most; RTCUR_NOT_CONVERGED if reached
  *   seed       sampler seed; samples are a pure function of (seed, t, dims,
  *              sizes), identical to the oracle's

@@ -1,5 +1,5 @@
 """Oracle RTCUR: Algorithm 1 with the L-update of Section 3.1, the partial
-S-update of Section 3.3 (equation 10), the sampled stopping rule (equation 11)
+S-update of Section 3.3 (equation 13), the sampled stopping rule (equation 14)
 and both variants of Section 3.4.  Plain numpy, float64 throughout.
 
 TEST INFRASTRUCTURE ONLY.  Only tests/, the smoke check and the benchmark's
@@ -7,19 +7,19 @@ CPU-baseline leg may import this module; the HIP library never does, and the
 two share no code.
 
 The oracle deliberately uses the literal form of the L-update,
-L = R x_i (C_i U_i^+) (equation 5), evaluated on the sampled blocks, and
+L = R x_i (C_i U_i^+) (equation 8), evaluated on the sampled blocks, and
 calls LAPACK (numpy.linalg.svd) for the truncated SVD.
 
 Readings of the paper where it is silent (each listed in the design doc):
 
 * blocks: the sampled set is the core subtensor R (rows I_1 x ... x I_n) and
   the n fiber blocks C_i = X_(i)(:, J_i).  Each block keeps its own S and its
-  own error, even where blocks overlap (equations 10 and 11 treat them
+  own error, even where blocks overlap (equations 13 and 14 treat them
   separately);
 * threshold: zeta_{k+1} = gamma * zeta_k by repeated float64 multiplication,
   applied before the hard threshold, so the first threshold is gamma*zeta_0;
   zeta_0 <= 0 means max|X| over the whole tensor;
-* hard threshold keeps |x| > zeta strictly (equation 7);
+* hard threshold keeps |x| > zeta strictly (equation 10);
 * e^(0) = 1 (E^(0) = X on the blocks); the loop stops when e^(k) <= tol or
   after max_iter L-updates (status NOT_CONVERGED);
 * RTCUR-R draws a fresh sample before every iteration after the first
@@ -96,7 +96,7 @@ class Result:
         return [s != 0 for s in self.SB]
 
     def reconstruct(self) -> np.ndarray:
-        """Full L = R x_1 A_1 ... x_n A_n (equation 5 on the whole grid)."""
+        """Full L = R x_1 A_1 ... x_n A_n (equation 8 on the whole grid)."""
         if self.factors is None:
             return np.zeros(self.dims)
         return multi_mode_product(self.factors.R, self.factors.A)
@@ -122,8 +122,8 @@ def truncated_pinv(U: np.ndarray, r: int):
 
 
 def l_update(CB: List[np.ndarray], samp: Sample, ranks: Sequence[int]) -> Factors:
-    """Step (II) of Algorithm 1: R, C_i, U_i from X - S (equation 6), then
-    A_i = C_i U_i^+ so that L = R x_i A_i (equation 5)."""
+    """Step (II) of Algorithm 1: R, C_i, U_i from X - S (equation 9), then
+    A_i = C_i U_i^+ so that L = R x_i A_i (equation 8)."""
     n = len(samp.dims)
     R = CB[0].copy()
     f = Factors(R, [])
@@ -207,14 +207,14 @@ def rtcur(X: np.ndarray, ranks: Sequence[int], I_sizes: Sequence[int],
             den = sum(fro(b) for b in XB)
             LB = evaluate(f, samp)
         zeta = gamma * zeta
-        # Step (I): partial S-update on the blocks (equations 8 and 10)
+        # Step (I): partial S-update on the blocks (equations 11 and 13)
         SB = [hard_threshold(XB[b] - LB[b], zeta) for b in range(n + 1)]
         CB = [XB[b] - SB[b] for b in range(n + 1)]
-        # Step (II): Fiber CUR L-update (equations 5 and 6)
+        # Step (II): Fiber CUR L-update (equations 8 and 9)
         f = l_update(CB, samp, ranks)
         LB = evaluate(f, samp)
         k += 1
-        # Stopping rule (equation 11): E = X - L - S = C - L on the blocks
+        # Stopping rule (equation 14): E = X - L - S = C - L on the blocks
         e = sum(fro(CB[b] - LB[b]) for b in range(n + 1)) / den
         if not math.isfinite(e):
             raise OracleError(E_NONFINITE, "non-finite relative error")

@@ -8,7 +8,7 @@ Readings of the paper (its text only says the indices are sampled uniformly,
 Algorithm 1 and Section 4 sizes rule):
 
 * I_i is a uniformly random subset of [d_i] of size |I_i|, drawn without
-  replacement and sorted ascending (I_i is a set in Theorem 3.3).
+  replacement and sorted ascending (I_i is a set in Theorem 2.5).
 * J_i is either "chidori" (J_i is the product of the I_j, j != i, the layout
   the paper names in Section 2.2) or "fiber" (a uniformly random subset of
   the prod_{j!=i} d_j columns of the mode-i unfolding, sorted ascending).

@@ -40,7 +40,7 @@ def multi_mode_product(T: np.ndarray, mats) -> np.ndarray:
 
 
 def hard_threshold(D: np.ndarray, zeta: float) -> np.ndarray:
-    """HT_zeta (equation 7): keep an entry iff its magnitude is strictly
+    """HT_zeta (equation 10): keep an entry iff its magnitude is strictly
     greater than zeta, else zero."""
     return np.where(np.abs(D) > zeta, D, 0.0)
 

@@ -6,7 +6,7 @@
 //   H_b = (G x_{j != mode} B_j)(columns of block b), RP x ncols per block;
 //   W_i, Y_i (float64) s_i x RP; Z_i (float64) RP x m_i.
 // With these, L on any block entry (x, c) is sum_p B_mode[x][p] H_b[p][c]:
-// the Tucker form G x_i B_i of L = R x_i (C_i U_i^+) (equation 5), where
+// the Tucker form G x_i B_i of L = R x_i (C_i U_i^+) (equation 8), where
 // U_i^+ = V_i S_i^-1 W_i^T, G = R x_i W_i^T and B_i = C_i V_i S_i^-1.
 //
 // Cross-workgroup reductions never use in-kernel fences: each launch writes
@@ -179,8 +179,8 @@ __global__ __launch_bounds__(kThreads) void k_absmax_fin(const double* part, int
 }
 
 // ------------------------------------------------------------------ gather
-// X_Omega: R = X(I_1..I_n), C_i = X_(i)(:, J_i) (Algorithm 1, equation 6),
-// with per-tile squared sums for the denominator of e^(k) (equation 11).
+// X_Omega: R = X(I_1..I_n), C_i = X_(i)(:, J_i) (Algorithm 1, equation 9),
+// with per-tile squared sums for the denominator of e^(k) (equation 14).
 template <typename TX, typename T>
 __global__ __launch_bounds__(kThreads) void k_gather(
     const TX* __restrict__ X, Prob P, const int4* __restrict__ tiles,
@@ -252,11 +252,11 @@ __global__ __launch_bounds__(kThreads) void k_den(Prob P, const double* part, in
 }
 
 // ---------------------------------------------- fused residual + threshold
-// For iteration k+1 on every block entry (Section 3.3, equations 8, 10, 11):
+// For iteration k+1 on every block entry (Section 3.3, equations 11, 13, 14):
 //   L^k = sum_p B[x][p] H[p][c]              (formed on the fly, never stored)
 //   E   = C^k - L^k  -> per-tile sums of E^2 (numerator of e^(k))
 //   D   = X - L^k;  S = D if |D| > zeta_{k+1} else 0;  C^{k+1} = X - S
-// zeta_{k+1} = gamma^(k+1) zeta_0 by repeated multiplication (equation 9).
+// zeta_{k+1} = gamma^(k+1) zeta_0 by repeated multiplication (equation 12).
 template <typename T, int RP>
 __global__ __launch_bounds__(kThreads) void k_ht(
     Prob P, const int4* __restrict__ tiles, const T* __restrict__ XO,
@@ -369,7 +369,7 @@ __global__ __launch_bounds__(kThreads) void k_decide(Prob P, const double* part,
 
 // -------------------------------------------------------- Gram of U_i rows
 // Gram_i = U_i U_i^T, U_i = C_i(I_i, :) (the matrix whose truncated SVD gives
-// U_i^+, equation 6), in float64 on the matrix cores.  One work item is a
+// U_i^+, equation 9), in float64 on the matrix cores.  One work item is a
 // 16x16 output tile (upper triangle only) over one column chunk: the tile's
 // 16 + 16 rows are staged through LDS in panels of 256 columns with
 // coalesced loads (the next panel's loads in flight during this panel's

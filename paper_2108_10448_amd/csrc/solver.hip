@@ -4,7 +4,7 @@
 // the host (every kernel returns at once after the device-side stop flag is
 // raised, so the host only checks the flag every few iterations):
 //   k_ht     fused residual, e^(k) numerator partials, hard threshold,
-//            support bits (Step I, equations 8-11)
+//            support bits (Step I, equations 11-14)
 //   k_gram   Gram_i = U_i U_i^T on the float64 matrix cores, plus the
 //            e^(k) decision from k_ht's partials
 //   k_eig    top-r_i eigenspace of Gram_i -> W_i, Y_i
@@ -453,7 +453,7 @@ struct Runner {
         return 0;
     }
 
-    // Step (II): L-update from C (equations 5-6) into B_i, G, H_b.  With
+    // Step (II): L-update from C (equations 8-9) into B_i, G, H_b.  With
     // `decide`, the Gram launch also forms e^(kcur) from k_ht's partials.
     int lupdate(const T* C, int warm, int decide_flag, int kcur, double tol) {
         const Prob& P = im.P;

@@ -1,5 +1,5 @@
 """Pins for the oracle's L-update (Section 3.1) against results the
-mathematics fixes: the Fiber CUR identity (Theorem 3.3), the full-sample case
+mathematics fixes: the Fiber CUR identity (Theorem 2.5), the full-sample case
 (a truncated HOSVD projection, Remark on HOSVD), the two-mode case (matrix
 CUR, Section 2.2) and the algebra of the truncated pseudo-inverse."""
 import numpy as np
@@ -28,7 +28,7 @@ CASES = [
 
 @pytest.mark.parametrize("dims,ranks,I,J", CASES)
 def test_fiber_cur_identity_on_exact_low_rank(dims, ranks, I, J):
-    # Theorem 3.3 (ii): A = R x_i (C_i U_i^+) when rank(U_i) = r_i
+    # Theorem 2.5 (ii): A = R x_i (C_i U_i^+) when rank(U_i) = r_i
     inst = synth.tucker_plus_sparse(dims, ranks, alpha=0.0, seed=11)
     Ls = inst.L_star
     s = draw_sample(4, 0, dims, I, J)

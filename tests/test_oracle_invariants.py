@@ -1,7 +1,7 @@
 """Pins for the oracle's whole loop (Algorithm 1): a separately written
 brute-force alternating projection on tiny tensors, the threshold schedule
-(equation 9), the hard-threshold support (equations 7, 8, 10), the stopping
-rule (equation 11), the recovery criterion of the phase-transition study, and
+(equation 12), the hard-threshold support (equations 10, 11, 13), the stopping
+rule (equation 14), the recovery criterion of the phase-transition study, and
 the error paths."""
 import math
 
