@@ -111,6 +111,13 @@ __device__ __forceinline__ bool stopped(const DevState* st) {
     return *(volatile const int*)&st->stop != 0;
 }
 
+// The same flag for kernels that issue their first loads before testing it:
+// the flag's load bypasses the caches, so testing it at once would stall
+// every workgroup on that round trip.
+__device__ __forceinline__ int stop_flag(const DevState* st) {
+    return *(volatile const int*)&st->stop;
+}
+
 // --------------------------------------------------------------- set-up
 
 __global__ void k_init_state(DevState* st, double zeta0) {
@@ -264,7 +271,7 @@ __global__ __launch_bounds__(kThreads) void k_ht(
     uint64_t* __restrict__ mask, const T* __restrict__ Bf,
     const T* __restrict__ H, double gamma, int kcur, int flags,
     double* __restrict__ part, const DevState* st) {
-    if (stopped(st)) return;
+    const int sf = stop_flag(st);
     __shared__ T brow[kTileRows][RP];
     __shared__ double red[4];
     const bool haveL = flags & kHaveL, doE = flags & kDoE, doHT = flags & kDoHT;
@@ -293,6 +300,9 @@ __global__ __launch_bounds__(kThreads) void k_ht(
     if (haveL) {
 #pragma unroll
         for (int p = 0; p < RP; ++p) h[p] = H[bd.hoff + (int64_t)p * bd.ncols + cc];
+    }
+    if (sf) return;
+    if (haveL) {
         if (tid < kTileRows * RP) {
             const int x = tid / RP, p = tid % RP;
             const int xr = tl.y + (x < rows ? x : rows - 1);
@@ -372,8 +382,8 @@ __global__ __launch_bounds__(kThreads) void k_decide(Prob P, const double* part,
 // U_i^+, equation 9), in float64 on the matrix cores.  One work item is a
 // 16x16 output tile (upper triangle only) over one column chunk: the tile's
 // 16 + 16 rows are staged through LDS in panels of 256 columns with
-// coalesced loads (the next panel's loads in flight during this panel's
-// products), and each wave runs a chain of V_MFMA_F64_16X16X4 over its 64
+// coalesced loads (the loads of the panel after next in flight during this
+// panel's products), and each wave runs a chain of V_MFMA_F64_16X16X4 over its 64
 // columns of the panel (lane l feeds row l%16 at column 4q + l/16 of
 // product q; the accumulator's register v of lane l is row 4v + l/16,
 // column l%16).  The eigensolver adds the per-chunk tiles in order.  With
@@ -386,12 +396,12 @@ __global__ __launch_bounds__(kThreads) void k_gram(
     Prob P, const T* __restrict__ C, const int4* __restrict__ items, int nitems,
     double* __restrict__ gpart, int decide, const double* hpart, int kcur, double tol,
     double* err_hist, DevState* st) {
-    if (stopped(st)) return;
+    const int sf = stop_flag(st);
     constexpr int LD = kGramPanel + (sizeof(T) == 8 ? 1 : 2);  // bank-spread row stride
     __shared__ T pan[32 * LD];
     __shared__ double sacc[4][256];
     if ((int)blockIdx.x == nitems) {
-        if (decide) decide_block(P, hpart, kcur, tol, err_hist, st, &sacc[0][0]);
+        if (decide && !sf) decide_block(P, hpart, kcur, tol, err_hist, st, &sacc[0][0]);
         return;
     }
     const int4 it = items[blockIdx.x];
@@ -412,33 +422,54 @@ __global__ __launch_bounds__(kThreads) void k_gram(
         rowok[j] = a < s && (j < 16 || !same);
         rowp[j] = C + bd.off + (int64_t)P.I[i][a < s ? a : s - 1] * m;
     }
-    T v[32];
     // unconditional loads at clamped addresses (a branch per load would
-    // serialise them); the mask is applied when the panel goes to LDS, so
-    // the next panel's loads stay in flight during this panel's products
-    bool vin = false;
-    auto load = [&](int p0) {
+    // serialise them); the mask is applied when a panel goes to LDS.  Two
+    // register sets alternate, so each panel's loads have two panels of
+    // products to arrive.
+    T va[32], vb[32];
+    bool ina = false, inb = false;
+    auto load = [&](T (&vv)[32], bool& in, int p0) {
         const int c = p0 + tid;
-        vin = c < ce;
-        const int cs = vin ? c : cb;
+        in = c < ce;
+        const int cs = in ? c : cb;
 #pragma unroll
-        for (int j = 0; j < 32; ++j) v[j] = rowp[j][cs];
+        for (int j = 0; j < 32; ++j) vv[j] = rowp[j][cs];
     };
     v4d acc = {0.0, 0.0, 0.0, 0.0};
     const int boff = same ? 0 : 16;
-    load(cb);
-    for (int p0 = cb; p0 < ce; p0 += kGramPanel) {
-        __syncthreads();
+    load(va, ina, cb);
+    if (cb + kGramPanel < ce) load(vb, inb, cb + kGramPanel);
+    if (sf) return;
+    for (int p0 = cb; p0 < ce; p0 += 2 * kGramPanel) {
+        {
+            const bool in = ina;
+            __syncthreads();
 #pragma unroll
-        for (int j = 0; j < 32; ++j) pan[j * LD + tid] = (vin && rowok[j]) ? v[j] : T(0);
-        __syncthreads();
-        if (p0 + kGramPanel < ce) load(p0 + kGramPanel);
-        const T* pa = pan + rr * LD + 64 * w + g;
-        const T* pb = pan + (boff + rr) * LD + 64 * w + g;
+            for (int j = 0; j < 32; ++j) pan[j * LD + tid] = (in && rowok[j]) ? va[j] : T(0);
+            __syncthreads();
+            if (p0 + 2 * kGramPanel < ce) load(va, ina, p0 + 2 * kGramPanel);
+            const T* pa = pan + rr * LD + 64 * w + g;
+            const T* pb = pan + (boff + rr) * LD + 64 * w + g;
 #pragma unroll
-        for (int q = 0; q < 16; ++q)
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64((double)pa[4 * q], (double)pb[4 * q], acc,
-                                                       0, 0, 0);
+            for (int q = 0; q < 16; ++q)
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64((double)pa[4 * q], (double)pb[4 * q],
+                                                           acc, 0, 0, 0);
+        }
+        if (p0 + kGramPanel >= ce) break;
+        {
+            const bool in = inb;
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < 32; ++j) pan[j * LD + tid] = (in && rowok[j]) ? vb[j] : T(0);
+            __syncthreads();
+            if (p0 + 3 * kGramPanel < ce) load(vb, inb, p0 + 3 * kGramPanel);
+            const T* pa = pan + rr * LD + 64 * w + g;
+            const T* pb = pan + (boff + rr) * LD + 64 * w + g;
+#pragma unroll
+            for (int q = 0; q < 16; ++q)
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64((double)pa[4 * q], (double)pb[4 * q],
+                                                           acc, 0, 0, 0);
+        }
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) sacc[w][(4 * u + g) * 16 + rr] = acc[u];
@@ -469,85 +500,50 @@ __device__ __forceinline__ uint32_t eig_hash(uint32_t a, uint32_t b) {
 
 template <int RP>
 struct EigShared {
-    double qs[kMaxS * RP];                 // Q rows (G Q product, dot products)
-    double zs[kMaxS * RP];                 // Z rows (dot products)
+    double qs[kMaxS * RP];                 // Q rows; rows s..sp-1 stay zero
+    double zs[kMaxS * RP];                 // Z = G Q rows; rows s..sp-1 stay zero
     double tm[RP * RP], mm[RP * RP];       // T = Q^T Z, M = Z^T Z
-    double halves[2 * (RP * RP + RP * (RP + 1) / 2)];  // half-dot products
+    double part[4][256];                   // per-wave 16 x 16 MFMA partials
     double red[4];
+    int2 pairs[(kMaxS / 16) * (kMaxS / 16 + 1) / 2];  // Gram tile pair -> (ta, tb)
     int ok;
 };
 
-// T = Q^T Z and (when wantM) M = Z^T Z (upper triangle, mirrored) over the
-// workgroup into LDS.  The rows go to LDS; each output's dot product over
-// the s rows is split into two halves, each run by one thread in row order
-// with its loads issued eight rows at a time, and the halves are added.
+// T = Q^T Z (when wantT) and M = Z^T Z from the rows in LDS (sp = s rounded
+// up to 16, rows beyond s zero) on the float64 matrix cores: waves 0 and 1
+// sum T over the two halves of the rows, waves 2 and 3 sum M; lane l feeds
+// column l%16 at row 4j + l/16 of product j.  The halves are added in a
+// fixed order.
 template <int RP>
-__device__ void eig_reduce(const double (&q)[RP], const double (&z)[RP], int s, int r,
-                           bool wantM, EigShared<RP>& sh) {
-    constexpr int NT = RP * RP, NM = RP * (RP + 1) / 2, NO = NT + NM;
-    const int a = threadIdx.x;
-    __syncthreads();
-    if (a < s) {
+__device__ void eig_tm(int sp, bool wantT, EigShared<RP>& sh) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int col = lane & 15, kq = lane >> 4, cc = col < RP ? col : RP - 1;
+    const bool isM = w >= 2;
+    const int nk = sp >> 2, half = w & 1;
+    const int j0 = half ? nk / 2 : 0, j1 = half ? nk : nk / 2;
+    // two independent chains (even and odd products), added at the end
+    v4d acc[2] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
+    if (isM || wantT) {
+        for (int j = j0; j < j1; j += 2) {
 #pragma unroll
-        for (int p = 0; p < RP; ++p) {
-            sh.qs[a * RP + p] = q[p];
-            sh.zs[a * RP + p] = z[p];
+            for (int u = 0; u < 2; ++u) {
+                const int jj = j + u < j1 ? j + u : j0;
+                const int b = 4 * jj + kq;
+                double zv = sh.zs[b * RP + cc];
+                double qv = sh.qs[b * RP + cc];
+                zv = (col < RP && j + u < j1) ? zv : 0.0;
+                qv = col < RP ? qv : 0.0;
+                acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(isM ? zv : qv, zv, acc[u], 0, 0, 0);
+            }
         }
     }
-    __syncthreads();
-    for (int w = threadIdx.x; w < 2 * NO; w += kThreads) {
-        const int e = w % NO, half = w / NO;
-        const bool isM = e >= NT;
-        int p, t;
-        if (!isM) {
-            p = e / RP;
-            t = e % RP;
-        } else {
-            int k = e - NT;
-            p = 0;
-            while (k >= RP - p) {
-                k -= RP - p;
-                ++p;
-            }
-            t = p + k;
-        }
-        double v = 0.0;
-        if (p < r && t < r && (!isM || wantM)) {
-            const int hs = (s + 1) / 2;
-            const int b0 = half * hs, b1 = half ? s : hs;
-            const double* x = isM ? sh.zs : sh.qs;
-            double acc[2] = {0.0, 0.0};
-            for (int b = b0; b < b1; b += 8) {
-                double xv[8], zv[8];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const int bb = b + u < b1 ? b + u : b1 - 1;
-                    xv[u] = x[bb * RP + p];
-                    zv[u] = sh.zs[bb * RP + t];
-                    zv[u] = b + u < b1 ? zv[u] : 0.0;
-                }
-#pragma unroll
-                for (int u = 0; u < 8; ++u) acc[u & 1] = fma(xv[u], zv[u], acc[u & 1]);
-            }
-            v = acc[0] + acc[1];
-        }
-        sh.halves[w] = v;
-    }
+    for (int v = 0; v < 4; ++v) sh.part[w][(4 * v + kq) * 16 + col] = acc[0][v] + acc[1][v];
     __syncthreads();
-    for (int e = threadIdx.x; e < NO; e += kThreads) {
-        const double v = sh.halves[e] + sh.halves[NO + e];
-        if (e < NT) {
-            sh.tm[e] = v;
-        } else if (wantM) {
-            int k = e - NT, p = 0;
-            while (k >= RP - p) {
-                k -= RP - p;
-                ++p;
-            }
-            const int t = p + k;
-            sh.mm[p * RP + t] = v;
-            sh.mm[t * RP + p] = v;
-        }
+    if (threadIdx.x < RP * RP) {
+        const int p = threadIdx.x / RP, t = threadIdx.x % RP;
+        if (wantT) sh.tm[threadIdx.x] = sh.part[0][p * 16 + t] + sh.part[1][p * 16 + t];
+        sh.mm[threadIdx.x] = sh.part[2][p * 16 + t] + sh.part[3][p * 16 + t];
     }
     __syncthreads();
 }
@@ -601,57 +597,41 @@ __device__ __forceinline__ void eig_trsm(const double (&z)[RP], const double (&R
     }
 }
 
-// z = (G Q)(a, :) with G symmetric (column a read, conflict-free in LDS).
-// The sum over the s rows of Q is split into NG = min(4, 256 / s) ranges,
-// one per group of s threads, with loads issued eight rows at a time; the
-// partial rows meet in zp (NG * s * RP doubles of LDS) and are added in
-// group order by the row's owner.
+// Z = G Q into zs (rows < s, columns < RP) on the float64 matrix cores; G
+// is sp x sp with row stride sp + 1 (zero beyond s), Q's rows s..sp-1 are
+// zero.  Wave w takes the 16-row tiles w, w + 4, ...; per tile one
+// accumulator chain over the rows of Q, its LDS operands loaded four
+// products ahead: lane l feeds G row 16t + l%16 and Q column l%16 at row
+// 4j + l/16 of product j; accumulator register v of lane l is row
+// 4v + l/16, column l%16.
 template <int RP>
-__device__ __forceinline__ void eig_gq(const double* G, const double* qs, double* zp, int s, int a,
-                                       bool act, double (&z)[RP]) {
-    const int NG = s <= 64 ? 4 : s <= 85 ? 3 : s <= 128 ? 2 : 1;
-    const int t = threadIdx.x;
-    const int ga = t % s, gg = t / s;
-    double acc[RP];
+__device__ __forceinline__ void eig_gq(const double* G, int sp, int s, EigShared<RP>& sh) {
+    const int ldg = sp + 1;  // odd row stride: a tile's 16 rows fall in different banks
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int col = lane & 15, kq = lane >> 4, cc = col < RP ? col : RP - 1;
+    const int nt = sp >> 4;
+    for (int t = w; t < nt; t += 4) {
+        const double* ga = G + (int64_t)(16 * t + col) * ldg + kq;
+        v4d acc = {0.0, 0.0, 0.0, 0.0};
+        for (int j = 0; j < sp; j += 16) {  // sp is a multiple of 16
+            double av[4], bv[4];
 #pragma unroll
-    for (int p = 0; p < RP; ++p) acc[p] = 0.0;
-    if (gg < NG) {
-        const int len = (s + NG - 1) / NG;
-        const int b0 = gg * len, b1 = min(s, b0 + len);
-        for (int b = b0; b < b1; b += 8) {
-            double g[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int bb = b + u < b1 ? b + u : b1 - 1;
-                g[u] = G[bb * s + ga];  // unconditional: a branch would serialise the loads
-                g[u] = b + u < b1 ? g[u] : 0.0;
+            for (int u = 0; u < 4; ++u) {
+                av[u] = ga[j + 4 * u];
+                bv[u] = sh.qs[(j + 4 * u + kq) * RP + cc];
             }
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int bb = b + u < b1 ? b + u : b1 - 1;
-#pragma unroll
-                for (int p = 0; p < RP; ++p) acc[p] = fma(g[u], qs[bb * RP + p], acc[p]);
-            }
+            for (int u = 0; u < 4; ++u)
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], col < RP ? bv[u] : 0.0, acc,
+                                                           0, 0, 0);
         }
-    }
-    if (NG == 1) {
 #pragma unroll
-        for (int p = 0; p < RP; ++p) z[p] = act ? acc[p] : 0.0;
-        return;
-    }
-    if (gg < NG) {
-#pragma unroll
-        for (int p = 0; p < RP; ++p) zp[(gg * s + ga) * RP + p] = acc[p];
+        for (int v = 0; v < 4; ++v) {
+            const int row = 16 * t + 4 * v + kq;
+            if (row < s && col < RP) sh.zs[row * RP + col] = acc[v];
+        }
     }
     __syncthreads();
-#pragma unroll
-    for (int p = 0; p < RP; ++p) z[p] = 0.0;
-    if (act) {
-        for (int g2 = 0; g2 < NG; ++g2) {
-#pragma unroll
-            for (int p = 0; p < RP; ++p) z[p] += zp[(g2 * s + a) * RP + p];
-        }
-    }
 }
 
 // kLdsGram: the Gram sits in dynamic LDS (else in `gram`); a compile-time
@@ -663,23 +643,37 @@ __global__ __launch_bounds__(kThreads) void k_eig(Prob P, const double* __restri
                                                   double* __restrict__ W,
                                                   double* __restrict__ Y, int warm,
                                                   int maxit, double rtol, DevState* st) {
-    if (stopped(st)) return;
-    extern __shared__ double Gl[];  // s x s, when it fits
+    extern __shared__ double Gl[];  // sp x sp (row stride sp + 1), when it fits
     __shared__ EigShared<RP> sh;
     const int i = blockIdx.x;
     const int s = P.s[i], r = P.r[i];
+    const int sp = (s + 15) & ~15;
     const int a = threadIdx.x;
     const bool act = a < s;
-    double* Gg = gram + P.goff[i];
-    double* G = kLdsGram ? Gl : Gg;
+    double* G = kLdsGram ? Gl : gram + P.goff[i];
+    const int nt = sp >> 4;
+    const int npairs = nt * (nt + 1) / 2;
+    if (threadIdx.x < npairs) {
+        // pair index -> (ta, tb), ta <= tb, ta-major (the order of k_gram's items)
+        int ta = 0, rem = threadIdx.x;
+        while (rem >= nt - ta) {
+            rem -= nt - ta;
+            ++ta;
+        }
+        sh.pairs[threadIdx.x] = make_int2(ta, ta + rem);
+    }
+    // Q and Z rows s..sp-1 stay zero for the padded products
+    for (int e = s * RP + threadIdx.x; e < sp * RP; e += kThreads) {
+        sh.qs[e] = 0.0;
+        sh.zs[e] = 0.0;
+    }
+    __syncthreads();
     {
-        // the Gram from k_gram's per-chunk tiles, chunks added in order
-        const int nt = (s + 15) / 16;
-        const int npairs = nt * (nt + 1) / 2;
+        // the Gram from k_gram's per-chunk 16 x 16 tiles, chunks added in
+        // order; every load of a thread is issued before the first use
         const int nkc = P.gnkc[i];
         const int total = npairs * 256;
         const double* src0 = gpart + (int64_t)P.gitem0[i] * 256;
-        // up to 24 entries x kGramMaxKC partials per thread in flight at once
         constexpr int E = 24;
         for (int f0 = threadIdx.x; f0 < total; f0 += E * kThreads) {
             double v[E][kGramMaxKC];
@@ -691,6 +685,7 @@ __global__ __launch_bounds__(kThreads) void k_eig(Prob P, const double* __restri
                 for (int q = 0; q < kGramMaxKC; ++q)
                     v[u][q] = src[(int64_t)(q < nkc ? q : 0) * 256];  // masked in the sum
             }
+            if (f0 == (int)threadIdx.x && stopped(st)) return;  // uniform: same f0 in every thread
 #pragma unroll
             for (int u = 0; u < E; ++u) {
                 const int f = f0 + u * kThreads;
@@ -699,18 +694,12 @@ __global__ __launch_bounds__(kThreads) void k_eig(Prob P, const double* __restri
 #pragma unroll
                 for (int q = 0; q < kGramMaxKC; ++q)
                     if (q < nkc) sum += v[u][q];
-                // pair f/256 -> (ta, tb), ta <= tb, ta-major
-                int ta = 0, rem = f >> 8;
-                while (rem >= nt - ta) {
-                    rem -= nt - ta;
-                    ++ta;
-                }
-                const int tb = ta + rem, t = f & 255;
-                const int a2 = ta * 16 + (t >> 4), b2 = tb * 16 + (t & 15);
-                if (a2 < s && b2 < s) {
-                    G[a2 * s + b2] = sum;
-                    G[b2 * s + a2] = sum;
-                }
+                const int2 pr = sh.pairs[f >> 8];
+                const int t = f & 255;
+                const int a2 = pr.x * 16 + (t >> 4), b2 = pr.y * 16 + (t & 15);
+                // rows and columns beyond s come out of k_gram as zeros
+                G[a2 * (sp + 1) + b2] = sum;
+                G[b2 * (sp + 1) + a2] = sum;
             }
         }
     }
@@ -730,16 +719,23 @@ __global__ __launch_bounds__(kThreads) void k_eig(Prob P, const double* __restri
             sh.qs[e] = p < r ? ((eig_hash(b, p) & 1u) ? 1.0 : -1.0) : 0.0;
         }
         __syncthreads();
-        eig_gq<RP>(G, sh.qs, sh.zs, s, a, act, z);
+        eig_gq<RP>(G, sp, s, sh);
+#pragma unroll
+        for (int p = 0; p < RP; ++p) z[p] = act ? sh.zs[a * RP + p] : 0.0;
         bool ok = true;
         for (int rep = 0; rep < 2 && ok; ++rep) {
-            eig_reduce<RP>(z, z, s, r, true, sh);
+            eig_tm<RP>(sp, false, sh);  // M = Z^T Z
             double R[RP][RP], di[RP];
             ok = eig_chol<RP>(sh.mm, r, R, di);
             if (ok) {
                 eig_trsm<RP>(z, R, di, q);
 #pragma unroll
                 for (int p = 0; p < RP; ++p) z[p] = q[p];
+                if (rep == 0 && act) {
+#pragma unroll
+                    for (int p = 0; p < RP; ++p) sh.zs[a * RP + p] = z[p];
+                }
+                __syncthreads();
             }
         }
         if (!ok) {
@@ -759,9 +755,11 @@ __global__ __launch_bounds__(kThreads) void k_eig(Prob P, const double* __restri
             for (int p = 0; p < RP; ++p) sh.qs[a * RP + p] = q[p];
         }
         __syncthreads();
-        eig_gq<RP>(G, sh.qs, sh.zs, s, a, act, z);
+        eig_gq<RP>(G, sp, s, sh);
+#pragma unroll
+        for (int p = 0; p < RP; ++p) z[p] = act ? sh.zs[a * RP + p] : 0.0;
         const bool last = steps == maxit;
-        eig_reduce<RP>(q, z, s, r, true, sh);
+        eig_tm<RP>(sp, true, sh);  // T = Q^T Z, M = Z^T Z
         double rn = 0.0, tn = 0.0;
         {
             double Tr[RP][RP];
@@ -890,12 +888,13 @@ __global__ __launch_bounds__(kThreads) void k_eig(Prob P, const double* __restri
 // G = R x_i W_i^T before its last contraction (with W_0, done by k_hexp).
 template <typename T, int RP>
 __device__ void zmat_tile(const Prob& P, const T* __restrict__ C, const double* __restrict__ Y,
-                          double* __restrict__ Zbuf, int2 tl, double* ys) {
+                          double* __restrict__ Zbuf, int2 tl, double* ys, int sf) {
     const int i = tl.x;
     const BlockDev& bd = P.blk[1 + i];
     const int s = P.s[i], m = bd.ncols;
     const double* Yi = Y + P.woff[i];
     for (int e = threadIdx.x; e < s * RP; e += kThreads) ys[e] = Yi[e];
+    if (sf) return;
     __syncthreads();
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int quarter = lane & 3;
@@ -965,7 +964,8 @@ constexpr int kSliceLds = 4096; // elements of R staged per pass
 // (r_1, .., r_{n-1}).
 template <typename T, int RP>
 __device__ void core_slice(const Prob& P, const T* __restrict__ R, const double* __restrict__ W,
-                           double* __restrict__ Tbuf, int a, double* buf, double* ws, T* rs) {
+                           double* __restrict__ Tbuf, int a, double* buf, double* ws, T* rs,
+                           int sf) {
     const int n = P.n;
     const int tid = threadIdx.x;
     int rows = 1;
@@ -973,6 +973,7 @@ __device__ void core_slice(const Prob& P, const T* __restrict__ R, const double*
     const int K = P.s[n - 1];
     const int rq = P.r[n - 1];
     for (int e = tid; e < K * RP; e += kThreads) ws[e] = W[P.woff[n - 1] + e];
+    if (sf) return;
     const T* Ra = R + (int64_t)a * rows * K;
     const int RC = max(1, kSliceLds / K);
     for (int r0 = 0; r0 < rows; r0 += RC) {
@@ -1071,15 +1072,15 @@ __global__ __launch_bounds__(kThreads) void k_zcore(Prob P, const T* __restrict_
                                                     const double* __restrict__ W,
                                                     double* __restrict__ Tbuf,
                                                     const DevState* st) {
-    if (stopped(st)) return;
+    const int sf = stop_flag(st);
     __shared__ double sh[kMaxS * RP];
     __shared__ double buf[kCoreLds];
     __shared__ T rs[kSliceLds];
     if ((int)blockIdx.x < nz) {
-        zmat_tile<T, RP>(P, C, Y, Zbuf, ztiles[blockIdx.x], sh);
+        zmat_tile<T, RP>(P, C, Y, Zbuf, ztiles[blockIdx.x], sh, sf);
         return;
     }
-    core_slice<T, RP>(P, C + P.blk[0].off, W, Tbuf, (int)blockIdx.x - nz, buf, sh, rs);
+    core_slice<T, RP>(P, C + P.blk[0].off, W, Tbuf, (int)blockIdx.x - nz, buf, sh, rs, sf);
 }
 
 // -------------------------------------------------------- B_i = C_i Z_i
@@ -1094,7 +1095,7 @@ __global__ __launch_bounds__(kThreads) void k_bfac(Prob P, const T* __restrict__
                                                    const int4* __restrict__ items,
                                                    double* __restrict__ bpart,
                                                    const DevState* st) {
-    if (stopped(st)) return;
+    const int sf = stop_flag(st);
     constexpr int KC = RP <= 8 ? kBfacKC : kBfacKC / 2;
     __shared__ double zs[KC * RP];
     const int4 it = items[blockIdx.x];
@@ -1105,6 +1106,7 @@ __global__ __launch_bounds__(kThreads) void k_bfac(Prob P, const T* __restrict__
     const int c0 = kc * KC, cn = min(KC, m - c0);
     const double* Zc = Zbuf + P.zoff[i] + (int64_t)c0 * RP;
     for (int e = tid; e < KC * RP; e += kThreads) zs[e] = e < cn * RP ? Zc[e] : 0.0;
+    if (sf) return;
     const int xb = rb * kBfacRows + w * kBfacRowsPerWave;
     const T* rowp[kBfacRowsPerWave];
 #pragma unroll
@@ -1168,9 +1170,10 @@ __global__ __launch_bounds__(kThreads) void k_bred(Prob P, const double* __restr
                                                    int nred, const double* __restrict__ W,
                                                    const double* __restrict__ Tbuf,
                                                    double* __restrict__ Gd, const DevState* st) {
-    if (stopped(st)) return;
+    const int sf = stop_flag(st);
     __shared__ double buf[kCoreLds];
     if ((int)blockIdx.x == nred) {
+        if (sf) return;
         core_finish<RP>(P, W, Tbuf, Gd, buf, buf + kCoreLds / 2);
         return;
     }
@@ -1189,6 +1192,7 @@ __global__ __launch_bounds__(kThreads) void k_bred(Prob P, const double* __restr
     double v[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) v[q] = src[(int64_t)(q < nkc ? q : 0) * kBfacRows * RP];
+    if (sf) return;
     double sum = 0.0;
 #pragma unroll
     for (int q = 0; q < 16; ++q)
@@ -1209,7 +1213,7 @@ __global__ __launch_bounds__(kThreads) void k_hexp(
     Prob P, const int2* __restrict__ tiles, const T* __restrict__ Bf,
     const double* __restrict__ Gd, T* __restrict__ H, const DevState* st,
     int dense_mode, int64_t dense_cols) {
-    if (st && stopped(st)) return;
+    const int sf = st ? stop_flag(st) : 0;
     constexpr int GP = N == 2 ? RP * RP : (N == 3 ? RP * RP * RP : RP * RP * RP * RP);
     __shared__ double gp[GP];
     __shared__ double vs[(N - 1) * RP * kThreads];
@@ -1264,6 +1268,7 @@ __global__ __launch_bounds__(kThreads) void k_hexp(
         for (int q = 0; q < N - 1; ++q)
 #pragma unroll
             for (int k = 0; k < RP; ++k) bv[q][k] = Bf[rowoff[q] + k];
+        if (sf) return;
 #pragma unroll
         for (int q = 0; q < N - 1; ++q)
 #pragma unroll

@@ -259,7 +259,9 @@ static void plan(Impl& im, const Shape& sh, int esize, size_t idx_bytes, int max
         P.woff[i] = im.w_elems;
         im.w_elems += sh.s[i] * RP;
         P.goff[i] = im.g_elems;
-        im.g_elems += sh.s[i] * sh.s[i];
+        // Gram padded to whole 16 x 16 tiles, row stride sp + 1
+        const int64_t sp = (sh.s[i] + 15) / 16 * 16;
+        im.g_elems += sp * (sp + 1);
         P.zoff[i] = im.z_elems;
         im.z_elems += (int64_t)RP * sh.m[i];
     }
@@ -466,8 +468,8 @@ struct Runner {
         HIPCHK(hipGetLastError());
         HIPCHK(pe());
         int smax = 0;
-        for (int i = 0; i < n; ++i) smax = std::max(smax, P.s[i]);
-        const size_t lds_g = sizeof(double) * (size_t)smax * smax;
+        for (int i = 0; i < n; ++i) smax = std::max(smax, (P.s[i] + 15) / 16 * 16);
+        const size_t lds_g = sizeof(double) * (size_t)smax * (smax + 1);
         const int use_lds = lds_g <= (size_t)im.max_dyn_lds[RP == 4 ? 0 : RP == 8 ? 1 : 2];
         // float64 blocks: subspace to 1e-13; float32 blocks need far less
         const double rtol = sizeof(T) == 8 ? 1e-13 : 1e-10;
