@@ -295,6 +295,25 @@ def main():
     true_err = float(torch.linalg.norm(Lrec.double() - Ls) / torch.linalg.norm(Ls))
     del Lrec, Ls
 
+    # full-grid outliers fused with the reconstruction (one read of X, one
+    # write of S): time a few calls after the solve
+    rt.outliers(h, X)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    nout = 5
+    for _ in range(nout):
+        S = rt.outliers(h, X)
+    torch.cuda.synchronize()
+    t_out = (time.perf_counter() - t0) / nout
+    planted = torch.from_numpy(inst.S_star != 0).to("cuda:0")
+    found = S != 0
+    outlier_row = {"ms": 1e3 * t_out,
+                   "hbm_GBps": 2 * X.numel() * X.element_size() / t_out / 1e9,
+                   "support_recall": float((found & planted).sum() / planted.sum()),
+                   "support_precision": float((found & planted).sum() / max(1, int(found.sum())))}
+    del S, planted, found
+    log(f"outliers: {outlier_row}")
+
     rows = {}
 
     def side(variant, dtype, name):
@@ -404,6 +423,7 @@ def main():
         "true_rel_err": true_err,
         "eig_steps_per_solve": eig_steps,
         "variants": rows,
+        "outliers_full_grid": outlier_row,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernels": kernels,

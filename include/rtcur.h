@@ -108,6 +108,23 @@ int rtcur_solve(rtcur_t h, const void* X, int x_dtype, int32_t n,
  * RTCUR_E_STATE if no successful solve precedes it. */
 int rtcur_reconstruct(rtcur_t h, void* L_out, int out_dtype);
 
+/* Full-grid outliers (the S-update of equation 11, S = HT_zeta(X - L) with
+ * the strict threshold of equation 10, applied to every entry of X rather
+ * than only to the sampled blocks), fused with the reconstruction of L:
+ *   X       device, C-contiguous, prod(dims) elements of x_dtype
+ *           (RTCUR_F64/F32), the dims of the last solve; read-only.
+ *   zeta    threshold; <= 0 means the threshold of the returned iterate,
+ *           zeta_K (zeta_0 when the solve did no iteration).
+ *   S_out   caller's device buffer, prod(dims) elements of out_dtype:
+ *           X - L where |X - L| > zeta, else 0 (X - L formed in the solve's
+ *           compute type).
+ *   L_out   NULL, or a caller's device buffer receiving L as
+ *           rtcur_reconstruct would (out_dtype).
+ * One read of X and one write per output; blocks until done.
+ * RTCUR_E_STATE if no successful solve precedes it. */
+int rtcur_outliers(rtcur_t h, const void* X, int x_dtype, double zeta, void* S_out,
+                   void* L_out, int out_dtype);
+
 /* Release the handle and its device workspace.  NULL-safe. */
 int rtcur_destroy(rtcur_t h);
 

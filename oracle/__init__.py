@@ -7,7 +7,7 @@ with the HIP library under ``paper_2108_10448_amd/`` and never imports it.
 
 from .rtcur import (E_INVAL, E_NONFINITE, E_RANK, NOT_CONVERGED, OK, Factors,
                     OracleError, Result, evaluate, gather_blocks, l_update,
-                    rank_rtol, rtcur, truncated_pinv)
+                    outliers, rank_rtol, rtcur, truncated_pinv)
 from .sampler import (Sample, Stream, chidori_tuples, decode_columns,
                       draw_sample, encode_columns, floyd_subset, sample_I,
                       splitmix64_step)

@@ -225,6 +225,18 @@ def rtcur(X: np.ndarray, ranks: Sequence[int], I_sizes: Sequence[int],
                   SB, LB, f, dims)
 
 
+def outliers(res: Result, X: np.ndarray, zeta: Optional[float] = None):
+    """Full-grid outliers: the S-update of equation 11 applied to every entry
+    of X, S = HT_zeta(X - L) with the strict threshold of equation 10 and
+    L = res.reconstruct().  zeta None (or <= 0): the returned iterate's
+    threshold zeta_K, zeta_0 when no iteration ran.  Returns (S, L)."""
+    X = np.asarray(X, dtype=np.float64)
+    L = res.reconstruct()
+    if zeta is None or zeta <= 0:
+        zeta = res.zeta_hist[-1] if res.iters > 0 else res.zeta0
+    return hard_threshold(X - L, zeta), L
+
+
 def _checked_gather(X, samp):
     XB = gather_blocks(X, samp)
     for b in XB:

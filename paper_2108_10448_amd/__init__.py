@@ -34,7 +34,8 @@ F64, F32 = 0, 1
 FIXED, RESAMPLE = 0, 1
 BLOCK_X, BLOCK_C, BLOCK_L, BLOCK_SUPPORT = 0, 1, 2, 3
 
-SYMBOLS = ["rtcur_create", "rtcur_solve", "rtcur_reconstruct", "rtcur_destroy",
+SYMBOLS = ["rtcur_create", "rtcur_solve", "rtcur_reconstruct", "rtcur_outliers",
+           "rtcur_destroy",
            "rtcur_get_indices", "rtcur_get_history", "rtcur_get_block",
            "rtcur_get_tucker", "rtcur_sample", "rtcur_set_profiling",
            "rtcur_get_profile", "rtcur_strerror", "rtcur_last_error"]
@@ -78,6 +79,7 @@ def lib() -> ctypes.CDLL:
                               ctypes.POINTER(ctypes.c_int32), p64, p64, dbl, dbl,
                               dbl, i32, u64, ctypes.POINTER(RtcurInfo)]
     L.rtcur_reconstruct.argtypes = [vp, vp, ctypes.c_int]
+    L.rtcur_outliers.argtypes = [vp, vp, ctypes.c_int, dbl, vp, vp, ctypes.c_int]
     L.rtcur_destroy.argtypes = [vp]
     L.rtcur_get_indices.argtypes = [vp, i32, i32, p64, i64, p64]
     L.rtcur_get_history.argtypes = [vp, pd, pd, i32, ctypes.POINTER(ctypes.c_int32)]
@@ -246,6 +248,32 @@ def reconstruct(h: Handle, out=None, dtype=None):
     if rc != OK:
         raise RTCURError(rc, f"rtcur_reconstruct: {strerror(rc)}: {h.last_error()}")
     return out
+
+
+def outliers(h: Handle, X, zeta: Optional[float] = None, *, with_L: bool = False,
+             dtype=None):
+    """rtcur_outliers: S = HT_zeta(X - L) over the whole tensor (zeta None:
+    the returned iterate's threshold), and L too when with_L; X is the
+    solved device tensor.  Returns S, or (S, L)."""
+    torch = _torch()
+    if not (isinstance(X, torch.Tensor) and X.is_cuda and X.is_contiguous()):
+        raise TypeError("X must be a C-contiguous device torch.Tensor")
+    if X.dtype not in (torch.float32, torch.float64):
+        raise TypeError("X must be float32 or float64")
+    if tuple(X.shape) != tuple(h.dims):
+        raise ValueError(f"X has shape {tuple(X.shape)}, the solve had {tuple(h.dims)}")
+    odt = dtype or h.dtype
+    S = torch.empty(h.dims, dtype=odt, device=X.device)
+    L_ = torch.empty(h.dims, dtype=odt, device=X.device) if with_L else None
+    rc = lib().rtcur_outliers(h.ptr, ctypes.c_void_p(X.data_ptr()),
+                              F64 if X.dtype == torch.float64 else F32,
+                              float(zeta) if zeta is not None else 0.0,
+                              ctypes.c_void_p(S.data_ptr()),
+                              ctypes.c_void_p(L_.data_ptr()) if with_L else None,
+                              F64 if odt == torch.float64 else F32)
+    if rc != OK:
+        raise RTCURError(rc, f"rtcur_outliers: {strerror(rc)}: {h.last_error()}")
+    return (S, L_) if with_L else S
 
 
 def get_indices(h: Handle, mode: int, which: int) -> np.ndarray:

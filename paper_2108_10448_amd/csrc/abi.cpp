@@ -140,6 +140,18 @@ int rtcur_reconstruct(rtcur_t h, void* L_out, int out_dtype) {
     return rtcur::reconstruct(h, L_out, out_dtype);
 }
 
+int rtcur_outliers(rtcur_t h, const void* X, int x_dtype, double zeta, void* S_out,
+                   void* L_out, int out_dtype) {
+    if (!h) return RTCUR_E_INVAL;
+    if (!X || !S_out) return fail(h, RTCUR_E_INVAL, "X and S_out must not be null");
+    if (x_dtype != RTCUR_F64 && x_dtype != RTCUR_F32)
+        return fail(h, RTCUR_E_INVAL, "x_dtype must be RTCUR_F64 or RTCUR_F32");
+    if (out_dtype != RTCUR_F64 && out_dtype != RTCUR_F32)
+        return fail(h, RTCUR_E_INVAL, "out_dtype must be RTCUR_F64 or RTCUR_F32");
+    if (!std::isfinite(zeta)) return fail(h, RTCUR_E_INVAL, "zeta must be finite");
+    return rtcur::outliers(h, X, x_dtype, zeta, S_out, L_out, out_dtype);
+}
+
 int rtcur_destroy(rtcur_t h) {
     if (!h) return RTCUR_OK;
     rtcur::release(h);

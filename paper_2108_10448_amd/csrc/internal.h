@@ -133,6 +133,8 @@ int solve(rtcur_s* h, const void* X, int x_dtype, const Shape& sh,
           double zeta0, double gamma, double tol, int max_iter,
           uint64_t seed);
 int reconstruct(rtcur_s* h, void* out, int out_dtype);
+int outliers(rtcur_s* h, const void* X, int x_dtype, double zeta, void* S_out, void* L_out,
+             int out_dtype);
 int get_block(rtcur_s* h, int block, int what, double* out, int64_t cap,
               int64_t* len);
 int get_tucker(rtcur_s* h, double* core, double* const* B);

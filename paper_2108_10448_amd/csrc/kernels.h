@@ -1341,6 +1341,48 @@ __global__ __launch_bounds__(kThreads) void k_recon(int d0, int64_t ncols,
     }
 }
 
+// Full-grid outliers fused with the reconstruction (the S-update of
+// equation 11 applied to every entry of X instead of the sampled blocks):
+// L = sum_p B_0[x][p] H[p][c] on the mode-0 unfolding, D = X - L in the
+// compute type, S = D where |D| > zeta (strict, equation 10) else 0.  One
+// read of X, one write of S (and of L when L_out is given).
+template <typename T, typename TX, typename TO, int RP>
+__global__ __launch_bounds__(kThreads) void k_outliers(int d0, int64_t ncols,
+                                                       const T* __restrict__ B0,
+                                                       const T* __restrict__ Hf,
+                                                       const TX* __restrict__ X, double zeta,
+                                                       TO* __restrict__ S_out,
+                                                       TO* __restrict__ L_out) {
+    const int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    const int x0 = blockIdx.y * kTileRows;
+    __shared__ T bs[kTileRows][RP];
+    if (threadIdx.x < kTileRows * RP) {
+        const int x = threadIdx.x / RP, p = threadIdx.x % RP;
+        bs[x][p] = (x0 + x < d0) ? B0[(int64_t)(x0 + x) * RP + p] : T(0);
+    }
+    __syncthreads();
+    if (c >= ncols) return;
+    const int rows = min(kTileRows, d0 - x0);
+    TX xv[kTileRows];
+#pragma unroll
+    for (int x = 0; x < kTileRows; ++x)
+        xv[x] = X[(int64_t)(x0 + (x < rows ? x : rows - 1)) * ncols + c];
+    T h[RP];
+#pragma unroll
+    for (int p = 0; p < RP; ++p) h[p] = Hf[(int64_t)p * ncols + c];
+#pragma unroll
+    for (int x = 0; x < kTileRows; ++x) {
+        if (x >= rows) break;  // uniform
+        T L = T(0);
+#pragma unroll
+        for (int p = 0; p < RP; ++p) L = fma(bs[x][p], h[p], L);
+        const T D = (T)xv[x] - L;
+        const int64_t e = (int64_t)(x0 + x) * ncols + c;
+        S_out[e] = (TO)(fabs((double)D) > zeta ? D : T(0));
+        if (L_out) L_out[e] = (TO)L;
+    }
+}
+
 // L on one sampled block (for inspection): out[x][c] = sum_p B[x][p] H[p][c].
 template <typename T, int RP>
 __global__ __launch_bounds__(kThreads) void k_evalblock(Prob P, int b,

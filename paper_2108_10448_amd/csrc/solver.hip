@@ -836,17 +836,11 @@ static int ensure_scratch(rtcur_s* h, Impl& im, size_t bytes) {
     return 0;
 }
 
-template <typename T, typename TO, int RP>
-static int recon_t(rtcur_s* h, Impl& im, void* out) {
+// H of the full mode-0 unfolding (RP x prod_{j>0} d_j) into the scratch
+// buffer, for the dense reconstruction and the full-grid outliers.
+template <typename T, int RP>
+static int dense_h(rtcur_s* h, Impl& im, int64_t ncols, T** Hf_out) {
     const Prob& P = im.P;
-    int64_t ncols = 1;
-    for (int j = 1; j < P.n; ++j) ncols *= P.d[j];
-    const int64_t total = ncols * P.d[0];
-    if (im.final_iter == 0) {
-        HIPCHK(hipMemsetAsync(out, 0, total * sizeof(TO), h->stream));
-        HIPCHK(hipStreamSynchronize(h->stream));
-        return 0;
-    }
     const int64_t ntile = (ncols + kThreads - 1) / kThreads;
     size_t need = align_up(sizeof(T) * RP * ncols, 256) + sizeof(int2) * ntile + 256;
     int rc = ensure_scratch(h, im, need);
@@ -877,6 +871,25 @@ static int recon_t(rtcur_s* h, Impl& im, void* out) {
             break;
     }
     HIPCHK(hipGetLastError());
+    *Hf_out = Hf;
+    return 0;
+}
+
+template <typename T, typename TO, int RP>
+static int recon_t(rtcur_s* h, Impl& im, void* out) {
+    const Prob& P = im.P;
+    int64_t ncols = 1;
+    for (int j = 1; j < P.n; ++j) ncols *= P.d[j];
+    const int64_t total = ncols * P.d[0];
+    if (im.final_iter == 0) {
+        HIPCHK(hipMemsetAsync(out, 0, total * sizeof(TO), h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        return 0;
+    }
+    T* Hf = nullptr;
+    int rc = dense_h<T, RP>(h, im, ncols, &Hf);
+    if (rc) return rc;
+    const int64_t ntile = (ncols + kThreads - 1) / kThreads;
     dim3 grid((unsigned)ntile, (unsigned)((P.d[0] + kTileRows - 1) / kTileRows));
     hipLaunchKernelGGL((k_recon<T, TO, RP>), grid, dim3(kThreads), 0, h->stream, P.d[0],
                        ncols, (const T*)im.Bf + P.boff[0], (const T*)Hf, (TO*)out);
@@ -892,6 +905,69 @@ static int recon_rp(rtcur_s* h, Impl& im, void* out, int odt) {
         case 8: return odt == RTCUR_F64 ? recon_t<T, double, 8>(h, im, out) : recon_t<T, float, 8>(h, im, out);
         default: return odt == RTCUR_F64 ? recon_t<T, double, 16>(h, im, out) : recon_t<T, float, 16>(h, im, out);
     }
+}
+
+// Full-grid outliers S = HT_zeta(X - L) and optionally L itself, in one pass.
+template <typename T, typename TX, typename TO, int RP>
+static int outl_t(rtcur_s* h, Impl& im, const void* X, double zeta, void* S, void* L) {
+    const Prob& P = im.P;
+    int64_t ncols = 1;
+    for (int j = 1; j < P.n; ++j) ncols *= P.d[j];
+    T* Hf = nullptr;
+    const T* B0 = (const T*)im.Bf + P.boff[0];
+    if (im.final_iter == 0) {
+        // L = 0: H = 0 (B is never read then: H zero makes every L zero)
+        const size_t need = align_up(sizeof(T) * RP * ncols, 256) + 256;
+        int rc = ensure_scratch(h, im, need);
+        if (rc) return rc;
+        Hf = static_cast<T*>(im.scratch);
+        HIPCHK(hipMemsetAsync(Hf, 0, sizeof(T) * RP * ncols, h->stream));
+    } else {
+        int rc = dense_h<T, RP>(h, im, ncols, &Hf);
+        if (rc) return rc;
+    }
+    const int64_t ntile = (ncols + kThreads - 1) / kThreads;
+    dim3 grid((unsigned)ntile, (unsigned)((P.d[0] + kTileRows - 1) / kTileRows));
+    hipLaunchKernelGGL((k_outliers<T, TX, TO, RP>), grid, dim3(kThreads), 0, h->stream, P.d[0],
+                       ncols, B0, (const T*)Hf, (const TX*)X, zeta, (TO*)S, (TO*)L);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return 0;
+}
+
+template <typename T, int RP>
+static int outl_rp(rtcur_s* h, Impl& im, const void* X, int xdt, double zeta, void* S, void* L,
+                   int odt) {
+    if (xdt == RTCUR_F64)
+        return odt == RTCUR_F64 ? outl_t<T, double, double, RP>(h, im, X, zeta, S, L)
+                                : outl_t<T, double, float, RP>(h, im, X, zeta, S, L);
+    return odt == RTCUR_F64 ? outl_t<T, float, double, RP>(h, im, X, zeta, S, L)
+                            : outl_t<T, float, float, RP>(h, im, X, zeta, S, L);
+}
+
+template <typename T>
+static int outl_t2(rtcur_s* h, Impl& im, const void* X, int xdt, double zeta, void* S, void* L,
+                   int odt) {
+    switch (im.P.rp) {
+        case 4: return outl_rp<T, 4>(h, im, X, xdt, zeta, S, L, odt);
+        case 8: return outl_rp<T, 8>(h, im, X, xdt, zeta, S, L, odt);
+        default: return outl_rp<T, 16>(h, im, X, xdt, zeta, S, L, odt);
+    }
+}
+
+int outliers(rtcur_s* h, const void* X, int x_dtype, double zeta, void* S_out, void* L_out,
+             int out_dtype) {
+    Impl* im = static_cast<Impl*>(h->impl);
+    if (!h->have_result || !im) {
+        h->last_error = "no successful solve";
+        return RTCUR_E_STATE;
+    }
+    HIPCHK(hipSetDevice(h->device));
+    // default: the threshold of the returned iterate, zeta_K (zeta_0 when K = 0)
+    if (!(zeta > 0.0)) zeta = h->info.zeta;
+    if (h->dtype == RTCUR_F64)
+        return outl_t2<double>(h, *im, X, x_dtype, zeta, S_out, L_out, out_dtype);
+    return outl_t2<float>(h, *im, X, x_dtype, zeta, S_out, L_out, out_dtype);
 }
 
 int reconstruct(rtcur_s* h, void* out, int out_dtype) {

@@ -55,6 +55,7 @@ def test_argument_checks_without_device(L):
     assert L.rtcur_solve(None, None, 0, 3, None, None, None, None, 0.0, 0.7, 1e-5,
                          10, 0, None) == rt.E_INVAL
     assert L.rtcur_reconstruct(None, None, 0) == rt.E_INVAL
+    assert L.rtcur_outliers(None, None, 0, 0.0, None, None, 0) == rt.E_INVAL
     for s in (0, 1, -1, -2, -3, -4, -5, -6):
         assert L.rtcur_strerror(s)
     assert L.rtcur_strerror(99) == b"unknown status"

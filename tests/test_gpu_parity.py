@@ -9,6 +9,7 @@ import pytest
 
 import synth
 from oracle import OracleError
+from oracle import outliers as oracle_outliers
 from oracle import rtcur as oracle_rtcur
 
 from _parity import compare, rel, run_gpu
@@ -210,3 +211,56 @@ def test_cube300_fp32_compute(cube300):
     import paper_2108_10448_amd as rt
     rt.reconstruct(h, out=L)
     assert rel(L.cpu().numpy().astype(np.float64), res.reconstruct()) < 1e-4
+
+
+def _outlier_compare(S_g, L_g, S_o, L_o, exact, tol, label):
+    sg, so = S_g != 0, S_o != 0
+    agree = float(np.mean(sg == so))
+    if exact:
+        assert np.array_equal(sg, so), f"{label}: support differs at {np.sum(sg != so)} entries"
+    else:
+        assert agree >= 0.9999, f"{label}: support agreement {agree}"
+    both = sg & so
+    eS = rel(S_g[both], S_o[both])
+    eL = rel(L_g, L_o)
+    print(f"[parity] outliers {label}: support agree {agree:.6f}, S {eS:.2e}, L {eL:.2e}")
+    assert eS <= tol and eL <= tol
+
+
+def test_outliers_fp64_cube100(cube100):
+    import paper_2108_10448_amd as rt
+    inst, I = cube100
+    res = oracle_rtcur(inst.X, inst.ranks, I, None, None, 0.7, 1e-5, 100, 0, "F")
+    h, info, X = run_gpu(inst.X, inst.ranks, I)
+    assert info.iters == res.iters
+    S_g, L_g = rt.outliers(h, X, with_L=True)
+    S_o, L_o = oracle_outliers(res, inst.X)
+    _outlier_compare(S_g.cpu().numpy(), L_g.cpu().numpy(), S_o, L_o, True, 1e-10, "cube100")
+    # an explicit threshold, S only
+    z = 10 * res.zeta_hist[-1]
+    S_g = rt.outliers(h, X, z).cpu().numpy()
+    S_o, _ = oracle_outliers(res, inst.X, z)
+    _outlier_compare(S_g, L_g.cpu().numpy(), S_o, L_o, True, 1e-10, "cube100 zeta")
+
+
+def test_outliers_fp32_cube300(cube300):
+    import paper_2108_10448_amd as rt
+    inst, I = cube300
+    h, info, X = run_gpu(inst.X, inst.ranks, I, dtype=torch.float32)
+    res = oracle_rtcur(inst.X, inst.ranks, I, None, None, 0.7, 0.0, info.iters, 0, "F")
+    S_g, L_g = rt.outliers(h, X, with_L=True)
+    S_o, L_o = oracle_outliers(res, inst.X)
+    _outlier_compare(S_g.double().cpu().numpy(), L_g.double().cpu().numpy(), S_o, L_o, False,
+                     1e-4, "cube300 fp32")
+
+
+def test_outliers_without_iterations():
+    import paper_2108_10448_amd as rt
+    inst = synth.tucker_plus_sparse((12, 10, 8), (2, 2, 2), alpha=0.1, seed=1)
+    res = oracle_rtcur(inst.X, inst.ranks, (6, 6, 6), None, None, 0.7, 1.0, 100, 0, "F")
+    h, info, X = run_gpu(inst.X, inst.ranks, (6, 6, 6), tol=1.0, check=False)
+    assert info.iters == 0 == res.iters
+    S_g, L_g = rt.outliers(h, X, with_L=True)
+    S_o, L_o = oracle_outliers(res, inst.X)
+    assert not np.any(L_g.cpu().numpy())
+    assert np.array_equal(S_g.cpu().numpy(), S_o)
