@@ -76,6 +76,8 @@ struct Prob {
     int gitem0[kMaxModes];    // first Gram work item of mode i
     int gnkc[kMaxModes];      // Gram column chunks per output tile of mode i
     int gchunk[kMaxModes];    // columns per Gram chunk (multiple of 256)
+    int cparts;               // core slices per a (middle-mode row parts, 3 modes)
+    int crows;                // middle-mode rows per part
     int bitem0[kMaxModes];    // first B-factor work item of mode i
     int bnkc[kMaxModes];      // B-factor column chunks per row block of mode i
     const int32_t* I[kMaxModes];   // sampled rows of each mode (device)

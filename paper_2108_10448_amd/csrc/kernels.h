@@ -974,10 +974,22 @@ __device__ void core_slice(const Prob& P, const T* __restrict__ R, const double*
     const int rq = P.r[n - 1];
     for (int e = tid; e < K * RP; e += kThreads) ws[e] = W[P.woff[n - 1] + e];
     if (sf) return;
+    // this item's rows [rb, re) of the slice (the whole slice unless the
+    // middle mode is split into P.cparts parts; the parts' partial cores
+    // are added by core_finish)
+    const int part = a % P.cparts;
+    a /= P.cparts;
+    const int rb = part * P.crows, re = min(rows, rb + P.crows);
     const T* Ra = R + (int64_t)a * rows * K;
     const int RC = max(1, kSliceLds / K);
-    for (int r0 = 0; r0 < rows; r0 += RC) {
-        const int nr = min(RC, rows - r0);
+    if (P.cparts > 1) {
+        for (int o = tid; o < rq * rows; o += kThreads) {
+            const int row = o % rows;
+            if (row < rb || row >= re) buf[o] = 0.0;
+        }
+    }
+    for (int r0 = rb; r0 < re; r0 += RC) {
+        const int nr = min(RC, re - r0);
         const int ne = nr * K;
         __syncthreads();
         for (int e0 = tid; e0 < ne; e0 += 8 * kThreads) {
@@ -1024,16 +1036,18 @@ __device__ void core_slice(const Prob& P, const T* __restrict__ R, const double*
     }
     int tot = 1;
     for (int l = 1; l < n; ++l) tot *= P.r[l];
-    for (int e = tid; e < tot; e += kThreads) Tbuf[(int64_t)a * tot + e] = cur[e];
+    for (int e = tid; e < tot; e += kThreads)
+        Tbuf[((int64_t)a * P.cparts + part) * tot + e] = cur[e];
 }
 
-// G = sum_a W_0[a]^T T[a] (the last contraction of the core), one
-// workgroup, T staged through LDS (tb, wb: kCoreLds / 2 doubles each).
+// G = sum_a W_0[a]^T T[a] (the last contraction of the core, the parts of
+// each slice added in order with it), one workgroup, T staged through LDS
+// (tb, wb: kCoreLds / 2 doubles each).
 template <int RP>
 __device__ void core_finish(const Prob& P, const double* __restrict__ W,
                             const double* __restrict__ Tbuf, double* __restrict__ Gd,
                             double* tb, double* wb) {
-    const int s0 = P.s[0], r0 = P.r[0];
+    const int s0 = P.s[0] * P.cparts, r0 = P.r[0];  // slices: (a, part), part fastest
     const int tot = P.core / r0;
     const int A = max(1, min((kCoreLds / 2) / tot, (kCoreLds / 2) / RP));
     constexpr int JM = kMaxCore / kThreads;
@@ -1046,7 +1060,7 @@ __device__ void core_finish(const Prob& P, const double* __restrict__ W,
         for (int e = threadIdx.x; e < na * tot; e += kThreads)
             tb[e] = Tbuf[(int64_t)a0 * tot + e];
         for (int e = threadIdx.x; e < na * RP; e += kThreads)
-            wb[e] = W[P.woff[0] + (int64_t)a0 * RP + e];
+            wb[e] = W[P.woff[0] + (int64_t)((a0 + e / RP) / P.cparts) * RP + e % RP];
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < JM; ++j) {
@@ -1087,17 +1101,28 @@ __global__ __launch_bounds__(kThreads) void k_zcore(Prob P, const T* __restrict_
 // B_i (d_i x RP) = C_i V_i S_i^-1 = C_i Z_i.  Work item = (mode, 16 rows,
 // 1024 columns): Z_i's chunk is staged in LDS, each wave owns 4 rows and its
 // lanes stride the columns; k_bred adds the chunks' partial rows in order.
+// One extra workgroup finishes the core G from the slices of k_zcore.
 constexpr int kBfacKC = 1024;
 
 template <typename T, int RP>
 __global__ __launch_bounds__(kThreads) void k_bfac(Prob P, const T* __restrict__ C,
                                                    const double* __restrict__ Zbuf,
-                                                   const int4* __restrict__ items,
+                                                   const int4* __restrict__ items, int nitems,
                                                    double* __restrict__ bpart,
-                                                   const DevState* st) {
+                                                   const double* __restrict__ W,
+                                                   const double* __restrict__ Tbuf,
+                                                   double* __restrict__ Gd, const DevState* st) {
     const int sf = stop_flag(st);
     constexpr int KC = RP <= 8 ? kBfacKC : kBfacKC / 2;
+    static_assert(KC * RP >= kCoreLds, "core_finish staging fits in zs");
     __shared__ double zs[KC * RP];
+    if ((int)blockIdx.x == nitems) {
+        // the core G = sum_a W_0[a]^T T[a] from k_zcore's slices, beside the
+        // B-factor items
+        if (sf) return;
+        core_finish<RP>(P, W, Tbuf, Gd, zs, zs + kCoreLds / 2);
+        return;
+    }
     const int4 it = items[blockIdx.x];
     const int i = it.x, rb = it.y, kc = it.z;
     const BlockDev& bd = P.blk[1 + i];
@@ -1162,21 +1187,13 @@ __global__ __launch_bounds__(kThreads) void k_bfac(Prob P, const T* __restrict__
 }
 
 // B_i rows: the column-chunk partials of k_bfac added in chunk order (one
-// thread per entry); the workgroup after the last one finishes the core G.
+// thread per entry).
 template <typename T, int RP>
 __global__ __launch_bounds__(kThreads) void k_bred(Prob P, const double* __restrict__ bpart,
                                                    const int4* __restrict__ items,
                                                    T* __restrict__ Bf, double* __restrict__ Bd,
-                                                   int nred, const double* __restrict__ W,
-                                                   const double* __restrict__ Tbuf,
-                                                   double* __restrict__ Gd, const DevState* st) {
+                                                   const DevState* st) {
     const int sf = stop_flag(st);
-    __shared__ double buf[kCoreLds];
-    if ((int)blockIdx.x == nred) {
-        if (sf) return;
-        core_finish<RP>(P, W, Tbuf, Gd, buf, buf + kCoreLds / 2);
-        return;
-    }
     const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     int i = 0;
     int64_t base = 0;

@@ -11,7 +11,8 @@
 //   k_zcore  Z_i = U_i^T Y_i (so V_i S_i^-1 = Z_i) and the core slices
 //            T[a] = R(a, ..) x_{l >= 1} W_l^T
 //   k_bfac   B_i = C_i Z_i partials over column chunks
-//   k_bred   B_i from the partials; the core G = sum_a W_0[a]^T T[a]
+//   k_bred   B_i from the partials (k_bfac's extra workgroup finishes the
+//            core G = sum_a W_0[a]^T T[a])
 //   k_hexp   H_b = G x_{j != mode} B_j on each block's columns
 // so that the next k_ht forms L on the blocks as B_mode H_b (Section 3.3).
 #include <hip/hip_runtime.h>
@@ -310,7 +311,17 @@ static void plan(Impl& im, const Shape& sh, int esize, size_t idx_bytes, int max
         for (int cb = 0; cb * kThreads < P.blk[b].ncols; ++cb)
             im.h_tiles.push_back(make_int2(b, cb));
     // core slices T[a] = R(a, ..) x_{l >= 1} W_l^T: s_0 x prod_{l >= 1} r_l
-    im.t_elems = sh.s[0] * (P.core / sh.r[0]);
+    // with three modes the slice's middle-mode rows are split so that each
+    // part is staged in one pass
+    P.cparts = 1;
+    P.crows = 1;  // all middle-mode rows of a slice
+    for (int l = 1; l < n - 1; ++l) P.crows *= (int)sh.s[l];
+    if (n == 3) {
+        const int rc = std::max<int>(1, kSliceLds / (int)sh.s[2]);
+        P.cparts = (P.crows + rc - 1) / rc;
+        P.crows = (P.crows + P.cparts - 1) / P.cparts;
+    }
+    im.t_elems = sh.s[0] * P.cparts * (P.core / sh.r[0]);
 
     const size_t nb = (size_t)im.nblk_elems;
     rg.XO = ar.add(nb * esize);
@@ -486,21 +497,21 @@ struct Runner {
         HIPCHK(pe());
         const int nz = (int)im.z_tiles.size();
         HIPCHK(pb(PK_ZCORE));
-        hipLaunchKernelGGL((k_zcore<T, RP>), dim3(nz + P.s[0]), dim3(kThreads), 0, s, P, C,
+        hipLaunchKernelGGL((k_zcore<T, RP>), dim3(nz + P.s[0] * P.cparts), dim3(kThreads), 0, s, P, C,
                            (const double*)im.Y, im.Z, im.d_z_tiles, nz, (const double*)im.W,
                            im.Tc, im.st);
         HIPCHK(hipGetLastError());
         HIPCHK(pe());
         HIPCHK(pb(PK_BFAC));
-        hipLaunchKernelGGL((k_bfac<T, RP>), dim3((unsigned)im.bfac_items.size()), dim3(kThreads),
-                           0, s, P, C, (const double*)im.Z, im.d_bfac_items, im.bpart, im.st);
+        const int nb = (int)im.bfac_items.size();
+        hipLaunchKernelGGL((k_bfac<T, RP>), dim3(nb + 1), dim3(kThreads), 0, s, P, C,
+                           (const double*)im.Z, im.d_bfac_items, nb, im.bpart,
+                           (const double*)im.W, (const double*)im.Tc, im.Gd, im.st);
         HIPCHK(hipGetLastError());
         HIPCHK(pe());
         HIPCHK(pb(PK_BRED));
-        hipLaunchKernelGGL((k_bred<T, RP>), dim3(im.n_bred_wg + 1), dim3(kThreads), 0, s, P,
-                           (const double*)im.bpart, im.d_bfac_items, (T*)im.Bf, im.Bd,
-                           im.n_bred_wg, (const double*)im.W, (const double*)im.Tc, im.Gd,
-                           im.st);
+        hipLaunchKernelGGL((k_bred<T, RP>), dim3(im.n_bred_wg), dim3(kThreads), 0, s, P,
+                           (const double*)im.bpart, im.d_bfac_items, (T*)im.Bf, im.Bd, im.st);
         HIPCHK(hipGetLastError());
         HIPCHK(pe());
         return hexp();
