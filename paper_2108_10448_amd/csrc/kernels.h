@@ -956,7 +956,7 @@ __device__ __forceinline__ double lds_dot(const TX* x, int xs, const double* y, 
 }
 
 constexpr int kCoreLds = 4096;  // doubles of LDS for one slice's partial core
-constexpr int kSliceLds = 4096; // elements of R staged per pass
+constexpr int kSliceBytes = 16384;  // bytes of R staged per pass (in buf's second half)
 
 // T[a] for one slice a of the R block (row-major s_0 x ... x s_{n-1}):
 // contract the last mode (R staged through LDS), then the others in LDS;
@@ -981,7 +981,7 @@ __device__ void core_slice(const Prob& P, const T* __restrict__ R, const double*
     a /= P.cparts;
     const int rb = part * P.crows, re = min(rows, rb + P.crows);
     const T* Ra = R + (int64_t)a * rows * K;
-    const int RC = max(1, kSliceLds / K);
+    const int RC = max(1, kSliceBytes / (int)sizeof(T) / K);
     if (P.cparts > 1) {
         for (int o = tid; o < rq * rows; o += kThreads) {
             const int row = o % rows;
@@ -1089,7 +1089,10 @@ __global__ __launch_bounds__(kThreads) void k_zcore(Prob P, const T* __restrict_
     const int sf = stop_flag(st);
     __shared__ double sh[kMaxS * RP];
     __shared__ double buf[kCoreLds];
-    __shared__ T rs[kSliceLds];
+    // the slice's staged rows share buf's second half (free until the
+    // contraction of the middle modes)
+    static_assert(kSliceBytes <= (int)sizeof(double) * kCoreLds / 2, "staging fits");
+    T* rs = reinterpret_cast<T*>(buf + kCoreLds / 2);
     if ((int)blockIdx.x < nz) {
         zmat_tile<T, RP>(P, C, Y, Zbuf, ztiles[blockIdx.x], sh, sf);
         return;
@@ -1130,22 +1133,13 @@ __global__ __launch_bounds__(kThreads) void k_bfac(Prob P, const T* __restrict__
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int c0 = kc * KC, cn = min(KC, m - c0);
     const double* Zc = Zbuf + P.zoff[i] + (int64_t)c0 * RP;
-    for (int e = tid; e < KC * RP; e += kThreads) zs[e] = e < cn * RP ? Zc[e] : 0.0;
-    if (sf) return;
     const int xb = rb * kBfacRows + w * kBfacRowsPerWave;
     const T* rowp[kBfacRowsPerWave];
 #pragma unroll
     for (int j = 0; j < kBfacRowsPerWave; ++j)
         rowp[j] = C + bd.off + (int64_t)(xb + j < d ? xb + j : d - 1) * m + c0;
-    double acc[kBfacRowsPerWave][RP];
-#pragma unroll
-    for (int j = 0; j < kBfacRowsPerWave; ++j)
-#pragma unroll
-        for (int p = 0; p < RP; ++p) acc[j][p] = 0.0;
-    __syncthreads();
     constexpr int U = 8;
-    for (int u0 = 0; u0 < KC / 64; u0 += U) {
-        T cv[kBfacRowsPerWave][U];
+    auto load_c = [&](T (&cv)[kBfacRowsPerWave][U], int u0) {
 #pragma unroll
         for (int j = 0; j < kBfacRowsPerWave; ++j)
 #pragma unroll
@@ -1153,6 +1147,35 @@ __global__ __launch_bounds__(kThreads) void k_bfac(Prob P, const T* __restrict__
                 const int c = lane + 64 * (u0 + u);
                 cv[j][u] = rowp[j][c < cn ? c : 0];
             }
+    };
+    // the first batch of C is in flight while the Z chunk is staged
+    T cv[kBfacRowsPerWave][U];
+    load_c(cv, 0);
+    {
+        // Z chunk -> LDS: every load of a thread issued before the stores
+        constexpr int ZE = KC * RP / kThreads;
+        double zv[ZE];
+#pragma unroll
+        for (int q = 0; q < ZE; ++q) {
+            const int e = tid + q * kThreads;
+            zv[q] = Zc[e < cn * RP ? e : 0];
+        }
+#pragma unroll
+        for (int q = 0; q < ZE; ++q) {
+            const int e = tid + q * kThreads;
+            zs[e] = e < cn * RP ? zv[q] : 0.0;
+        }
+    }
+    if (sf) return;
+    double acc[kBfacRowsPerWave][RP];
+#pragma unroll
+    for (int j = 0; j < kBfacRowsPerWave; ++j)
+#pragma unroll
+        for (int p = 0; p < RP; ++p) acc[j][p] = 0.0;
+    __syncthreads();
+    for (int u0 = 0; u0 < KC / 64; u0 += U) {
+        T cn_[kBfacRowsPerWave][U];
+        if (u0 + U < KC / 64) load_c(cn_, u0 + U);  // next batch in flight
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int c = lane + 64 * (u0 + u);
@@ -1167,6 +1190,12 @@ __global__ __launch_bounds__(kThreads) void k_bfac(Prob P, const T* __restrict__
                     for (int p = 0; p < RP; ++p) acc[j][p] = fma(x, z[p], acc[j][p]);
                 }
             }
+        }
+        if (u0 + U < KC / 64) {
+#pragma unroll
+            for (int j = 0; j < kBfacRowsPerWave; ++j)
+#pragma unroll
+                for (int u = 0; u < U; ++u) cv[j][u] = cn_[j][u];
         }
     }
 #pragma unroll

@@ -317,7 +317,7 @@ static void plan(Impl& im, const Shape& sh, int esize, size_t idx_bytes, int max
     P.crows = 1;  // all middle-mode rows of a slice
     for (int l = 1; l < n - 1; ++l) P.crows *= (int)sh.s[l];
     if (n == 3) {
-        const int rc = std::max<int>(1, kSliceLds / (int)sh.s[2]);
+        const int rc = std::max<int>(1, kSliceBytes / esize / (int)sh.s[2]);
         P.cparts = (P.crows + rc - 1) / rc;
         P.crows = (P.crows + P.cparts - 1) / P.cparts;
     }
