@@ -69,6 +69,9 @@ typedef struct {
     double zeta0;        /* zeta_0 used (given, or max|X|)                    */
     int32_t eig_steps;   /* total subspace-iteration steps of the eigensolver */
     int32_t status;      /* status of the last rtcur_solve                    */
+    int32_t eig_unconverged; /* eigensolver calls that stopped at their step
+                                limit before the residual test passed (a
+                                near-degenerate gap sigma_r ~ sigma_{r+1})   */
 } rtcur_info;
 
 /* Create a solver bound to HIP device `device` and stream `hip_stream`

@@ -45,7 +45,7 @@ class RtcurInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32),
                 ("err", ctypes.c_double), ("zeta", ctypes.c_double),
                 ("zeta0", ctypes.c_double), ("eig_steps", ctypes.c_int32),
-                ("status", ctypes.c_int32)]
+                ("status", ctypes.c_int32), ("eig_unconverged", ctypes.c_int32)]
 
 
 class RTCURError(RuntimeError):
@@ -154,6 +154,7 @@ class Info:
     zeta: float
     zeta0: float
     eig_steps: int
+    eig_unconverged: int = 0
 
 
 class Handle:
@@ -235,7 +236,7 @@ def solve(h: Handle, X, ranks: Sequence[int], I_sizes: Optional[Sequence[int]] =
     if rc == NOT_CONVERGED and check:
         warnings.warn(f"RTCUR did not reach tol in {max_iter} iterations (e={info.err:.3e})")
     return Info(rc, info.iters, bool(info.converged), info.err, info.zeta, info.zeta0,
-                info.eig_steps)
+                info.eig_steps, info.eig_unconverged)
 
 
 def reconstruct(h: Handle, out=None, dtype=None):

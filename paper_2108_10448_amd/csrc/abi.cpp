@@ -46,10 +46,6 @@ int validate(rtcur_t h, int32_t n, const int64_t* dims, const int32_t* ranks,
         core *= ranks[i];
     }
     if (core > rtcur::kMaxCore) return fail(h, RTCUR_E_INVAL, "prod(r_i) must be <= 4096");
-    if (n == 4) {
-        for (int i = 0; i < n; ++i)
-            if (ranks[i] > 8) return fail(h, RTCUR_E_INVAL, "4-mode tensors need r_i <= 8");
-    }
     {
         // one slice of the core, r_{n-1} x prod_{0 < l < n-1} |I_l|, fits in LDS
         int64_t slice = ranks[n - 1];

@@ -506,6 +506,9 @@ struct EigShared {
     double part[4][256];                   // per-wave 16 x 16 MFMA partials
     double red[4];
     int2 pairs[(kMaxS / 16) * (kMaxS / 16 + 1) / 2];  // Gram tile pair -> (ta, tb)
+    double vv[RP * RP];                    // Rayleigh-Ritz: eigenvectors of T
+    double th[RP], jc[RP], js[RP];         // eigenvalues; one Jacobi round's rotations
+    int jp[RP], ord[RP];                   // rotation partners; decreasing order
     int ok;
 };
 
@@ -634,6 +637,207 @@ __device__ __forceinline__ void eig_gq(const double* G, int sp, int s, EigShared
     __syncthreads();
 }
 
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Eigen-decomposition of the symmetric RP x RP matrix in sh.mm by cyclic
+// Jacobi rotations (Golub and Van Loan, the symmetric Schur step with the
+// round-robin ordering of RP/2 disjoint rotations per round), run by wave 0
+// alone: on return sh.vv holds the eigenvectors as columns, sh.th the
+// eigenvalues and sh.ord the indices by decreasing eigenvalue.  Sweeps stop
+// once the off-diagonal mass is below 1e-29 of the diagonal's (squares).
+template <int RP>
+__device__ void eig_jacobi(EigShared<RP>& sh) {
+    const int lane = threadIdx.x;  // 0..63
+    constexpr int NE = (RP * RP + 63) / 64;
+    double* A = sh.mm;
+#pragma unroll
+    for (int u = 0; u < NE; ++u) {
+        const int e = lane + 64 * u;
+        if (e < RP * RP) sh.vv[e] = (e / RP == e % RP) ? 1.0 : 0.0;
+    }
+    wave_sync();
+    for (int sweep = 0; sweep < 40; ++sweep) {
+        double off = 0.0, dg = 0.0;
+#pragma unroll
+        for (int u = 0; u < NE; ++u) {
+            const int e = lane + 64 * u;
+            const double v = e < RP * RP ? A[e] : 0.0;
+            if (e / RP == e % RP) dg += v * v;
+            else off += v * v;
+        }
+        off = wave_sum(off);
+        dg = wave_sum(dg);
+        if (!(off > 1e-29 * dg)) break;
+        for (int k = 0; k < RP - 1; ++k) {
+            if (lane < RP / 2) {
+                int p = RP - 1, q = k;
+                if (lane > 0) {
+                    p = (k + lane) % (RP - 1);
+                    q = (k - lane + RP - 1) % (RP - 1);
+                }
+                const double app = A[p * RP + p], aqq = A[q * RP + q], apq = A[p * RP + q];
+                double c = 1.0, sn = 0.0;
+                if (apq != 0.0) {
+                    const double tau = (aqq - app) / (2.0 * apq);
+                    const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                    c = 1.0 / sqrt(1.0 + t * t);
+                    sn = t * c;
+                }
+                // J[p][p] = J[q][q] = c, J[p][q] = sn, J[q][p] = -sn; column i of
+                // J is c at row i and js[i] at row jp[i]
+                sh.jp[p] = q;
+                sh.jp[q] = p;
+                sh.jc[p] = c;
+                sh.jc[q] = c;
+                sh.js[p] = -sn;
+                sh.js[q] = sn;
+            }
+            wave_sync();
+            double na[NE], nv[NE];
+#pragma unroll
+            for (int u = 0; u < NE; ++u) {
+                const int e = lane + 64 * u < RP * RP ? lane + 64 * u : 0;
+                const int i = e / RP, j = e % RP;
+                const int i2 = sh.jp[i], j2 = sh.jp[j];
+                const double ci = sh.jc[i], si = sh.js[i], cj = sh.jc[j], sj = sh.js[j];
+                // (J^T A J)[i][j] and (V J)[i][j]
+                na[u] = ci * (cj * A[i * RP + j] + sj * A[i * RP + j2]) +
+                        si * (cj * A[i2 * RP + j] + sj * A[i2 * RP + j2]);
+                nv[u] = cj * sh.vv[i * RP + j] + sj * sh.vv[i * RP + j2];
+            }
+            wave_sync();
+#pragma unroll
+            for (int u = 0; u < NE; ++u) {
+                const int e = lane + 64 * u;
+                if (e < RP * RP) {
+                    A[e] = na[u];
+                    sh.vv[e] = nv[u];
+                }
+            }
+            wave_sync();
+        }
+    }
+    if (lane < RP) {
+        const double t = A[lane * RP + lane];
+        int rank = 0;
+        for (int k = 0; k < RP; ++k) {
+            const double u = A[k * RP + k];
+            rank += (u > t || (u == t && k < lane)) ? 1 : 0;
+        }
+        sh.th[lane] = t;
+        sh.ord[rank] = lane;
+    }
+    wave_sync();
+}
+
+constexpr int kEigCheck = 4;     // guarded iteration: Rayleigh-Ritz every 4 steps
+constexpr int kEigGuardMax = 400;
+
+// Guarded subspace iteration for a slow gap (lambda_{r+1} / lambda_r close
+// to 1): the iterate gets m - r extra columns (m = min(RP, s)), so that the
+// top-r part converges at lambda_{m+1} / lambda_r, with a Rayleigh-Ritz
+// step (T = Q^T G Q diagonalised by eig_jacobi) every kEigCheck steps that
+// rotates the basis to Ritz vectors in decreasing order and tests the top-r
+// residual ||G q_p - theta_p q_p|| against rtol ||theta_{1..r}||.  Cholesky-QR
+// is applied twice per step, because the m-column iterate is worse
+// conditioned than the r-column one.  Returns 1 when converged (q holds the
+// top-r Ritz vectors, zero beyond r), 0 when not (q holds the best r
+// columns), -1 when the m-column iterate lost rank (q untouched).
+template <int RP>
+__device__ int eig_guarded(const double* G, int sp, int s, int r, int m, double rtol,
+                           double (&q)[RP], EigShared<RP>& sh, int& steps) {
+    const int a = threadIdx.x;
+    const bool act = a < s;
+    double x[RP], z[RP];
+#pragma unroll
+    for (int p = 0; p < RP; ++p)
+        x[p] = p < r ? q[p] : ((act && p < m) ? ((eig_hash(a, p + 977) & 1u) ? 1.0 : -1.0) : 0.0);
+    int res = 0;
+    for (int it = 0; it <= kEigGuardMax; ++it, ++steps) {
+        __syncthreads();
+        if (act) {
+#pragma unroll
+            for (int p = 0; p < RP; ++p) sh.qs[a * RP + p] = x[p];
+        }
+        __syncthreads();
+        eig_gq<RP>(G, sp, s, sh);
+#pragma unroll
+        for (int p = 0; p < RP; ++p) z[p] = act ? sh.zs[a * RP + p] : 0.0;
+        if (it > 0 && (it % kEigCheck == 0 || it == kEigGuardMax)) {
+            eig_tm<RP>(sp, true, sh);  // T = Q^T Z
+            if (threadIdx.x < RP * RP) {
+                const int p = threadIdx.x / RP, t = threadIdx.x % RP;
+                sh.mm[threadIdx.x] = 0.5 * (sh.tm[p * RP + t] + sh.tm[t * RP + p]);
+            }
+            __syncthreads();
+            if (threadIdx.x < 64) eig_jacobi<RP>(sh);
+            __syncthreads();
+            double xr[RP], zr[RP], rn = 0.0, tn = 0.0;
+#pragma unroll
+            for (int p = 0; p < RP; ++p) {
+                const int o = sh.ord[p] & (RP - 1);  // in range even if a NaN broke the ranking
+                double u = 0.0, v = 0.0;
+#pragma unroll
+                for (int k = 0; k < RP; ++k) {
+                    const double w = sh.vv[k * RP + o];
+                    u += x[k] * w;
+                    v += z[k] * w;
+                }
+                xr[p] = u;
+                zr[p] = v;
+                if (p < r) {
+                    const double t = sh.th[o];
+                    const double d = v - t * u;
+                    rn += act ? d * d : 0.0;
+                    tn += t * t;
+                }
+            }
+            rn = block_sum<4>(rn, sh.red);
+#pragma unroll
+            for (int p = 0; p < RP; ++p) {
+                x[p] = xr[p];
+                z[p] = zr[p];
+            }
+            if (rn <= rtol * rtol * tn || it == kEigGuardMax) {
+                res = rn <= rtol * rtol * tn ? 1 : 0;
+                break;
+            }
+        }
+        // Cholesky-QR twice over the m columns
+        __syncthreads();
+        if (act) {
+#pragma unroll
+            for (int p = 0; p < RP; ++p) sh.zs[a * RP + p] = z[p];
+        }
+        __syncthreads();
+        bool ok = true;
+        for (int rep = 0; rep < 2; ++rep) {
+            eig_tm<RP>(sp, false, sh);  // M = Z^T Z
+            double R[RP][RP], di[RP];
+            ok = eig_chol<RP>(sh.mm, m, R, di);  // same value in every thread
+            if (!ok) break;
+            eig_trsm<RP>(z, R, di, x);
+            if (rep == 0) {
+#pragma unroll
+                for (int p = 0; p < RP; ++p) z[p] = x[p];
+                if (act) {
+#pragma unroll
+                    for (int p = 0; p < RP; ++p) sh.zs[a * RP + p] = z[p];
+                }
+                __syncthreads();
+            }
+        }
+        if (!ok) return -1;
+    }
+#pragma unroll
+    for (int p = 0; p < RP; ++p) q[p] = (act && p < r) ? x[p] : 0.0;
+    return res;
+}
+
 // kLdsGram: the Gram sits in dynamic LDS (else in `gram`); a compile-time
 // choice so that its accesses compile to LDS (or global) instructions rather
 // than generic ones.
@@ -747,50 +951,67 @@ __global__ __launch_bounds__(kThreads) void k_eig(Prob P, const double* __restri
         }
     }
     int steps = 0;
-    bool conv = false;
-    for (;; ++steps) {
-        __syncthreads();
-        if (act) {
+    const int m = s < RP ? s : RP;  // columns available to the guarded iteration
+    // Plain subspace iteration on r columns for at most `limit` steps:
+    // 0 = converged, 1 = limit reached, 2 = too slow (the contraction per
+    // step predicts more than 30 further steps; only with allow_guard),
+    // 3 = Cholesky breakdown (sh.ok cleared).  Every branch is uniform: rn
+    // and tn come out of a block-wide sum.
+    auto plain = [&](int limit, bool allow_guard) -> int {
+        double prev = 0.0;
+        for (int it = 0;; ++it, ++steps) {
+            __syncthreads();
+            if (act) {
 #pragma unroll
-            for (int p = 0; p < RP; ++p) sh.qs[a * RP + p] = q[p];
-        }
-        __syncthreads();
-        eig_gq<RP>(G, sp, s, sh);
+                for (int p = 0; p < RP; ++p) sh.qs[a * RP + p] = q[p];
+            }
+            __syncthreads();
+            eig_gq<RP>(G, sp, s, sh);
 #pragma unroll
-        for (int p = 0; p < RP; ++p) z[p] = act ? sh.zs[a * RP + p] : 0.0;
-        const bool last = steps == maxit;
-        eig_tm<RP>(sp, true, sh);  // T = Q^T Z, M = Z^T Z
-        double rn = 0.0, tn = 0.0;
-        {
-            double Tr[RP][RP];
+            for (int p = 0; p < RP; ++p) z[p] = act ? sh.zs[a * RP + p] : 0.0;
+            eig_tm<RP>(sp, true, sh);  // T = Q^T Z, M = Z^T Z
+            double rn = 0.0, tn = 0.0;
+            {
+                double Tr[RP][RP];
 #pragma unroll
-            for (int k = 0; k < RP; ++k)
+                for (int k = 0; k < RP; ++k)
+#pragma unroll
+                    for (int p = 0; p < RP; ++p) {
+                        Tr[k][p] = sh.tm[k * RP + p];
+                        tn += Tr[k][p] * Tr[k][p];
+                    }
 #pragma unroll
                 for (int p = 0; p < RP; ++p) {
-                    Tr[k][p] = sh.tm[k * RP + p];
-                    tn += Tr[k][p] * Tr[k][p];
+                    double v = z[p];
+#pragma unroll
+                    for (int k = 0; k < RP; ++k) v -= q[k] * Tr[k][p];
+                    rn += act ? v * v : 0.0;
                 }
-#pragma unroll
-            for (int p = 0; p < RP; ++p) {
-                double v = z[p];
-#pragma unroll
-                for (int k = 0; k < RP; ++k) v -= q[k] * Tr[k][p];
-                rn += act ? v * v : 0.0;
             }
+            rn = block_sum<4>(rn, sh.red);
+            if (rn <= rtol * rtol * tn) return 0;
+            if (it >= limit) return 1;
+            if (allow_guard && m > r && it >= 4 && prev > 0.0 &&
+                (rn >= prev || log(rtol * rtol * tn / rn) < 30.0 * log(rn / prev)))
+                return 2;
+            prev = rn;
+            double R[RP][RP], di[RP];
+            if (!eig_chol<RP>(sh.mm, r, R, di)) {
+                if (threadIdx.x == 0) sh.ok = 0;
+                return 3;
+            }
+            eig_trsm<RP>(z, R, di, q);
         }
-        rn = block_sum<4>(rn, sh.red);
-        if (rn <= rtol * rtol * tn) {
-            conv = true;
-            break;
-        }
-        if (last) break;
-        double R[RP][RP], di[RP];
-        if (!eig_chol<RP>(sh.mm, r, R, di)) {
-            if (threadIdx.x == 0) sh.ok = 0;
-            break;
-        }
-        eig_trsm<RP>(z, R, di, q);
+    };
+    int pr = plain(maxit, true);
+    if (pr == 2) {
+        const int g = eig_guarded<RP>(G, sp, s, r, m, rtol, q, sh, steps);
+        // a few plain steps from the Ritz vectors (or, after a breakdown of
+        // the guarded iterate, the plain iterate) polish the basis and form
+        // the T used below
+        pr = plain(g >= 0 ? 8 : maxit, false);
     }
+    const bool conv = pr == 0;
     __syncthreads();
     if (!sh.ok) {
         if (threadIdx.x == 0) {
@@ -1252,7 +1473,7 @@ __global__ __launch_bounds__(kThreads) void k_bred(Prob P, const double* __restr
 // For every column of a block (or, with a negative block id, every column of
 // the full mode-`dense_mode` unfolding), H[p][c] = sum over the other modes'
 // core indices of G[..p..] * prod_j B_j[idx_j(c)][q_j].  G sits in LDS
-// permuted so that the block's own mode comes first (padded to RP per mode);
+// permuted so that the block's own mode comes first (at the true ranks);
 // each thread's B rows sit in LDS too, so the loops run to the true ranks.
 template <typename T, int RP, int N>
 __global__ __launch_bounds__(kThreads) void k_hexp(
@@ -1260,7 +1481,8 @@ __global__ __launch_bounds__(kThreads) void k_hexp(
     const double* __restrict__ Gd, T* __restrict__ H, const DevState* st,
     int dense_mode, int64_t dense_cols) {
     const int sf = st ? stop_flag(st) : 0;
-    constexpr int GP = N == 2 ? RP * RP : (N == 3 ? RP * RP * RP : RP * RP * RP * RP);
+    constexpr int GPAD = N == 2 ? RP * RP : (N == 3 ? RP * RP * RP : RP * RP * RP * RP);
+    constexpr int GP = GPAD < kMaxCore ? GPAD : kMaxCore;
     __shared__ double gp[GP];
     __shared__ double vs[(N - 1) * RP * kThreads];
     const int2 tl = tiles[blockIdx.x];
@@ -1271,25 +1493,28 @@ __global__ __launch_bounds__(kThreads) void k_hexp(
     int no = 0;
     for (int j = 0; j < N; ++j)
         if (j != mode) others[no++] = j;
-    // permuted, padded core: gp[p][q_0]..[q_{N-2}] = G[...] with p at `mode`
+    const int rm = P.r[mode];
+    const int r0 = P.r[others[0]];
+    const int r1 = N >= 3 ? P.r[others[1]] : 1;
+    const int r2 = N >= 4 ? P.r[others[2]] : 1;
+    // permuted core at the true ranks: gp[((p*r0 + q)*r1 + u)*r2 + z] = G[...]
+    // with p at `mode` and q, u, z at the other modes in increasing order
     int gstr[kMaxModes];
     gstr[N - 1] = 1;
     for (int j = N - 2; j >= 0; --j) gstr[j] = gstr[j + 1] * P.r[j + 1];
-    for (int e = threadIdx.x; e < GP; e += kThreads) {
-        int rem = e, idx[kMaxModes];
-        for (int q = N - 2; q >= 0; --q) {
-            idx[q] = rem % RP;
-            rem /= RP;
-        }
-        const int p = rem;
-        bool ok = p < P.r[mode];
-        int off = p * gstr[mode];
-        for (int q = 0; q < N - 1; ++q) {
-            ok = ok && idx[q] < P.r[others[q]];
-            off += idx[q] * gstr[others[q]];
-        }
-        const double gv = Gd[ok ? off : 0];
-        gp[e] = ok ? gv : 0.0;
+    const int gcount = rm * r0 * r1 * r2;
+    for (int e = threadIdx.x; e < gcount; e += kThreads) {
+        int rem = e;
+        const int z = rem % r2;
+        rem /= r2;
+        const int u = rem % r1;
+        rem /= r1;
+        const int q = rem % r0;
+        const int p = rem / r0;
+        int off = p * gstr[mode] + q * gstr[others[0]];
+        if (N >= 3) off += u * gstr[others[1]];
+        if (N >= 4) off += z * gstr[others[2]];
+        gp[e] = Gd[off];
     }
     const int tid = threadIdx.x;
     const int64_t c = (int64_t)tl.y * kThreads + tid;
@@ -1321,10 +1546,6 @@ __global__ __launch_bounds__(kThreads) void k_hexp(
             for (int k = 0; k < RP; ++k) vs[(q * RP + k) * kThreads + tid] = (double)bv[q][k];
     }
     __syncthreads();
-    const int rm = P.r[mode];
-    const int r0 = P.r[others[0]];
-    const int r1 = N >= 3 ? P.r[others[1]] : 1;
-    const int r2 = N >= 4 ? P.r[others[2]] : 1;
     const double* v0 = vs + tid;
     const double* v1 = vs + RP * kThreads + tid;
     const double* v2 = vs + 2 * RP * kThreads + tid;
@@ -1335,17 +1556,17 @@ __global__ __launch_bounds__(kThreads) void k_hexp(
             for (int q = 0; q < r0; ++q) {
                 double t1;
                 if constexpr (N == 2) {
-                    t1 = gp[p * RP + q];
+                    t1 = gp[p * r0 + q];
                 } else {
                     t1 = 0.0;
                     for (int u = 0; u < r1; ++u) {
                         double t2;
                         if constexpr (N == 3) {
-                            t2 = gp[(p * RP + q) * RP + u];
+                            t2 = gp[(p * r0 + q) * r1 + u];
                         } else {
                             t2 = 0.0;
                             for (int z = 0; z < r2; ++z)
-                                t2 = fma(gp[((p * RP + q) * RP + u) * RP + z],
+                                t2 = fma(gp[((p * r0 + q) * r1 + u) * r2 + z],
                                          v2[z * kThreads], t2);
                         }
                         t1 = fma(t2, v1[u * kThreads], t1);

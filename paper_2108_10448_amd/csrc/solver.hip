@@ -455,10 +455,9 @@ struct Runner {
                                    (int64_t)0);
                 break;
             default:
-                if constexpr (RP <= 8)
-                    hipLaunchKernelGGL((k_hexp<T, RP, 4>), dim3(nt), dim3(kThreads), 0, s,
-                                       im.P, im.d_h_tiles, (const T*)im.Bf, im.Gd, (T*)im.H,
-                                       im.st, 0, (int64_t)0);
+                hipLaunchKernelGGL((k_hexp<T, RP, 4>), dim3(nt), dim3(kThreads), 0, s,
+                                   im.P, im.d_h_tiles, (const T*)im.Bf, im.Gd, (T*)im.H,
+                                   im.st, 0, (int64_t)0);
                 break;
         }
         HIPCHK(hipGetLastError());
@@ -621,6 +620,7 @@ struct Runner {
         info.zeta = K > 0 ? h->zeta_hist[K - 1] : ds.zeta0;
         info.zeta0 = ds.zeta0;
         info.eig_steps = ds.eig_steps;
+        info.eig_unconverged = ds.eig_unconverged;
         info.status = info.converged ? RTCUR_OK : RTCUR_NOT_CONVERGED;
         h->have_result = true;
         return info.status;
@@ -875,10 +875,9 @@ static int dense_h(rtcur_s* h, Impl& im, int64_t ncols, T** Hf_out) {
                                (DevState*)nullptr, 0, ncols);
             break;
         default:
-            if constexpr (RP <= 8)
-                hipLaunchKernelGGL((k_hexp<T, RP, 4>), dim3((unsigned)ntile), dim3(kThreads), 0,
-                                   h->stream, P, tiles, (const T*)im.Bf, im.Gd, Hf,
-                                   (DevState*)nullptr, 0, ncols);
+            hipLaunchKernelGGL((k_hexp<T, RP, 4>), dim3((unsigned)ntile), dim3(kThreads), 0,
+                               h->stream, P, tiles, (const T*)im.Bf, im.Gd, Hf,
+                               (DevState*)nullptr, 0, ncols);
             break;
     }
     HIPCHK(hipGetLastError());

@@ -26,8 +26,8 @@ from typing import Optional, Sequence
 
 import numpy as np
 
-__all__ = ["Instance", "tucker_plus_sparse", "sample_sizes", "CONFIGS",
-           "config_instance"]
+__all__ = ["Instance", "tucker_plus_sparse", "video_like", "sample_sizes",
+           "CONFIGS", "config_instance"]
 
 
 @dataclass
@@ -80,6 +80,75 @@ def tucker_plus_sparse(dims: Sequence[int], ranks: Sequence[int], alpha: float,
     if not keep_parts:
         return Instance(X, None, None, dims, ranks, alpha, seed, meta)
     return Instance(X, L, S, dims, ranks, alpha, seed, meta)
+
+
+def video_like(dims: Sequence[int] = (240, 320, 3, 400),
+               ranks: Sequence[int] = (10, 10, 3, 5), n_rects: int = 40,
+               side: tuple = (20, 60), coverage: float = 0.05, seed: int = 0,
+               storage=np.float32, keep_parts: bool = True) -> Instance:
+    """Video-shaped 4-mode tensor (height x width x colour x frame).
+
+    Background L*: Tucker rank ``ranks`` with i.i.d. U[0, 1] core and factors
+    (nonnegative), scaled so that max L* = 1.  Foreground S*: ``n_rects``
+    axis-aligned rectangles with sides uniform in ``side`` pixels, one
+    intensity U[0, 1] per rectangle and colour channel, each visible during a
+    window of frames in which it moves at a constant velocity (clipped at the
+    frame border).  Window lengths are scaled once so that the covered share
+    of (pixel, frame) pairs is close to ``coverage``; the realised share is
+    returned in ``meta["coverage"]``.  X = L* + S* in float64, then cast to
+    the storage dtype.  Draw order: core, factors, rectangles (size, start,
+    velocity, window start, window length, intensities).
+    """
+    dims = tuple(int(d) for d in dims)
+    ranks = tuple(int(r) for r in ranks)
+    if len(dims) != 4:
+        raise ValueError("video_like draws height x width x colour x frame")
+    H, W, CH, F = dims
+    rng = np.random.default_rng(seed)
+    core = rng.random(ranks)
+    factors = [rng.random((d, r)) for d, r in zip(dims, ranks)]
+    L = _tucker(core, factors)
+    L /= float(L.max())
+    sides = rng.integers(side[0], side[1] + 1, size=(n_rects, 2))
+    y0 = rng.uniform(0, H - sides[:, 0])
+    x0 = rng.uniform(0, W - sides[:, 1])
+    vel = rng.uniform(-3.0, 3.0, size=(n_rects, 2))
+    t_start = rng.random(n_rects)
+    t_len = rng.uniform(0.5, 1.5, size=n_rects)
+    inten = rng.random((n_rects, CH))
+
+    def windows(scale):
+        lens = np.maximum(1, np.round(scale * t_len)).astype(int)
+        starts = np.floor(t_start * np.maximum(F - lens, 0)).astype(int)
+        return starts, lens
+
+    def paint(scale, S=None):
+        starts, lens = windows(scale)
+        occ = np.zeros((F, H, W), dtype=bool) if S is None else None
+        for k in range(n_rects):
+            h, w = int(sides[k, 0]), int(sides[k, 1])
+            for f in range(starts[k], min(F, starts[k] + lens[k])):
+                dt = f - starts[k]
+                y = int(round(min(max(y0[k] + vel[k, 0] * dt, 0), H - h)))
+                x = int(round(min(max(x0[k] + vel[k, 1] * dt, 0), W - w)))
+                if S is None:
+                    occ[f, y:y + h, x:x + w] = True
+                else:
+                    S[y:y + h, x:x + w, :, f] += inten[k]
+        return None if S is None else S, (occ.mean() if occ is not None else None)
+
+    # one calibration step of the window length towards the target share
+    base = coverage * F * H * W / float(np.sum(sides[:, 0] * sides[:, 1]))
+    _, cov0 = paint(base)
+    scale = base * coverage / max(cov0, 1e-12)
+    _, cov = paint(scale)
+    S = np.zeros(dims, dtype=np.float64)
+    paint(scale, S)
+    X = (L + S).astype(storage)
+    meta = {"coverage": float(cov), "window_scale": float(scale)}
+    if not keep_parts:
+        return Instance(X, None, None, dims, ranks, coverage, seed, meta)
+    return Instance(X, L, S, dims, ranks, coverage, seed, meta)
 
 
 def sample_sizes(dims: Sequence[int], ranks: Sequence[int],

@@ -78,6 +78,41 @@ def test_four_modes_ragged_fp64():
     compare(res, h, info, label="4-mode ragged")
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_four_modes_wide_ranks(dtype):
+    # the video-shaped rank pattern (10, 10, 3, 5): ranks above 8 in a 4-mode
+    # tensor, the colour-like mode fully sampled (s = d = r = 3)
+    inst = synth.tucker_plus_sparse((40, 44, 3, 30), (10, 10, 3, 5), alpha=0.1, seed=12)
+    I = (30, 32, 3, 16)
+    X = inst.X if dtype == "f64" else inst.X.astype(np.float32)
+    res = oracle_rtcur(X, inst.ranks, I, None, None, 0.7, 0.0, 10, 4, "F")
+    h, info, _ = run_gpu(X, inst.ranks, I, tol=0.0, max_iter=10, seed=4, check=False,
+                         dtype=torch.float64 if dtype == "f64" else torch.float32)
+    compare(res, h, info, fp64=dtype == "f64", label=f"4-mode r=(10,10,3,5) {dtype}")
+
+
+@pytest.fixture(scope="module")
+def video_small():
+    # the video recipe (nonnegative Tucker background, moving rectangles) at a
+    # quarter of the frame size and half the frames; upsilon = 2 sample sizes
+    inst = synth.video_like((120, 160, 3, 200), side=(10, 30), storage=np.float32)
+    I, _ = synth.sample_sizes(inst.dims, inst.ranks, 2.0)
+    res = oracle_rtcur(inst.X, inst.ranks, I, None, None, 0.7, 0.0, 5, 0, "F")
+    return inst, I, res
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_video_shaped(video_small, dtype):
+    # the samples' spectra have sigma_{r+1} / sigma_r up to 0.98 here, which
+    # takes the eigensolver's guarded (Rayleigh-Ritz) iteration
+    inst, I, res = video_small
+    h, info, _ = run_gpu(inst.X, inst.ranks, I, tol=0.0, max_iter=5, seed=0, check=False,
+                         dtype=torch.float64 if dtype == "f64" else torch.float32)
+    print(f"[video] eig steps {info.eig_steps} unconverged {info.eig_unconverged}", flush=True)
+    assert info.eig_unconverged == 0
+    compare(res, h, info, fp64=dtype == "f64", label=f"video 120x160x3x200 {dtype}")
+
+
 def test_two_modes_fp64():
     inst = synth.tucker_plus_sparse((300, 257), (4, 4), alpha=0.1, seed=8)
     I = (40, 37)
@@ -115,7 +150,7 @@ def test_shape_limits_rejected():
         assert e.value.status == rt.E_INVAL
     X4 = torch.zeros((12, 12, 12, 12), dtype=torch.float64, device="cuda:0")
     with pytest.raises(rt.RTCURError) as e:
-        rt.solve(h, X4, (9, 2, 2, 2), (10, 6, 6, 6))       # 4 modes: r_i <= 8
+        rt.solve(h, X4, (9, 9, 9, 9), (10, 10, 10, 10))    # prod r_i = 6561 > 4096
     assert e.value.status == rt.E_INVAL
     # the handle still solves a valid problem afterwards
     inst = synth.tucker_plus_sparse((16, 16, 16), (2, 2, 2), alpha=0.1, seed=2)
