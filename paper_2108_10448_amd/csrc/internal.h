@@ -54,6 +54,9 @@ struct BlockDev {
     int64_t moff;             // 64-bit word offset of the support bitmask
     int words;                // bitmask words per row
     int tile0, tile1;         // range of the block's tiles in the tile table
+    int plen;                 // consecutive columns that share every other-mode
+                              // index but the last (chidori: s of the last
+                              // other mode); 0 when columns have no such runs
     const int32_t* rowidx;    // row -> index in `mode` (nullptr: identity)
     const int64_t* colx;      // column -> X offset of the other modes' indices
     const int32_t* cidx;      // [n-1][ncols] other-mode index of each column
@@ -80,6 +83,7 @@ struct Prob {
     int crows;                // middle-mode rows per part
     int bitem0[kMaxModes];    // first B-factor work item of mode i
     int bnkc[kMaxModes];      // B-factor column chunks per row block of mode i
+    int bsub[kMaxModes];      // staged Z sub-chunks per B-factor column chunk
     const int32_t* I[kMaxModes];   // sampled rows of each mode (device)
     BlockDev blk[kMaxBlocks];
 };

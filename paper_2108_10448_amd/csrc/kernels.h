@@ -24,7 +24,8 @@ constexpr int kThreads = 256;      // 4 waves of 64
 constexpr int kTileRows = 16;      // rows per gather / threshold tile
 constexpr int kTileCols = 256;     // one column per thread
 constexpr int kGramMinChunk = 2048; // Gram: columns per work item (at least)
-constexpr int kGramMaxKC = 4;      // Gram: column chunks per output tile (at most)
+constexpr int kGramMaxKC = 64;     // Gram: column chunks per output tile (at most)
+constexpr int kGramKCGroup = 4;    // chunks summed per load round in the eigensolver
 constexpr int kBfacRowsPerWave = 4;
 constexpr int kBfacRows = 4 * kBfacRowsPerWave;
 
@@ -509,6 +510,7 @@ struct EigShared {
     double vv[RP * RP];                    // Rayleigh-Ritz: eigenvectors of T
     double th[RP], jc[RP], js[RP];         // eigenvalues; one Jacobi round's rotations
     int jp[RP], ord[RP];                   // rotation partners; decreasing order
+    int gsteps;                            // steps of the guarded iteration
     int ok;
 };
 
@@ -744,15 +746,22 @@ constexpr int kEigGuardMax = 400;
 // rotates the basis to Ritz vectors in decreasing order and tests the top-r
 // residual ||G q_p - theta_p q_p|| against rtol ||theta_{1..r}||.  Cholesky-QR
 // is applied twice per step, because the m-column iterate is worse
-// conditioned than the r-column one.  Returns 1 when converged (q holds the
-// top-r Ritz vectors, zero beyond r), 0 when not (q holds the best r
-// columns), -1 when the m-column iterate lost rank (q untouched).
+// conditioned than the r-column one.  The iterate enters and leaves in
+// sh.qs (rows < s): on return it holds the top-r Ritz vectors (zero beyond
+// r) when converged (result 1) or the best r columns found (0); after a rank
+// loss of the m-column iterate (-1) it is left as it came.  *steps counts
+// the steps taken.  Kept out of line so that its registers do not weigh on
+// the plain iteration of the caller.
 template <int RP>
-__device__ int eig_guarded(const double* G, int sp, int s, int r, int m, double rtol,
-                           double (&q)[RP], EigShared<RP>& sh, int& steps) {
+__device__ __noinline__ int eig_guarded(const double* G, int sp, int s, int r, int m,
+                                        double rtol, EigShared<RP>* shp, int* steps_out) {
+    EigShared<RP>& sh = *shp;
     const int a = threadIdx.x;
     const bool act = a < s;
-    double x[RP], z[RP];
+    int steps = 0;
+    double x[RP], z[RP], q[RP];
+#pragma unroll
+    for (int p = 0; p < RP; ++p) q[p] = act ? sh.qs[a * RP + p] : 0.0;
 #pragma unroll
     for (int p = 0; p < RP; ++p)
         x[p] = p < r ? q[p] : ((act && p < m) ? ((eig_hash(a, p + 977) & 1u) ? 1.0 : -1.0) : 0.0);
@@ -831,10 +840,18 @@ __device__ int eig_guarded(const double* G, int sp, int s, int r, int m, double 
                 __syncthreads();
             }
         }
-        if (!ok) return -1;
+        if (!ok) {
+            res = -1;
+            break;
+        }
     }
+    __syncthreads();
+    if (act) {
 #pragma unroll
-    for (int p = 0; p < RP; ++p) q[p] = (act && p < r) ? x[p] : 0.0;
+        for (int p = 0; p < RP; ++p) sh.qs[a * RP + p] = res < 0 ? q[p] : (p < r ? x[p] : 0.0);
+    }
+    if (threadIdx.x == 0) *steps_out = steps;
+    __syncthreads();
     return res;
 }
 
@@ -878,32 +895,68 @@ __global__ __launch_bounds__(kThreads) void k_eig(Prob P, const double* __restri
         const int nkc = P.gnkc[i];
         const int total = npairs * 256;
         const double* src0 = gpart + (int64_t)P.gitem0[i] * 256;
-        constexpr int E = 24;
-        for (int f0 = threadIdx.x; f0 < total; f0 += E * kThreads) {
-            double v[E][kGramMaxKC];
+        constexpr int KG = kGramKCGroup;
+        auto put = [&](int f, double sum) {
+            const int2 pr = sh.pairs[f >> 8];
+            const int t = f & 255;
+            const int a2 = pr.x * 16 + (t >> 4), b2 = pr.y * 16 + (t & 15);
+            // rows and columns beyond s come out of k_gram as zeros
+            G[a2 * (sp + 1) + b2] = sum;
+            G[b2 * (sp + 1) + a2] = sum;
+        };
+        if (nkc <= KG) {
+            // one load round per entry: E entries x KG chunks in flight
+            constexpr int E = 24;
+            for (int f0 = threadIdx.x; f0 < total; f0 += E * kThreads) {
+                double v[E][KG];
 #pragma unroll
-            for (int u = 0; u < E; ++u) {
-                const int f = f0 + u * kThreads < total ? f0 + u * kThreads : f0;
-                const double* src = src0 + (int64_t)(f >> 8) * nkc * 256 + (f & 255);
+                for (int u = 0; u < E; ++u) {
+                    const int f = f0 + u * kThreads < total ? f0 + u * kThreads : f0;
+                    const double* src = src0 + (int64_t)(f >> 8) * nkc * 256 + (f & 255);
 #pragma unroll
-                for (int q = 0; q < kGramMaxKC; ++q)
-                    v[u][q] = src[(int64_t)(q < nkc ? q : 0) * 256];  // masked in the sum
+                    for (int q = 0; q < KG; ++q)  // masked in the sum
+                        v[u][q] = src[(int64_t)(q < nkc ? q : 0) * 256];
+                }
+                // uniform: same f0 in every thread
+                if (f0 == (int)threadIdx.x && stopped(st)) return;
+#pragma unroll
+                for (int u = 0; u < E; ++u) {
+                    const int f = f0 + u * kThreads;
+                    if (f >= total) continue;
+                    double sum = 0.0;
+#pragma unroll
+                    for (int q = 0; q < KG; ++q)
+                        if (q < nkc) sum += v[u][q];
+                    put(f, sum);
+                }
             }
-            if (f0 == (int)threadIdx.x && stopped(st)) return;  // uniform: same f0 in every thread
+        } else {
+            // many chunks: E entries, KG2 chunks per load round, in chunk order
+            constexpr int E = 4, KG2 = 16;
+            for (int f0 = threadIdx.x; f0 < total; f0 += E * kThreads) {
+                double sum[E];
 #pragma unroll
-            for (int u = 0; u < E; ++u) {
-                const int f = f0 + u * kThreads;
-                if (f >= total) continue;
-                double sum = 0.0;
+                for (int u = 0; u < E; ++u) sum[u] = 0.0;
+                for (int q0 = 0; q0 < nkc; q0 += KG2) {
+                    double v[E][KG2];
 #pragma unroll
-                for (int q = 0; q < kGramMaxKC; ++q)
-                    if (q < nkc) sum += v[u][q];
-                const int2 pr = sh.pairs[f >> 8];
-                const int t = f & 255;
-                const int a2 = pr.x * 16 + (t >> 4), b2 = pr.y * 16 + (t & 15);
-                // rows and columns beyond s come out of k_gram as zeros
-                G[a2 * (sp + 1) + b2] = sum;
-                G[b2 * (sp + 1) + a2] = sum;
+                    for (int u = 0; u < E; ++u) {
+                        const int f = f0 + u * kThreads < total ? f0 + u * kThreads : f0;
+                        const double* src = src0 + (int64_t)(f >> 8) * nkc * 256 + (f & 255);
+#pragma unroll
+                        for (int q = 0; q < KG2; ++q)
+                            v[u][q] = src[(int64_t)(q0 + q < nkc ? q0 + q : q0) * 256];
+                    }
+                    if (q0 == 0 && f0 == (int)threadIdx.x && stopped(st)) return;
+#pragma unroll
+                    for (int u = 0; u < E; ++u)
+#pragma unroll
+                        for (int q = 0; q < KG2; ++q)
+                            if (q0 + q < nkc) sum[u] += v[u][q];
+                }
+#pragma unroll
+                for (int u = 0; u < E; ++u)
+                    if (f0 + u * kThreads < total) put(f0 + u * kThreads, sum[u]);
             }
         }
     }
@@ -991,9 +1044,13 @@ __global__ __launch_bounds__(kThreads) void k_eig(Prob P, const double* __restri
             rn = block_sum<4>(rn, sh.red);
             if (rn <= rtol * rtol * tn) return 0;
             if (it >= limit) return 1;
-            if (allow_guard && m > r && it >= 4 && prev > 0.0 &&
-                (rn >= prev || log(rtol * rtol * tn / rn) < 30.0 * log(rn / prev)))
-                return 2;
+            if (allow_guard && m > r && it >= 4 && prev > 0.0) {
+                // more than 30 further steps at this contraction rho = rn / prev:
+                // rtol^2 tn / rn < rho^30 (a tiny rho underflows to 0: fast)
+                const double r2 = (rn / prev) * (rn / prev), r4 = r2 * r2, r8 = r4 * r4;
+                const double r30 = r8 * r8 * r8 * r4 * r2;
+                if (rn >= prev || rtol * rtol * tn < r30 * rn) return 2;
+            }
             prev = rn;
             double R[RP][RP], di[RP];
             if (!eig_chol<RP>(sh.mm, r, R, di)) {
@@ -1005,7 +1062,17 @@ __global__ __launch_bounds__(kThreads) void k_eig(Prob P, const double* __restri
     };
     int pr = plain(maxit, true);
     if (pr == 2) {
-        const int g = eig_guarded<RP>(G, sp, s, r, m, rtol, q, sh, steps);
+        __syncthreads();
+        if (act) {
+#pragma unroll
+            for (int p = 0; p < RP; ++p) sh.qs[a * RP + p] = q[p];
+        }
+        if (threadIdx.x == 0) sh.gsteps = 0;
+        __syncthreads();
+        const int g = eig_guarded<RP>(G, sp, s, r, m, rtol, &sh, &sh.gsteps);
+#pragma unroll
+        for (int p = 0; p < RP; ++p) q[p] = act ? sh.qs[a * RP + p] : 0.0;
+        steps += sh.gsteps;
         // a few plain steps from the Ritz vectors (or, after a breakdown of
         // the guarded iterate, the plain iterate) polish the basis and form
         // the T used below
@@ -1327,8 +1394,10 @@ __global__ __launch_bounds__(kThreads) void k_zcore(Prob P, const T* __restrict_
 // lanes stride the columns; k_bred adds the chunks' partial rows in order.
 // One extra workgroup finishes the core G from the slices of k_zcore.
 constexpr int kBfacKC = 1024;
+constexpr int kBfacMaxKC = 64;  // column chunks (partial rows) per entry at most
 
-template <typename T, int RP>
+// kSub: some mode stages several Z sub-chunks per work item (P.bsub > 1).
+template <typename T, int RP, bool kSub>
 __global__ __launch_bounds__(kThreads) void k_bfac(Prob P, const T* __restrict__ C,
                                                    const double* __restrict__ Zbuf,
                                                    const int4* __restrict__ items, int nitems,
@@ -1352,71 +1421,150 @@ __global__ __launch_bounds__(kThreads) void k_bfac(Prob P, const T* __restrict__
     const BlockDev& bd = P.blk[1 + i];
     const int m = bd.ncols, d = bd.nrows;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int c0 = kc * KC, cn = min(KC, m - c0);
-    const double* Zc = Zbuf + P.zoff[i] + (int64_t)c0 * RP;
-    const int xb = rb * kBfacRows + w * kBfacRowsPerWave;
-    const T* rowp[kBfacRowsPerWave];
-#pragma unroll
-    for (int j = 0; j < kBfacRowsPerWave; ++j)
-        rowp[j] = C + bd.off + (int64_t)(xb + j < d ? xb + j : d - 1) * m + c0;
-    constexpr int U = 8;
-    auto load_c = [&](T (&cv)[kBfacRowsPerWave][U], int u0) {
+    double acc[kBfacRowsPerWave][RP];
+    if constexpr (!kSub) {
+        const int c0 = kc * KC, cn = min(KC, m - c0);
+        const double* Zc = Zbuf + P.zoff[i] + (int64_t)c0 * RP;
+        const int xb = rb * kBfacRows + w * kBfacRowsPerWave;
+        const T* rowp[kBfacRowsPerWave];
 #pragma unroll
         for (int j = 0; j < kBfacRowsPerWave; ++j)
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int c = lane + 64 * (u0 + u);
-                cv[j][u] = rowp[j][c < cn ? c : 0];
-            }
-    };
-    // the first batch of C is in flight while the Z chunk is staged
-    T cv[kBfacRowsPerWave][U];
-    load_c(cv, 0);
-    {
-        // Z chunk -> LDS: every load of a thread issued before the stores
-        constexpr int ZE = KC * RP / kThreads;
-        double zv[ZE];
-#pragma unroll
-        for (int q = 0; q < ZE; ++q) {
-            const int e = tid + q * kThreads;
-            zv[q] = Zc[e < cn * RP ? e : 0];
-        }
-#pragma unroll
-        for (int q = 0; q < ZE; ++q) {
-            const int e = tid + q * kThreads;
-            zs[e] = e < cn * RP ? zv[q] : 0.0;
-        }
-    }
-    if (sf) return;
-    double acc[kBfacRowsPerWave][RP];
-#pragma unroll
-    for (int j = 0; j < kBfacRowsPerWave; ++j)
-#pragma unroll
-        for (int p = 0; p < RP; ++p) acc[j][p] = 0.0;
-    __syncthreads();
-    for (int u0 = 0; u0 < KC / 64; u0 += U) {
-        T cn_[kBfacRowsPerWave][U];
-        if (u0 + U < KC / 64) load_c(cn_, u0 + U);  // next batch in flight
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int c = lane + 64 * (u0 + u);
-            if (c < cn) {
-                double z[RP];
-#pragma unroll
-                for (int p = 0; p < RP; ++p) z[p] = zs[c * RP + p];
-#pragma unroll
-                for (int j = 0; j < kBfacRowsPerWave; ++j) {
-                    const double x = (double)cv[j][u];
-#pragma unroll
-                    for (int p = 0; p < RP; ++p) acc[j][p] = fma(x, z[p], acc[j][p]);
-                }
-            }
-        }
-        if (u0 + U < KC / 64) {
+            rowp[j] = C + bd.off + (int64_t)(xb + j < d ? xb + j : d - 1) * m + c0;
+        constexpr int U = 8;
+        auto load_c = [&](T (&cv)[kBfacRowsPerWave][U], int u0) {
 #pragma unroll
             for (int j = 0; j < kBfacRowsPerWave; ++j)
 #pragma unroll
-                for (int u = 0; u < U; ++u) cv[j][u] = cn_[j][u];
+                for (int u = 0; u < U; ++u) {
+                    const int c = lane + 64 * (u0 + u);
+                    cv[j][u] = rowp[j][c < cn ? c : 0];
+                }
+        };
+        // the first batch of C is in flight while the Z chunk is staged
+        T cv[kBfacRowsPerWave][U];
+        load_c(cv, 0);
+        {
+            // Z chunk -> LDS: every load of a thread issued before the stores
+            constexpr int ZE = KC * RP / kThreads;
+            double zv[ZE];
+#pragma unroll
+            for (int q = 0; q < ZE; ++q) {
+                const int e = tid + q * kThreads;
+                zv[q] = Zc[e < cn * RP ? e : 0];
+            }
+#pragma unroll
+            for (int q = 0; q < ZE; ++q) {
+                const int e = tid + q * kThreads;
+                zs[e] = e < cn * RP ? zv[q] : 0.0;
+            }
+        }
+        if (sf) return;
+#pragma unroll
+        for (int j = 0; j < kBfacRowsPerWave; ++j)
+#pragma unroll
+            for (int p = 0; p < RP; ++p) acc[j][p] = 0.0;
+        __syncthreads();
+        for (int u0 = 0; u0 < KC / 64; u0 += U) {
+            T cn_[kBfacRowsPerWave][U];
+            if (u0 + U < KC / 64) load_c(cn_, u0 + U);  // next batch in flight
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int c = lane + 64 * (u0 + u);
+                if (c < cn) {
+                    double z[RP];
+#pragma unroll
+                    for (int p = 0; p < RP; ++p) z[p] = zs[c * RP + p];
+#pragma unroll
+                    for (int j = 0; j < kBfacRowsPerWave; ++j) {
+                        const double x = (double)cv[j][u];
+#pragma unroll
+                        for (int p = 0; p < RP; ++p) acc[j][p] = fma(x, z[p], acc[j][p]);
+                    }
+                }
+            }
+            if (u0 + U < KC / 64) {
+#pragma unroll
+                for (int j = 0; j < kBfacRowsPerWave; ++j)
+#pragma unroll
+                    for (int u = 0; u < U; ++u) cv[j][u] = cn_[j][u];
+            }
+        }
+    } else {
+        const int xb = rb * kBfacRows + w * kBfacRowsPerWave;
+        const int nsub = P.bsub[i];
+        for (int sc = 0; sc < nsub; ++sc) {
+            const int c0 = (kc * nsub + sc) * KC;
+            if (c0 >= m) break;  // uniform
+            const int cn = min(KC, m - c0);
+            const double* Zc = Zbuf + P.zoff[i] + (int64_t)c0 * RP;
+            const T* rowp[kBfacRowsPerWave];
+#pragma unroll
+            for (int j = 0; j < kBfacRowsPerWave; ++j)
+                rowp[j] = C + bd.off + (int64_t)(xb + j < d ? xb + j : d - 1) * m + c0;
+            constexpr int U = 8;
+            auto load_c = [&](T (&cv)[kBfacRowsPerWave][U], int u0) {
+#pragma unroll
+                for (int j = 0; j < kBfacRowsPerWave; ++j)
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const int c = lane + 64 * (u0 + u);
+                        cv[j][u] = rowp[j][c < cn ? c : 0];
+                    }
+            };
+            // the first batch of C is in flight while the Z chunk is staged
+            T cv[kBfacRowsPerWave][U];
+            load_c(cv, 0);
+            {
+                // Z chunk -> LDS: every load of a thread issued before the stores
+                constexpr int ZE = KC * RP / kThreads;
+                double zv[ZE];
+#pragma unroll
+                for (int q = 0; q < ZE; ++q) {
+                    const int e = tid + q * kThreads;
+                    zv[q] = Zc[e < cn * RP ? e : 0];
+                }
+#pragma unroll
+                for (int q = 0; q < ZE; ++q) {
+                    const int e = tid + q * kThreads;
+                    zs[e] = e < cn * RP ? zv[q] : 0.0;
+                }
+            }
+            if (sf) return;
+            if (sc == 0) {
+                // zeroed after the first staging: one sub-chunk keeps the
+                // accumulators out of the staging's registers
+#pragma unroll
+                for (int j = 0; j < kBfacRowsPerWave; ++j)
+#pragma unroll
+                    for (int p = 0; p < RP; ++p) acc[j][p] = 0.0;
+            }
+            __syncthreads();
+            for (int u0 = 0; u0 < KC / 64; u0 += U) {
+                T cn_[kBfacRowsPerWave][U];
+                if (u0 + U < KC / 64) load_c(cn_, u0 + U);  // next batch in flight
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int c = lane + 64 * (u0 + u);
+                    if (c < cn) {
+                        double z[RP];
+#pragma unroll
+                        for (int p = 0; p < RP; ++p) z[p] = zs[c * RP + p];
+#pragma unroll
+                        for (int j = 0; j < kBfacRowsPerWave; ++j) {
+                            const double x = (double)cv[j][u];
+#pragma unroll
+                            for (int p = 0; p < RP; ++p) acc[j][p] = fma(x, z[p], acc[j][p]);
+                        }
+                    }
+                }
+                if (u0 + U < KC / 64) {
+#pragma unroll
+                    for (int j = 0; j < kBfacRowsPerWave; ++j)
+#pragma unroll
+                        for (int u = 0; u < U; ++u) cv[j][u] = cn_[j][u];
+                }
+            }
+            __syncthreads();  // the next sub-chunk overwrites zs
         }
     }
 #pragma unroll
@@ -1456,15 +1604,17 @@ __global__ __launch_bounds__(kThreads) void k_bred(Prob P, const double* __restr
     const int rb = x / kBfacRows, xr = x % kBfacRows;
     const int nkc = P.bnkc[i];
     const double* src = bpart + ((int64_t)(P.bitem0[i] + rb * nkc) * kBfacRows + xr) * RP + p;
-    double v[16];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) v[q] = src[(int64_t)(q < nkc ? q : 0) * kBfacRows * RP];
-    if (sf) return;
     double sum = 0.0;
+    for (int q0 = 0; q0 < nkc; q0 += 16) {  // 16 loads in flight, added in order
+        double v[16];
 #pragma unroll
-    for (int q = 0; q < 16; ++q)
-        if (q < nkc) sum += v[q];
-    for (int q = 16; q < nkc; ++q) sum += src[(int64_t)q * kBfacRows * RP];
+        for (int q = 0; q < 16; ++q)
+            v[q] = src[(int64_t)(q0 + q < nkc ? q0 + q : q0) * kBfacRows * RP];
+        if (sf) return;
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+            if (q0 + q < nkc) sum += v[q];
+    }
     Bf[P.boff[i] + (int64_t)x * RP + p] = (T)sum;
     Bd[P.boff[i] + (int64_t)x * RP + p] = sum;
 }
@@ -1473,8 +1623,145 @@ __global__ __launch_bounds__(kThreads) void k_bred(Prob P, const double* __restr
 // For every column of a block (or, with a negative block id, every column of
 // the full mode-`dense_mode` unfolding), H[p][c] = sum over the other modes'
 // core indices of G[..p..] * prod_j B_j[idx_j(c)][q_j].  G sits in LDS
-// permuted so that the block's own mode comes first (at the true ranks);
-// each thread's B rows sit in LDS too, so the loops run to the true ranks.
+// permuted so that the block's own mode comes first (at the true ranks).
+// k_hexp contracts per column with each thread's B rows in LDS, so the loops
+// run to the true ranks.  k_hexp_fac serves three or more modes with columns
+// that come in runs sharing every other-mode index but the last (R, chidori
+// blocks, the dense unfolding) and a long per-column contraction: per run,
+// T[p][z] = sum over the leading other-mode core indices of G[..p..z] *
+// prod B (in LDS), then per column H[p][c] = sum_z T[p][z] B_last[idx_last(c)][z].
+constexpr int kHexpFactorMin = 256;  // prod r_i above which k_hexp_fac is used
+
+template <typename T, int RP, int N>
+__global__ __launch_bounds__(kThreads) void k_hexp_fac(
+    Prob P, const int2* __restrict__ tiles, const T* __restrict__ Bf,
+    const double* __restrict__ Gd, T* __restrict__ H, const DevState* st,
+    int dense_mode, int64_t dense_cols) {
+    const int sf = st ? stop_flag(st) : 0;
+    constexpr int GPAD = N == 2 ? RP * RP : (N == 3 ? RP * RP * RP : RP * RP * RP * RP);
+    constexpr int GP = GPAD < kMaxCore ? GPAD : kMaxCore;
+    __shared__ double gp[GP];
+    __shared__ double vs[RP * (kThreads + 2 * RP)];  // the runs' T
+    const int2 tl = tiles[blockIdx.x];
+    const bool dense = tl.x < 0;
+    const int mode = dense ? dense_mode : P.blk[tl.x].mode;
+    const int64_t ncols = dense ? dense_cols : P.blk[tl.x].ncols;
+    int others[kMaxModes - 1] = {0, 0, 0};
+    int no = 0;
+    for (int j = 0; j < N; ++j)
+        if (j != mode) others[no++] = j;
+    const int rm = P.r[mode];
+    const int r0 = P.r[others[0]];
+    const int r1 = N >= 3 ? P.r[others[1]] : 1;
+    const int r2 = N >= 4 ? P.r[others[2]] : 1;
+    // permuted core at the true ranks: gp[((p*r0 + q)*r1 + u)*r2 + z] = G[...]
+    // with p at `mode` and q, u, z at the other modes in increasing order
+    int gstr[kMaxModes];
+    gstr[N - 1] = 1;
+    for (int j = N - 2; j >= 0; --j) gstr[j] = gstr[j + 1] * P.r[j + 1];
+    const int gcount = rm * r0 * r1 * r2;
+    for (int e = threadIdx.x; e < gcount; e += kThreads) {
+        int rem = e;
+        const int z = rem % r2;
+        rem /= r2;
+        const int u = rem % r1;
+        rem /= r1;
+        const int q = rem % r0;
+        const int p = rem / r0;
+        int off = p * gstr[mode] + q * gstr[others[0]];
+        if (N >= 3) off += u * gstr[others[1]];
+        if (N >= 4) off += z * gstr[others[2]];
+        gp[e] = Gd[off];
+    }
+    const int tid = threadIdx.x;
+    const int64_t c = (int64_t)tl.y * kThreads + tid;
+    const int64_t cc = c < ncols ? c : ncols - 1;
+    const int plen = dense ? P.d[others[N - 2]] : P.blk[tl.x].plen;
+    {
+        if (sf) return;  // uniform
+        const int rl = P.r[others[N - 2]];          // rank of the last other mode
+        const int64_t c0 = (int64_t)tl.y * kThreads;
+        const int64_t g0 = c0 / plen;
+        const int64_t cl = (c0 + kThreads < ncols ? c0 + kThreads : ncols) - 1;
+        const int npre = (int)(cl / plen - g0 + 1);
+        double* Tb = vs;  // [npre][rm][rl]: at most RP (256 + 2 RP) doubles
+        const int nt = npre * rm * rl;
+        // the rows of the leading other modes at a column
+        auto lead_rows = [&](int64_t col, int64_t (&ro)[kMaxModes - 1]) {
+            if (dense) {
+                int64_t rem = col / plen;
+                for (int q = N - 3; q >= 0; --q) {
+                    const int j = others[q];
+                    ro[q] = P.boff[j] + (rem % P.d[j]) * RP;
+                    rem /= P.d[j];
+                }
+            } else {
+                const BlockDev& bd = P.blk[tl.x];
+                for (int q = 0; q < N - 2; ++q)
+                    ro[q] = P.boff[others[q]] + (int64_t)bd.cidx[(int64_t)q * ncols + col] * RP;
+            }
+        };
+        __syncthreads();  // gp staged
+        for (int e = tid; e < nt; e += kThreads) {
+            const int z = e % rl;
+            const int p = (e / rl) % rm;
+            const int g = e / (rl * rm);
+            int64_t ro[kMaxModes - 1] = {0, 0, 0};
+            lead_rows((g0 + g) * plen, ro);
+            double b0[RP], b1[RP];
+#pragma unroll
+            for (int k = 0; k < RP; ++k) {
+                b0[k] = (double)Bf[ro[0] + k];
+                b1[k] = N >= 4 ? (double)Bf[ro[1] + k] : 0.0;
+            }
+            double t = 0.0;
+            if constexpr (N == 3) {
+                // gp[(p*r0 + q)*r1 + z], z at the last other mode
+#pragma unroll
+                for (int q = 0; q < RP; ++q)
+                    if (q < r0) t = fma(gp[(p * r0 + q) * r1 + z], b0[q], t);
+            } else {
+#pragma unroll
+                for (int q = 0; q < RP; ++q) {
+                    if (q < r0) {
+                        double t1 = 0.0;
+#pragma unroll
+                        for (int u = 0; u < RP; ++u)
+                            if (u < r1) t1 = fma(gp[((p * r0 + q) * r1 + u) * r2 + z], b1[u], t1);
+                        t = fma(t1, b0[q], t);
+                    }
+                }
+            }
+            Tb[e] = t;
+        }
+        // this column's row of the last other mode
+        int64_t rlast;
+        if (dense) {
+            rlast = P.boff[others[N - 2]] + (cc % plen) * RP;
+        } else {
+            const BlockDev& bd = P.blk[tl.x];
+            rlast = P.boff[others[N - 2]] +
+                    (int64_t)bd.cidx[(int64_t)(N - 2) * ncols + cc] * RP;
+        }
+        double bl[RP];
+#pragma unroll
+        for (int k = 0; k < RP; ++k) bl[k] = (double)Bf[rlast + k];
+        __syncthreads();
+        const double* Tg = Tb + (int)(cc / plen - g0) * rm * rl;
+        const int64_t hoff = dense ? 0 : P.blk[tl.x].hoff;
+        for (int p = 0; p < RP; ++p) {
+            double a = 0.0;
+            if (p < rm) {
+#pragma unroll
+                for (int z = 0; z < RP; ++z)
+                    if (z < rl) a = fma(Tg[p * rl + z], bl[z], a);
+            }
+            if (c < ncols) H[hoff + (int64_t)p * ncols + c] = (T)a;
+        }
+        return;
+    }
+}
+
 template <typename T, int RP, int N>
 __global__ __launch_bounds__(kThreads) void k_hexp(
     Prob P, const int2* __restrict__ tiles, const T* __restrict__ Bf,

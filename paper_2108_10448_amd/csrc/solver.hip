@@ -237,6 +237,12 @@ static void plan(Impl& im, const Shape& sh, int esize, size_t idx_bytes, int max
             bd.ncols = (int)sh.m[b - 1];
         }
         bd.r = sh.r[bd.mode];
+        {
+            // the columns run over the other modes in C order (last fastest)
+            // for R and for chidori blocks
+            const int last = bd.mode == n - 1 ? n - 2 : n - 1;
+            bd.plen = (b == 0 || sh.chidori) ? (int)sh.s[last] : 0;
+        }
         bd.off = off;
         bd.hoff = hoff;
         bd.moff = moff;
@@ -276,8 +282,11 @@ static void plan(Impl& im, const Shape& sh, int esize, size_t idx_bytes, int max
     int pid = 0;
     for (int i = 0; i < n; ++i) {
         const int nt = (int)((sh.s[i] + 15) / 16);
+        // at least kGramMinChunk columns per chunk; at most kGramMaxKC chunks,
+        // and about 1024 tiles per mode for the eigensolver to add up
+        const int npi = nt * (nt + 1) / 2;
         int nkc = (int)std::min<int64_t>(kGramMaxKC, (sh.m[i] + kGramMinChunk - 1) / kGramMinChunk);
-        nkc = std::max(1, nkc);
+        nkc = std::max(1, std::min(nkc, std::max(kGramKCGroup, 1024 / npi)));
         const int chunk = (int)align_up((size_t)((sh.m[i] + nkc - 1) / nkc), 256);
         P.gitem0[i] = (int)im.gram_items.size();
         P.gnkc[i] = nkc;
@@ -296,9 +305,14 @@ static void plan(Impl& im, const Shape& sh, int esize, size_t idx_bytes, int max
     const int bkc = RP <= 8 ? kBfacKC : kBfacKC / 2;
     for (int i = 0; i < n; ++i) {
         for (int64_t c0 = 0; c0 < sh.m[i]; c0 += 64) im.z_tiles.push_back(make_int2(i, (int)c0));
-        const int nkc = (int)((sh.m[i] + bkc - 1) / bkc);
+        // at most kBfacMaxKC partial rows per entry for k_bred: long modes
+        // stage several Z sub-chunks per work item
+        const int nsc = (int)((sh.m[i] + bkc - 1) / bkc);
+        const int nsub = (nsc + kBfacMaxKC - 1) / kBfacMaxKC;
+        const int nkc = (nsc + nsub - 1) / nsub;
         P.bitem0[i] = (int)im.bfac_items.size();
         P.bnkc[i] = nkc;
+        P.bsub[i] = nsub;
         for (int rb = 0; rb * kBfacRows < sh.d[i]; ++rb, ++im.n_bgroups)
             for (int kc = 0; kc < nkc; ++kc)
                 im.bfac_items.push_back(make_int4(i, rb, kc, im.n_bgroups));
@@ -352,6 +366,38 @@ static void plan(Impl& im, const Shape& sh, int esize, size_t idx_bytes, int max
 }
 
 // ------------------------------------------------------------ the solver
+
+// H_b expansion launch: the run-factored kernel when the columns come in
+// runs and the per-column contraction (prod r_i) is long, else the
+// per-column one.
+template <typename T, int RP>
+static void launch_hexp(const Prob& P, bool runs, unsigned grid, hipStream_t st,
+                        const int2* tiles, const T* Bf, const double* Gd, T* H,
+                        const DevState* ds, int dense_mode, int64_t dense_cols) {
+    const bool fac = P.n >= 3 && runs && P.core > kHexpFactorMin;
+    switch (P.n) {
+        case 2:
+            hipLaunchKernelGGL((k_hexp<T, RP, 2>), dim3(grid), dim3(kThreads), 0, st, P, tiles,
+                               Bf, Gd, H, ds, dense_mode, dense_cols);
+            break;
+        case 3:
+            if (fac)
+                hipLaunchKernelGGL((k_hexp_fac<T, RP, 3>), dim3(grid), dim3(kThreads), 0, st, P,
+                                   tiles, Bf, Gd, H, ds, dense_mode, dense_cols);
+            else
+                hipLaunchKernelGGL((k_hexp<T, RP, 3>), dim3(grid), dim3(kThreads), 0, st, P,
+                                   tiles, Bf, Gd, H, ds, dense_mode, dense_cols);
+            break;
+        default:
+            if (fac)
+                hipLaunchKernelGGL((k_hexp_fac<T, RP, 4>), dim3(grid), dim3(kThreads), 0, st, P,
+                                   tiles, Bf, Gd, H, ds, dense_mode, dense_cols);
+            else
+                hipLaunchKernelGGL((k_hexp<T, RP, 4>), dim3(grid), dim3(kThreads), 0, st, P,
+                                   tiles, Bf, Gd, H, ds, dense_mode, dense_cols);
+            break;
+    }
+}
 
 template <typename T, int RP>
 struct Runner {
@@ -443,23 +489,9 @@ struct Runner {
     int hexp() {
         HIPCHK(pb(PK_HEXP));
         const unsigned nt = (unsigned)im.h_tiles.size();
-        switch (im.P.n) {
-            case 2:
-                hipLaunchKernelGGL((k_hexp<T, RP, 2>), dim3(nt), dim3(kThreads), 0, s, im.P,
-                                   im.d_h_tiles, (const T*)im.Bf, im.Gd, (T*)im.H, im.st, 0,
-                                   (int64_t)0);
-                break;
-            case 3:
-                hipLaunchKernelGGL((k_hexp<T, RP, 3>), dim3(nt), dim3(kThreads), 0, s, im.P,
-                                   im.d_h_tiles, (const T*)im.Bf, im.Gd, (T*)im.H, im.st, 0,
-                                   (int64_t)0);
-                break;
-            default:
-                hipLaunchKernelGGL((k_hexp<T, RP, 4>), dim3(nt), dim3(kThreads), 0, s,
-                                   im.P, im.d_h_tiles, (const T*)im.Bf, im.Gd, (T*)im.H,
-                                   im.st, 0, (int64_t)0);
-                break;
-        }
+        // every block comes in column runs only under chidori sampling
+        launch_hexp<T, RP>(im.P, h->shape.chidori, nt, s, im.d_h_tiles, (const T*)im.Bf,
+                           im.Gd, (T*)im.H, im.st, 0, 0);
         HIPCHK(hipGetLastError());
         HIPCHK(pe());
         return 0;
@@ -503,9 +535,16 @@ struct Runner {
         HIPCHK(pe());
         HIPCHK(pb(PK_BFAC));
         const int nb = (int)im.bfac_items.size();
-        hipLaunchKernelGGL((k_bfac<T, RP>), dim3(nb + 1), dim3(kThreads), 0, s, P, C,
-                           (const double*)im.Z, im.d_bfac_items, nb, im.bpart,
-                           (const double*)im.W, (const double*)im.Tc, im.Gd, im.st);
+        bool sub = false;
+        for (int i = 0; i < n; ++i) sub = sub || P.bsub[i] > 1;
+        if (sub)
+            hipLaunchKernelGGL((k_bfac<T, RP, true>), dim3(nb + 1), dim3(kThreads), 0, s, P, C,
+                               (const double*)im.Z, im.d_bfac_items, nb, im.bpart,
+                               (const double*)im.W, (const double*)im.Tc, im.Gd, im.st);
+        else
+            hipLaunchKernelGGL((k_bfac<T, RP, false>), dim3(nb + 1), dim3(kThreads), 0, s, P, C,
+                               (const double*)im.Z, im.d_bfac_items, nb, im.bpart,
+                               (const double*)im.W, (const double*)im.Tc, im.Gd, im.st);
         HIPCHK(hipGetLastError());
         HIPCHK(pe());
         HIPCHK(pb(PK_BRED));
@@ -863,23 +902,8 @@ static int dense_h(rtcur_s* h, Impl& im, int64_t ncols, T** Hf_out) {
     for (int64_t q = 0; q < ntile; ++q) tl[q] = make_int2(-1, (int)q);
     HIPCHK(hipMemcpyAsync(tiles, tl.data(), sizeof(int2) * ntile, hipMemcpyHostToDevice,
                           h->stream));
-    switch (P.n) {
-        case 2:
-            hipLaunchKernelGGL((k_hexp<T, RP, 2>), dim3((unsigned)ntile), dim3(kThreads), 0,
-                               h->stream, P, tiles, (const T*)im.Bf, im.Gd, Hf,
-                               (DevState*)nullptr, 0, ncols);
-            break;
-        case 3:
-            hipLaunchKernelGGL((k_hexp<T, RP, 3>), dim3((unsigned)ntile), dim3(kThreads), 0,
-                               h->stream, P, tiles, (const T*)im.Bf, im.Gd, Hf,
-                               (DevState*)nullptr, 0, ncols);
-            break;
-        default:
-            hipLaunchKernelGGL((k_hexp<T, RP, 4>), dim3((unsigned)ntile), dim3(kThreads), 0,
-                               h->stream, P, tiles, (const T*)im.Bf, im.Gd, Hf,
-                               (DevState*)nullptr, 0, ncols);
-            break;
-    }
+    launch_hexp<T, RP>(P, true, (unsigned)ntile, h->stream, tiles, (const T*)im.Bf, im.Gd, Hf,
+                       (const DevState*)nullptr, 0, ncols);
     HIPCHK(hipGetLastError());
     *Hf_out = Hf;
     return 0;
