@@ -240,6 +240,8 @@ def main():
                     help="minimum host time spent on the oracle baseline")
     ap.add_argument("--side-steps", type=int, default=5,
                     help="timed solves for the float64 and RTCUR-R rows (0: skip them)")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the 64-instance batch side row")
     ap.add_argument("--no-video", action="store_true",
                     help="skip the video-shaped 4-mode side rows")
     ap.add_argument("--copy-calib", action="store_true",
@@ -368,6 +370,54 @@ def main():
         del Xv, Lv, planted, vin
         torch.cuda.empty_cache()
 
+    # ---- a batch of 64 independent instances of uneven shapes and ranks
+    batch = None
+    if args.side_steps > 0 and not args.no_batch:
+        log("generating the 64-instance batch")
+        specs = synth.batch_specs()
+        Xb, Ib, rb, sb = [], [], [], []
+        for sp in specs:
+            ib = synth.tucker_plus_sparse(sp["dims"], sp["ranks"], sp["alpha"], seed=sp["seed"],
+                                          storage=np.float32, keep_parts=False)
+            Xb.append(torch.from_numpy(ib.X).to("cuda:0"))
+            Ib.append(synth.sample_sizes(sp["dims"], sp["ranks"], 3.0)[0])
+            rb.append(sp["ranks"])
+            sb.append(sp["seed"])
+            del ib
+        nh = 4
+        streams = [torch.cuda.Stream() for _ in range(nh)]
+        hs = [rt.create(0, stream=st, dtype=torch.float32) for st in streams]
+        rt.solve_batch(hs, Xb, rb, Ib, seeds=sb, check=False)   # warm-up pass
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        binfos, _ = rt.solve_batch(hs, Xb, rb, Ib, seeds=sb, check=False)
+        torch.cuda.synchronize()
+        t_batch = time.perf_counter() - t0
+        for hh in hs:
+            rt.destroy(hh)
+        h1 = rt.create(0, dtype=torch.float32)
+        single = []
+        for j in range(len(Xb)):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            rt.solve(h1, Xb[j], rb[j], Ib[j], seed=sb[j], check=False)
+            torch.cuda.synchronize()
+            single.append(time.perf_counter() - t1)
+        rt.destroy(h1)
+        batch = {"workload": "64 independent 3-mode float32 tensors, d_i ~ U{64..256}, "
+                             "r_i ~ U{2..8}, alpha ~ U[0.1, 0.4], RTCUR-F, upsilon 3, tol 1e-5",
+                 "handles": nh, "batch_ms": 1e3 * t_batch,
+                 "tensors_per_s": len(Xb) / t_batch,
+                 "one_by_one_ms": 1e3 * sum(single),
+                 "one_by_one_tensors_per_s": len(Xb) / sum(single),
+                 "single_solve_ms_p50": 1e3 * percentile(single, 0.5),
+                 "single_solve_ms_p99": 1e3 * percentile(single, 0.99),
+                 "converged": sum(1 for i in binfos if i.converged),
+                 "iters_total": sum(i.iters for i in binfos)}
+        del Xb
+        torch.cuda.empty_cache()
+        log(f"batch: {batch}")
+
     # ---- per-kernel figures
     def figures(name, ms, cnt, nsolve, eig_steps):
         work = work_per_solve(list(inst.dims), I, ranks, 4, K, eig_steps)
@@ -462,6 +512,7 @@ def main():
         "variants": rows,
         "outliers_full_grid": outlier_row,
         "video": video,
+        "batch": batch,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernels": kernels,

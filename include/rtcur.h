@@ -128,6 +128,36 @@ int rtcur_reconstruct(rtcur_t h, void* L_out, int out_dtype);
 int rtcur_outliers(rtcur_t h, const void* X, int x_dtype, double zeta, void* S_out,
                    void* L_out, int out_dtype);
 
+/* Many independent instances (a batch of tensors of uneven shapes and
+ * ranks), solved concurrently: instance j runs on handle hs[j % nh], each
+ * handle driven by its own host thread, so handles bound to distinct streams
+ * overlap their kernels on the device; the instances of one handle run in
+ * increasing j.  Each instance is Algorithm 1 exactly as rtcur_solve runs it
+ * (same results bit for bit).
+ *   hs, nh     nh >= 1 distinct handles (their variant and compute dtype
+ *              apply); after the call each holds its last instance's state
+ *   count      number of instances (>= 0)
+ *   X[j]       device tensor of instance j, x_dtype, C-contiguous, read-only
+ *   n[j]       its number of modes; dims, ranks, I_sizes (and J_sizes when
+ *              not NULL; NULL = chidori for all) hold 4 entries per instance
+ *              (entries beyond n[j] ignored): dims[4j .. 4j+n[j])
+ *   zeta0      NULL (max|X| for all) or count values (<= 0: max|X|)
+ *   gamma, tol, max_iter   shared, as in rtcur_solve
+ *   seeds[j]   sampler seed of instance j
+ *   L_out      NULL, or count device pointers (NULL entries skipped) that
+ *              receive instance j's full L (prod dims elements, out_dtype)
+ *   infos      NULL or count summaries; status[j] = rtcur_solve's result for
+ *              instance j (or rtcur_reconstruct's error)
+ * Returns the first error status by j, else RTCUR_NOT_CONVERGED if any
+ * instance did not converge, else RTCUR_OK; RTCUR_E_INVAL for bad arguments
+ * (NULL arrays, repeated handles) before any work. */
+int rtcur_solve_batch(rtcur_t* hs, int32_t nh, int32_t count, const void* const* X,
+                      int x_dtype, const int32_t* n, const int64_t* dims,
+                      const int32_t* ranks, const int64_t* I_sizes, const int64_t* J_sizes,
+                      const double* zeta0, double gamma, double tol, int32_t max_iter,
+                      const uint64_t* seeds, void* const* L_out, int out_dtype,
+                      rtcur_info* infos, int32_t* status);
+
 /* Release the handle and its device workspace.  NULL-safe. */
 int rtcur_destroy(rtcur_t h);
 

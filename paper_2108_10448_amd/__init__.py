@@ -38,7 +38,7 @@ SYMBOLS = ["rtcur_create", "rtcur_solve", "rtcur_reconstruct", "rtcur_outliers",
            "rtcur_destroy",
            "rtcur_get_indices", "rtcur_get_history", "rtcur_get_block",
            "rtcur_get_tucker", "rtcur_sample", "rtcur_set_profiling",
-           "rtcur_get_profile", "rtcur_strerror", "rtcur_last_error"]
+           "rtcur_get_profile", "rtcur_strerror", "rtcur_last_error", "rtcur_solve_batch"]
 
 
 class RtcurInfo(ctypes.Structure):
@@ -79,6 +79,12 @@ def lib() -> ctypes.CDLL:
                               ctypes.POINTER(ctypes.c_int32), p64, p64, dbl, dbl,
                               dbl, i32, u64, ctypes.POINTER(RtcurInfo)]
     L.rtcur_reconstruct.argtypes = [vp, vp, ctypes.c_int]
+    L.rtcur_solve_batch.argtypes = [ctypes.POINTER(vp), i32, i32, ctypes.POINTER(vp),
+                                    ctypes.c_int, ctypes.POINTER(ctypes.c_int32), p64,
+                                    ctypes.POINTER(ctypes.c_int32), p64, p64, pd, dbl, dbl,
+                                    i32, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(vp),
+                                    ctypes.c_int, ctypes.POINTER(RtcurInfo),
+                                    ctypes.POINTER(ctypes.c_int32)]
     L.rtcur_outliers.argtypes = [vp, vp, ctypes.c_int, dbl, vp, vp, ctypes.c_int]
     L.rtcur_destroy.argtypes = [vp]
     L.rtcur_get_indices.argtypes = [vp, i32, i32, p64, i64, p64]
@@ -237,6 +243,71 @@ def solve(h: Handle, X, ranks: Sequence[int], I_sizes: Optional[Sequence[int]] =
         warnings.warn(f"RTCUR did not reach tol in {max_iter} iterations (e={info.err:.3e})")
     return Info(rc, info.iters, bool(info.converged), info.err, info.zeta, info.zeta0,
                 info.eig_steps, info.eig_unconverged)
+
+
+def solve_batch(handles: Sequence[Handle], Xs, ranks, I_sizes=None, J_sizes=None, *,
+                upsilon: float = 3.0, zeta0=None, gamma: float = 0.7, tol: float = 1e-5,
+                max_iter: int = 100, seeds=None, with_L: bool = False, L_dtype=None,
+                check: bool = True):
+    """rtcur_solve_batch: instance j (device tensor Xs[j], ranks[j], I_sizes[j]
+    (default upsilon sizes), J_sizes[j] or chidori) on handles[j % len(handles)],
+    one host thread per handle.  All Xs share one dtype.  Returns (infos, Ls)
+    with Ls the full reconstructions when with_L, else None."""
+    torch = _torch()
+    count = len(Xs)
+    if count == 0:
+        return [], ([] if with_L else None)
+    if len(ranks) != count:
+        raise ValueError("one rank tuple per instance")
+    dt = Xs[0].dtype
+    for X in Xs:
+        if not isinstance(X, torch.Tensor) or not X.is_cuda or not X.is_contiguous():
+            raise TypeError("every X must be a C-contiguous device torch.Tensor")
+        if X.dtype != dt or dt not in (torch.float32, torch.float64):
+            raise TypeError("every X must have the same float32/float64 dtype")
+    K = 4
+    dims = (ctypes.c_int64 * (K * count))()
+    rk = (ctypes.c_int32 * (K * count))()
+    Is = (ctypes.c_int64 * (K * count))()
+    Js = (ctypes.c_int64 * (K * count))() if J_sizes is not None else None
+    nn = (ctypes.c_int32 * count)()
+    for j, X in enumerate(Xs):
+        d = list(X.shape)
+        nn[j] = len(d)
+        Ij = I_sizes[j] if I_sizes is not None else default_sizes(d, ranks[j], upsilon)[0]
+        for q in range(len(d)):
+            dims[K * j + q] = d[q]
+            rk[K * j + q] = int(ranks[j][q])
+            Is[K * j + q] = int(Ij[q])
+            if Js is not None:
+                Js[K * j + q] = int(J_sizes[j][q])
+    xs = (ctypes.c_void_p * count)(*[X.data_ptr() for X in Xs])
+    z0 = (ctypes.c_double * count)(*[float(z) if z else 0.0 for z in zeta0]) \
+        if zeta0 is not None else None
+    sd = (ctypes.c_uint64 * count)(*[int(s) & ((1 << 64) - 1) for s in
+                                     (seeds if seeds is not None else range(count))])
+    Ls = None
+    lo = None
+    odt = L_dtype or dt
+    if with_L:
+        Ls = [torch.empty(X.shape, dtype=odt, device=X.device) for X in Xs]
+        lo = (ctypes.c_void_p * count)(*[L.data_ptr() for L in Ls])
+    hs = (ctypes.c_void_p * len(handles))(*[h.ptr for h in handles])
+    infos = (RtcurInfo * count)()
+    st = (ctypes.c_int32 * count)()
+    rc = lib().rtcur_solve_batch(hs, len(handles), count, xs,
+                                 F64 if dt == torch.float64 else F32, nn, dims, rk, Is, Js,
+                                 z0, float(gamma), float(tol), int(max_iter), sd, lo,
+                                 F64 if odt == torch.float64 else F32, infos, st)
+    for j, X in enumerate(Xs):
+        h = handles[j % len(handles)]
+        h.dims, h.ranks = list(X.shape), list(ranks[j])
+    if rc < 0 and check:
+        raise RTCURError(rc, f"rtcur_solve_batch: {strerror(rc)}")
+    out = [Info(st[j], infos[j].iters, bool(infos[j].converged), infos[j].err,
+                infos[j].zeta, infos[j].zeta0, infos[j].eig_steps, infos[j].eig_unconverged)
+           for j in range(count)]
+    return out, Ls
 
 
 def reconstruct(h: Handle, out=None, dtype=None):

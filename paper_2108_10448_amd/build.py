@@ -31,7 +31,7 @@ def _hipcc() -> str:
 
 
 def _flags():
-    return ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+    return ["-O3", "-std=c++17", "-fPIC", "-pthread", f"--offload-arch={ARCH}",
             "-I", os.path.join(ROOT, "include"), "-I", CSRC,
             "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
             # packed-FP32 instructions off for all device code
@@ -64,7 +64,7 @@ def build(verbose: bool = False) -> str:
         if p.returncode != 0:
             raise RuntimeError("compile failed: " + " ".join(cmd))
     tmp = LIB + ".tmp"
-    link = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    link = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread", "-o", tmp, *objs]
     p = subprocess.run(link, capture_output=True, text=True)
     if p.returncode != 0:
         sys.stderr.write(p.stdout + p.stderr)

@@ -5,6 +5,8 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <thread>
+#include <vector>
 
 #include "internal.h"
 
@@ -146,6 +148,56 @@ int rtcur_outliers(rtcur_t h, const void* X, int x_dtype, double zeta, void* S_o
         return fail(h, RTCUR_E_INVAL, "out_dtype must be RTCUR_F64 or RTCUR_F32");
     if (!std::isfinite(zeta)) return fail(h, RTCUR_E_INVAL, "zeta must be finite");
     return rtcur::outliers(h, X, x_dtype, zeta, S_out, L_out, out_dtype);
+}
+
+int rtcur_solve_batch(rtcur_t* hs, int32_t nh, int32_t count, const void* const* X,
+                      int x_dtype, const int32_t* n, const int64_t* dims,
+                      const int32_t* ranks, const int64_t* I_sizes, const int64_t* J_sizes,
+                      const double* zeta0, double gamma, double tol, int32_t max_iter,
+                      const uint64_t* seeds, void* const* L_out, int out_dtype,
+                      rtcur_info* infos, int32_t* status) {
+    if (!hs || nh < 1 || count < 0 || (count > 0 && (!X || !n || !dims || !ranks ||
+                                                     !I_sizes || !seeds || !status)))
+        return RTCUR_E_INVAL;
+    if (L_out && out_dtype != RTCUR_F64 && out_dtype != RTCUR_F32) return RTCUR_E_INVAL;
+    for (int32_t t = 0; t < nh; ++t) {
+        if (!hs[t]) return RTCUR_E_INVAL;
+        for (int32_t u = 0; u < t; ++u)
+            if (hs[u] == hs[t]) return RTCUR_E_INVAL;  // one thread per handle
+    }
+    const int32_t nt = count < nh ? count : nh;
+    // worker t solves instances t, t + nh, ... on handle t, in order
+    auto work = [&](int32_t t) {
+        for (int32_t j = t; j < count; j += nh) {
+            const int64_t* Js = J_sizes ? J_sizes + (int64_t)j * rtcur::kMaxModes : nullptr;
+            rtcur_info inf;
+            std::memset(&inf, 0, sizeof(inf));
+            int rc = rtcur_solve(hs[t], X[j], x_dtype, n[j], dims + (int64_t)j * rtcur::kMaxModes,
+                                 ranks + (int64_t)j * rtcur::kMaxModes,
+                                 I_sizes + (int64_t)j * rtcur::kMaxModes, Js,
+                                 zeta0 ? zeta0[j] : 0.0, gamma, tol, max_iter, seeds[j], &inf);
+            if (rc >= 0 && L_out && L_out[j]) {
+                const int rr = rtcur_reconstruct(hs[t], L_out[j], out_dtype);
+                if (rr != RTCUR_OK) rc = rr;
+            }
+            status[j] = rc;
+            if (infos) infos[j] = inf;
+        }
+    };
+    try {
+        std::vector<std::thread> pool;
+        pool.reserve(nt > 1 ? nt - 1 : 0);
+        for (int32_t t = 1; t < nt; ++t) pool.emplace_back(work, t);
+        if (nt > 0) work(0);
+        for (auto& th : pool) th.join();
+    } catch (...) {
+        return RTCUR_E_STATE;  // no thread could be started
+    }
+    int rc = RTCUR_OK;
+    for (int32_t j = 0; j < count; ++j)
+        if (status[j] < 0) return status[j];
+        else if (status[j] == RTCUR_NOT_CONVERGED) rc = RTCUR_NOT_CONVERGED;
+    return rc;
 }
 
 int rtcur_destroy(rtcur_t h) {

@@ -855,6 +855,52 @@ __device__ __noinline__ int eig_guarded(const double* G, int sp, int s, int r, i
     return res;
 }
 
+// The Gram of one mode from k_gram's per-chunk 16 x 16 tiles into G (row
+// stride sp + 1, both triangles): E entries per thread and KG chunks per
+// load round, every load of a round issued before the first add; with
+// kMulti the rounds repeat over the chunks, which are always added in chunk
+// order.  Returns true (in every thread) if the stop flag was raised.
+template <int E, int KG, bool kMulti>
+__device__ __forceinline__ bool gram_assemble(const double* __restrict__ src0, int total,
+                                              int nkc, double* G, int sp, const int2* pairs,
+                                              const DevState* st) {
+    for (int f0 = threadIdx.x; f0 < total; f0 += E * kThreads) {
+        double sum[E];
+#pragma unroll
+        for (int u = 0; u < E; ++u) sum[u] = 0.0;
+        for (int q0 = 0; q0 < (kMulti ? nkc : 1); q0 += KG) {
+            double v[E][KG];
+#pragma unroll
+            for (int u = 0; u < E; ++u) {
+                const int f = f0 + u * kThreads < total ? f0 + u * kThreads : f0;
+                const double* src = src0 + (int64_t)(f >> 8) * nkc * 256 + (f & 255);
+#pragma unroll
+                for (int q = 0; q < KG; ++q)  // masked in the sum
+                    v[u][q] = src[(int64_t)(q0 + q < nkc ? q0 + q : q0) * 256];
+            }
+            // uniform: same f0 and q0 in every thread
+            if (q0 == 0 && f0 == (int)threadIdx.x && stopped(st)) return true;
+#pragma unroll
+            for (int u = 0; u < E; ++u)
+#pragma unroll
+                for (int q = 0; q < KG; ++q)
+                    if (q0 + q < nkc) sum[u] += v[u][q];
+        }
+#pragma unroll
+        for (int u = 0; u < E; ++u) {
+            const int f = f0 + u * kThreads;
+            if (f >= total) continue;
+            const int2 pr = pairs[f >> 8];
+            const int t = f & 255;
+            const int a2 = pr.x * 16 + (t >> 4), b2 = pr.y * 16 + (t & 15);
+            // rows and columns beyond s come out of k_gram as zeros
+            G[a2 * (sp + 1) + b2] = sum[u];
+            G[b2 * (sp + 1) + a2] = sum[u];
+        }
+    }
+    return false;
+}
+
 // kLdsGram: the Gram sits in dynamic LDS (else in `gram`); a compile-time
 // choice so that its accesses compile to LDS (or global) instructions rather
 // than generic ones.
@@ -895,70 +941,16 @@ __global__ __launch_bounds__(kThreads) void k_eig(Prob P, const double* __restri
         const int nkc = P.gnkc[i];
         const int total = npairs * 256;
         const double* src0 = gpart + (int64_t)P.gitem0[i] * 256;
-        constexpr int KG = kGramKCGroup;
-        auto put = [&](int f, double sum) {
-            const int2 pr = sh.pairs[f >> 8];
-            const int t = f & 255;
-            const int a2 = pr.x * 16 + (t >> 4), b2 = pr.y * 16 + (t & 15);
-            // rows and columns beyond s come out of k_gram as zeros
-            G[a2 * (sp + 1) + b2] = sum;
-            G[b2 * (sp + 1) + a2] = sum;
-        };
-        if (nkc <= KG) {
-            // one load round per entry: E entries x KG chunks in flight
-            constexpr int E = 24;
-            for (int f0 = threadIdx.x; f0 < total; f0 += E * kThreads) {
-                double v[E][KG];
-#pragma unroll
-                for (int u = 0; u < E; ++u) {
-                    const int f = f0 + u * kThreads < total ? f0 + u * kThreads : f0;
-                    const double* src = src0 + (int64_t)(f >> 8) * nkc * 256 + (f & 255);
-#pragma unroll
-                    for (int q = 0; q < KG; ++q)  // masked in the sum
-                        v[u][q] = src[(int64_t)(q < nkc ? q : 0) * 256];
-                }
-                // uniform: same f0 in every thread
-                if (f0 == (int)threadIdx.x && stopped(st)) return;
-#pragma unroll
-                for (int u = 0; u < E; ++u) {
-                    const int f = f0 + u * kThreads;
-                    if (f >= total) continue;
-                    double sum = 0.0;
-#pragma unroll
-                    for (int q = 0; q < KG; ++q)
-                        if (q < nkc) sum += v[u][q];
-                    put(f, sum);
-                }
-            }
-        } else {
-            // many chunks: E entries, KG2 chunks per load round, in chunk order
-            constexpr int E = 4, KG2 = 16;
-            for (int f0 = threadIdx.x; f0 < total; f0 += E * kThreads) {
-                double sum[E];
-#pragma unroll
-                for (int u = 0; u < E; ++u) sum[u] = 0.0;
-                for (int q0 = 0; q0 < nkc; q0 += KG2) {
-                    double v[E][KG2];
-#pragma unroll
-                    for (int u = 0; u < E; ++u) {
-                        const int f = f0 + u * kThreads < total ? f0 + u * kThreads : f0;
-                        const double* src = src0 + (int64_t)(f >> 8) * nkc * 256 + (f & 255);
-#pragma unroll
-                        for (int q = 0; q < KG2; ++q)
-                            v[u][q] = src[(int64_t)(q0 + q < nkc ? q0 + q : q0) * 256];
-                    }
-                    if (q0 == 0 && f0 == (int)threadIdx.x && stopped(st)) return;
-#pragma unroll
-                    for (int u = 0; u < E; ++u)
-#pragma unroll
-                        for (int q = 0; q < KG2; ++q)
-                            if (q0 + q < nkc) sum[u] += v[u][q];
-                }
-#pragma unroll
-                for (int u = 0; u < E; ++u)
-                    if (f0 + u * kThreads < total) put(f0 + u * kThreads, sum[u]);
-            }
-        }
+        // chunk counts up to 4 or 8: one load round per entry; more: rounds
+        // of 16 chunks, added in chunk order
+        bool stop;
+        if (nkc <= 4)
+            stop = gram_assemble<24, 4, false>(src0, total, nkc, G, sp, sh.pairs, st);
+        else if (nkc <= 8)
+            stop = gram_assemble<12, 8, false>(src0, total, nkc, G, sp, sh.pairs, st);
+        else
+            stop = gram_assemble<4, 16, true>(src0, total, nkc, G, sp, sh.pairs, st);
+        if (stop) return;
     }
     if (threadIdx.x == 0) sh.ok = 1;
     double* Wi = W + P.woff[i];

@@ -26,8 +26,8 @@ from typing import Optional, Sequence
 
 import numpy as np
 
-__all__ = ["Instance", "tucker_plus_sparse", "video_like", "sample_sizes",
-           "CONFIGS", "config_instance"]
+__all__ = ["Instance", "tucker_plus_sparse", "video_like", "batch_specs",
+           "sample_sizes", "CONFIGS", "config_instance"]
 
 
 @dataclass
@@ -149,6 +149,23 @@ def video_like(dims: Sequence[int] = (240, 320, 3, 400),
     if not keep_parts:
         return Instance(X, None, None, dims, ranks, coverage, seed, meta)
     return Instance(X, L, S, dims, ranks, coverage, seed, meta)
+
+
+def batch_specs(count: int = 64, dmin: int = 64, dmax: int = 256, rmin: int = 2,
+                rmax: int = 8, amin: float = 0.1, amax: float = 0.4, seed: int = 0):
+    """Shapes of a batch of independent 3-mode instances of uneven sizes: per
+    instance and mode d ~ U{dmin..dmax} and r ~ U{rmin..rmax}, and
+    alpha ~ U[amin, amax], drawn from default_rng(seed) in that order.
+    Returns a list of dicts (dims, ranks, alpha, seed = seed + j) for
+    tucker_plus_sparse."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for j in range(count):
+        dims = tuple(int(x) for x in rng.integers(dmin, dmax + 1, size=3))
+        ranks = tuple(int(x) for x in rng.integers(rmin, rmax + 1, size=3))
+        alpha = float(rng.uniform(amin, amax))
+        out.append({"dims": dims, "ranks": ranks, "alpha": alpha, "seed": seed + j})
+    return out
 
 
 def sample_sizes(dims: Sequence[int], ranks: Sequence[int],

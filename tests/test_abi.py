@@ -56,6 +56,16 @@ def test_argument_checks_without_device(L):
                          10, 0, None) == rt.E_INVAL
     assert L.rtcur_reconstruct(None, None, 0) == rt.E_INVAL
     assert L.rtcur_outliers(None, None, 0, 0.0, None, None, 0) == rt.E_INVAL
+    # batch: no handles, a null handle, a repeated handle
+    assert L.rtcur_solve_batch(None, 1, 0, None, 0, None, None, None, None, None, None,
+                               0.7, 1e-5, 10, None, None, 0, None, None) == rt.E_INVAL
+    nul = (ctypes.c_void_p * 1)(None)
+    assert L.rtcur_solve_batch(nul, 1, 0, None, 0, None, None, None, None, None, None,
+                               0.7, 1e-5, 10, None, None, 0, None, None) == rt.E_INVAL
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: rejected as repeated
+    two = (ctypes.c_void_p * 2)(fake, fake)
+    assert L.rtcur_solve_batch(two, 2, 0, None, 0, None, None, None, None, None, None,
+                               0.7, 1e-5, 10, None, None, 0, None, None) == rt.E_INVAL
     for s in (0, 1, -1, -2, -3, -4, -5, -6):
         assert L.rtcur_strerror(s)
     assert L.rtcur_strerror(99) == b"unknown status"

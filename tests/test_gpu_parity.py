@@ -113,6 +113,38 @@ def test_video_shaped(video_small, dtype):
     compare(res, h, info, fp64=dtype == "f64", label=f"video 120x160x3x200 {dtype}")
 
 
+def test_solve_batch_uneven_instances():
+    # six instances of uneven shapes and ranks over three handles on their
+    # own streams: each equals the oracle and, bit for bit, a single solve
+    import paper_2108_10448_amd as rt
+    specs = synth.batch_specs(count=6, dmin=24, dmax=60, rmin=2, rmax=5, seed=7)
+    insts = [synth.tucker_plus_sparse(**sp) for sp in specs]
+    Xs = [torch.from_numpy(i.X).to("cuda:0") for i in insts]
+    ranks = [i.ranks for i in insts]
+    I = [synth.sample_sizes(i.dims, i.ranks, 3.0)[0] for i in insts]
+    seeds = [sp["seed"] + 100 for sp in specs]
+    streams = [torch.cuda.Stream() for _ in range(3)]
+    hs = [rt.create(0, stream=st) for st in streams]
+    infos, Ls = rt.solve_batch(hs, Xs, ranks, I, tol=0.0, max_iter=6, seeds=seeds,
+                               with_L=True, check=False)
+    torch.cuda.synchronize()
+    for j, inst in enumerate(insts):
+        print(f"[batch] {inst.dims} r={inst.ranks} status {infos[j].status} "
+              f"iters {infos[j].iters} err {infos[j].err:.6e}", flush=True)
+        assert infos[j].status == rt.NOT_CONVERGED and infos[j].iters == 6
+        res = oracle_rtcur(inst.X, inst.ranks, I[j], None, None, 0.7, 0.0, 6, seeds[j], "F")
+        assert abs(infos[j].err - res.err) <= 1e-9 * res.err
+        assert rel(Ls[j].cpu().numpy(), res.reconstruct()) <= 1e-10
+        h1 = rt.create(0)
+        rt.solve(h1, Xs[j], ranks[j], I[j], tol=0.0, max_iter=6, seed=seeds[j], check=False)
+        L1 = rt.reconstruct(h1)
+        torch.cuda.synchronize()
+        assert torch.equal(L1, Ls[j])
+        rt.destroy(h1)
+    for h in hs:
+        rt.destroy(h)
+
+
 def test_two_modes_fp64():
     inst = synth.tucker_plus_sparse((300, 257), (4, 4), alpha=0.1, seed=8)
     I = (40, 37)
