@@ -323,14 +323,20 @@ def main():
     def side(variant, dtype, name):
         hh = rt.create(0, variant=variant, dtype=dtype)
         inf, ts = time_solves(rt, torch, hh, X, ranks, I, args.side_steps, 1)
+        Lr = rt.reconstruct(hh)
+        Ls_ = torch.from_numpy(inst.L_star).to("cuda:0")
+        terr = float(torch.linalg.norm(Lr.double() - Ls_) / torch.linalg.norm(Ls_))
+        del Lr, Ls_
         rows[name] = {"time_to_tol_ms_p50": 1e3 * percentile(ts, 0.5),
                       "iters": inf[-1].iters, "err": inf[-1].err,
-                      "iters_per_s": sum(i.iters for i in inf) / sum(ts)}
+                      "iters_per_s": sum(i.iters for i in inf) / sum(ts),
+                      "true_rel_err": terr}
         rt.destroy(hh)
         log(f"{name}: {rows[name]}")
 
     if args.side_steps > 0:
         side("F", torch.float32, "F_f32_no_events")
+        side("F", torch.bfloat16, "F_bf16_then_f32")
         side("F", torch.float64, "F_f64")
         side("R", torch.float32, "R_f32")
         side("R", torch.float64, "R_f64")
@@ -349,7 +355,8 @@ def main():
                              f"({100 * vin.meta['coverage']:.2f}% of pixel-frames), "
                              "RTCUR-F, upsilon 2, chidori, gamma 0.7, zeta0=max|X|, tol 1e-5",
                  "I_sizes": vI}
-        for dtype, name in ((torch.float32, "F_f32"), (torch.float64, "F_f64")):
+        for dtype, name in ((torch.float32, "F_f32"), (torch.bfloat16, "F_bf16_then_f32"),
+                            (torch.float64, "F_f64")):
             hh = rt.create(0, variant="F", dtype=dtype)
             inf, ts = time_solves(rt, torch, hh, Xv, list(vin.ranks), vI, args.side_steps, 1)
             S, Lr = rt.outliers(hh, Xv, with_L=True)

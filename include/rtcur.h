@@ -56,7 +56,7 @@ enum rtcur_status {
     RTCUR_E_STATE = -6        /* call out of order (e.g. reconstruct first)    */
 };
 
-enum rtcur_dtype { RTCUR_F64 = 0, RTCUR_F32 = 1 };
+enum rtcur_dtype { RTCUR_F64 = 0, RTCUR_F32 = 1, RTCUR_BF16 = 2 /* compute only */ };
 enum rtcur_variant { RTCUR_FIXED = 0 /* RTCUR-F */, RTCUR_RESAMPLE = 1 /* RTCUR-R */ };
 enum rtcur_block_what { RTCUR_BLOCK_X = 0, RTCUR_BLOCK_C = 1, RTCUR_BLOCK_L = 2,
                         RTCUR_BLOCK_SUPPORT = 3 };
@@ -78,8 +78,12 @@ typedef struct {
  * (a hipStream_t; NULL = the null stream).  variant: RTCUR_FIXED or
  * RTCUR_RESAMPLE.  compute_dtype: RTCUR_F64 or RTCUR_F32, the precision of
  * the sampled blocks, factors and the rebuilt L; the truncated SVD and the
- * stopping-rule norms always run in float64.  Fails with RTCUR_E_HIP when no
- * usable device exists.  *out is set to NULL on failure. */
+ * stopping-rule norms always run in float64.  RTCUR_BF16 (RTCUR_FIXED only)
+ * stores the sampled blocks in bfloat16 (factors, L and arithmetic in
+ * float) while e^(k) > max(tol, 1e-2), then finishes with float blocks (the
+ * FP32 refinement sweep) from that iterate; results and getters are then
+ * those of a float32 handle.  Fails with RTCUR_E_HIP when no usable device
+ * exists.  *out is set to NULL on failure. */
 int rtcur_create(rtcur_t* out, int device, void* hip_stream, int variant,
                  int compute_dtype);
 

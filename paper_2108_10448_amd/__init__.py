@@ -30,7 +30,7 @@ LIB_PATH = os.path.join(HERE, "librtcur.so")
 
 OK, NOT_CONVERGED = 0, 1
 E_INVAL, E_NOMEM, E_HIP, E_RANK, E_NONFINITE, E_STATE = -1, -2, -3, -4, -5, -6
-F64, F32 = 0, 1
+F64, F32, BF16 = 0, 1, 2
 FIXED, RESAMPLE = 0, 1
 BLOCK_X, BLOCK_C, BLOCK_L, BLOCK_SUPPORT = 0, 1, 2, 3
 
@@ -194,7 +194,7 @@ def create(device: int = 0, stream=None, variant: str = "F", dtype=None) -> Hand
     stream of that device).  variant "F" (fixed samples) or "R" (resample)."""
     torch = _torch()
     dtype = torch.float64 if dtype is None else dtype
-    cdt = F64 if dtype == torch.float64 else F32
+    cdt = F64 if dtype == torch.float64 else (BF16 if dtype == torch.bfloat16 else F32)
     if stream is None:
         stream = torch.cuda.current_stream(device)
     sptr = ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else stream)
@@ -289,6 +289,8 @@ def solve_batch(handles: Sequence[Handle], Xs, ranks, I_sizes=None, J_sizes=None
     Ls = None
     lo = None
     odt = L_dtype or dt
+    if odt not in (torch.float32, torch.float64):
+        raise TypeError("L_dtype must be float32 or float64")
     if with_L:
         Ls = [torch.empty(X.shape, dtype=odt, device=X.device) for X in Xs]
         lo = (ctypes.c_void_p * count)(*[L.data_ptr() for L in Ls])
@@ -310,11 +312,19 @@ def solve_batch(handles: Sequence[Handle], Xs, ranks, I_sizes=None, J_sizes=None
     return out, Ls
 
 
+def _out_dtype(h: Handle):
+    """Default output dtype: the handle's, float32 for a bfloat16 handle."""
+    torch = _torch()
+    return torch.float32 if h.dtype == torch.bfloat16 else h.dtype
+
+
 def reconstruct(h: Handle, out=None, dtype=None):
     """rtcur_reconstruct: the full L into `out` (allocated if None)."""
     torch = _torch()
     if out is None:
-        out = torch.empty(h.dims, dtype=dtype or h.dtype, device=f"cuda:{h.device}")
+        out = torch.empty(h.dims, dtype=dtype or _out_dtype(h), device=f"cuda:{h.device}")
+    if out.dtype not in (torch.float32, torch.float64) or not out.is_contiguous():
+        raise TypeError("out must be a C-contiguous float32/float64 tensor")
     rc = lib().rtcur_reconstruct(h.ptr, ctypes.c_void_p(out.data_ptr()),
                                  F64 if out.dtype == torch.float64 else F32)
     if rc != OK:
@@ -334,7 +344,9 @@ def outliers(h: Handle, X, zeta: Optional[float] = None, *, with_L: bool = False
         raise TypeError("X must be float32 or float64")
     if tuple(X.shape) != tuple(h.dims):
         raise ValueError(f"X has shape {tuple(X.shape)}, the solve had {tuple(h.dims)}")
-    odt = dtype or h.dtype
+    odt = dtype or _out_dtype(h)
+    if odt not in (torch.float32, torch.float64):
+        raise TypeError("output dtype must be float32 or float64")
     S = torch.empty(h.dims, dtype=odt, device=X.device)
     L_ = torch.empty(h.dims, dtype=odt, device=X.device) if with_L else None
     rc = lib().rtcur_outliers(h.ptr, ctypes.c_void_p(X.data_ptr()),

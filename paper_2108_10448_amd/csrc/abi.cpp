@@ -85,7 +85,9 @@ int rtcur_create(rtcur_t* out, int device, void* hip_stream, int variant, int co
     if (!out) return RTCUR_E_INVAL;
     *out = nullptr;
     if (variant != RTCUR_FIXED && variant != RTCUR_RESAMPLE) return RTCUR_E_INVAL;
-    if (compute_dtype != RTCUR_F64 && compute_dtype != RTCUR_F32) return RTCUR_E_INVAL;
+    if (compute_dtype != RTCUR_F64 && compute_dtype != RTCUR_F32 && compute_dtype != RTCUR_BF16)
+        return RTCUR_E_INVAL;
+    if (compute_dtype == RTCUR_BF16 && variant != RTCUR_FIXED) return RTCUR_E_INVAL;
     int count = 0;
     if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return RTCUR_E_HIP;
     if (device < 0 || device >= count) return RTCUR_E_INVAL;

@@ -16,6 +16,8 @@
 // any of them, so that many loads are in flight per wave.
 #pragma once
 
+#include <hip/hip_bf16.h>
+
 #include "internal.h"
 
 namespace rtcur {
@@ -133,6 +135,25 @@ __global__ void k_init_state(DevState* st, double zeta0) {
         st->eig_unconverged = 0;
         for (int j = 0; j < 4; ++j) st->counter[j] = 0u;
     }
+}
+
+// Clear the stop flag to continue the loop from the current iterate (the
+// FP32 refinement sweep after the bfloat16 iterations); the loop state
+// otherwise stays.
+__global__ void k_resume(DevState* st) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        st->stop = 0;
+        st->status = 0;
+        st->converged = 0;
+    }
+}
+
+// bfloat16 block entries to float (exact).
+__global__ __launch_bounds__(kThreads) void k_widen(const __hip_bfloat16* __restrict__ in,
+                                                    int64_t N, float* __restrict__ out) {
+    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < N;
+         e += (int64_t)gridDim.x * kThreads)
+        out[e] = (float)in[e];
 }
 
 // zeta_0 = ||X||_inf over the whole tensor (one full read) plus a
@@ -265,10 +286,12 @@ __global__ __launch_bounds__(kThreads) void k_den(Prob P, const double* part, in
 //   E   = C^k - L^k  -> per-tile sums of E^2 (numerator of e^(k))
 //   D   = X - L^k;  S = D if |D| > zeta_{k+1} else 0;  C^{k+1} = X - S
 // zeta_{k+1} = gamma^(k+1) zeta_0 by repeated multiplication (equation 12).
-template <typename T, int RP>
+// T: factor and arithmetic type; TB: block storage type (T, or bfloat16
+// with T = float).
+template <typename T, int RP, typename TB = T>
 __global__ __launch_bounds__(kThreads) void k_ht(
-    Prob P, const int4* __restrict__ tiles, const T* __restrict__ XO,
-    const T* __restrict__ Cold, T* __restrict__ Cnew,
+    Prob P, const int4* __restrict__ tiles, const TB* __restrict__ XO,
+    const TB* __restrict__ Cold, TB* __restrict__ Cnew,
     uint64_t* __restrict__ mask, const T* __restrict__ Bf,
     const T* __restrict__ H, double gamma, int kcur, int flags,
     double* __restrict__ part, const DevState* st) {
@@ -287,13 +310,13 @@ __global__ __launch_bounds__(kThreads) void k_ht(
     for (int j = 0; j <= kcur; ++j) zeta *= gamma;
 
     // all loads first
-    T xv[kTileRows], co[kTileRows];
+    TB xb[kTileRows], cb[kTileRows];
     const int64_t base = bd.off + (int64_t)tl.y * bd.ncols + cc;
 #pragma unroll
     for (int x = 0; x < kTileRows; ++x) {
         const int64_t e = base + (int64_t)(x < rows ? x : rows - 1) * bd.ncols;
-        xv[x] = doHT ? XO[e] : T(0);
-        co[x] = doE ? Cold[e] : T(0);
+        xb[x] = doHT ? XO[e] : TB(0.0f);
+        cb[x] = doE ? Cold[e] : TB(0.0f);
     }
     T h[RP];
 #pragma unroll
@@ -323,14 +346,15 @@ __global__ __launch_bounds__(kThreads) void k_ht(
         }
         const int64_t e = bd.off + (int64_t)(tl.y + x) * bd.ncols + c;
         if (doE && valid) {
-            const double dv = (double)co[x] - (double)L;
+            const double dv = (double)(T)cb[x] - (double)L;
             e2 += dv * dv;
         }
         if (doHT) {
-            const T D = xv[x] - L;
+            const T xv = (T)xb[x];
+            const T D = xv - L;
             const bool keep = valid && fabs((double)D) > zeta;
             const T S = keep ? D : T(0);
-            if (valid) Cnew[e] = xv[x] - S;
+            if (valid) Cnew[e] = (TB)(xv - S);
             const uint64_t bal = __ballot(keep);
             if (lane == 0 && tl.z + wv * 64 < bd.ncols)
                 mask[bd.moff + (int64_t)(tl.y + x) * bd.words + (tl.z >> 6) + wv] = bal;

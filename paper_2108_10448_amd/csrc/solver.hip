@@ -16,6 +16,9 @@
 //   k_hexp   H_b = G x_{j != mode} B_j on each block's columns
 // so that the next k_ht forms L on the blocks as B_mode H_b (Section 3.3).
 #include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+
+#include <type_traits>
 
 #include <algorithm>
 #include <cmath>
@@ -399,7 +402,9 @@ static void launch_hexp(const Prob& P, bool runs, unsigned grid, hipStream_t st,
     }
 }
 
-template <typename T, int RP>
+// T: factor and arithmetic type; TB: block storage type (T, or bfloat16
+// with T = float for the bfloat16 iterations).
+template <typename T, int RP, typename TB = T>
 struct Runner {
     rtcur_s* h;
     Impl& im;
@@ -452,11 +457,11 @@ struct Runner {
         const int nt = (int)im.ht_tiles.size();
         HIPCHK(pb(PK_GATHER));
         if (xdt == RTCUR_F64)
-            hipLaunchKernelGGL((k_gather<double, T>), dim3(nt), dim3(kThreads), 0, s,
-                               (const double*)X, im.P, im.d_ht_tiles, (T*)im.XO, im.part);
+            hipLaunchKernelGGL((k_gather<double, TB>), dim3(nt), dim3(kThreads), 0, s,
+                               (const double*)X, im.P, im.d_ht_tiles, (TB*)im.XO, im.part);
         else
-            hipLaunchKernelGGL((k_gather<float, T>), dim3(nt), dim3(kThreads), 0, s,
-                               (const float*)X, im.P, im.d_ht_tiles, (T*)im.XO, im.part);
+            hipLaunchKernelGGL((k_gather<float, TB>), dim3(nt), dim3(kThreads), 0, s,
+                               (const float*)X, im.P, im.d_ht_tiles, (TB*)im.XO, im.part);
         HIPCHK(hipGetLastError());
         hipLaunchKernelGGL(k_den, dim3(1), dim3(kThreads), 0, s, im.P, (const double*)im.part,
                            flags, im.st);
@@ -465,11 +470,11 @@ struct Runner {
         return 0;
     }
 
-    int ht(int kcur, int flags, const T* Cold, T* Cnew, uint64_t* mask, double gamma) {
+    int ht(int kcur, int flags, const TB* Cold, TB* Cnew, uint64_t* mask, double gamma) {
         const int nt = (int)im.ht_tiles.size();
         HIPCHK(pb(PK_HT));
-        hipLaunchKernelGGL((k_ht<T, RP>), dim3(nt), dim3(kThreads), 0, s, im.P,
-                           im.d_ht_tiles, (const T*)im.XO, Cold, Cnew, mask,
+        hipLaunchKernelGGL((k_ht<T, RP, TB>), dim3(nt), dim3(kThreads), 0, s, im.P,
+                           im.d_ht_tiles, (const TB*)im.XO, Cold, Cnew, mask,
                            (const T*)im.Bf, (const T*)im.H, gamma, kcur, flags, im.hpart,
                            im.st);
         HIPCHK(hipGetLastError());
@@ -499,12 +504,12 @@ struct Runner {
 
     // Step (II): L-update from C (equations 8-9) into B_i, G, H_b.  With
     // `decide`, the Gram launch also forms e^(kcur) from k_ht's partials.
-    int lupdate(const T* C, int warm, int decide_flag, int kcur, double tol) {
+    int lupdate(const TB* C, int warm, int decide_flag, int kcur, double tol) {
         const Prob& P = im.P;
         const int n = P.n;
         const int ng = (int)im.gram_items.size();
         HIPCHK(pb(PK_GRAM));
-        hipLaunchKernelGGL((k_gram<T>), dim3(ng + 1), dim3(kThreads), 0, s, P, C,
+        hipLaunchKernelGGL((k_gram<TB>), dim3(ng + 1), dim3(kThreads), 0, s, P, C,
                            im.d_gram_items, ng, im.gpart, decide_flag,
                            (const double*)im.hpart, kcur, tol, im.err_hist, im.st);
         HIPCHK(hipGetLastError());
@@ -528,7 +533,7 @@ struct Runner {
         HIPCHK(pe());
         const int nz = (int)im.z_tiles.size();
         HIPCHK(pb(PK_ZCORE));
-        hipLaunchKernelGGL((k_zcore<T, RP>), dim3(nz + P.s[0] * P.cparts), dim3(kThreads), 0, s, P, C,
+        hipLaunchKernelGGL((k_zcore<TB, RP>), dim3(nz + P.s[0] * P.cparts), dim3(kThreads), 0, s, P, C,
                            (const double*)im.Y, im.Z, im.d_z_tiles, nz, (const double*)im.W,
                            im.Tc, im.st);
         HIPCHK(hipGetLastError());
@@ -538,11 +543,11 @@ struct Runner {
         bool sub = false;
         for (int i = 0; i < n; ++i) sub = sub || P.bsub[i] > 1;
         if (sub)
-            hipLaunchKernelGGL((k_bfac<T, RP, true>), dim3(nb + 1), dim3(kThreads), 0, s, P, C,
+            hipLaunchKernelGGL((k_bfac<TB, RP, true>), dim3(nb + 1), dim3(kThreads), 0, s, P, C,
                                (const double*)im.Z, im.d_bfac_items, nb, im.bpart,
                                (const double*)im.W, (const double*)im.Tc, im.Gd, im.st);
         else
-            hipLaunchKernelGGL((k_bfac<T, RP, false>), dim3(nb + 1), dim3(kThreads), 0, s, P, C,
+            hipLaunchKernelGGL((k_bfac<TB, RP, false>), dim3(nb + 1), dim3(kThreads), 0, s, P, C,
                                (const double*)im.Z, im.d_bfac_items, nb, im.bpart,
                                (const double*)im.W, (const double*)im.Tc, im.Gd, im.st);
         HIPCHK(hipGetLastError());
@@ -584,9 +589,9 @@ struct Runner {
         return 0;
     }
 
-    int run(const void* X, int xdt, const Shape& sh, double zeta0, double gamma,
-            double tol, int max_iter, uint64_t seed) {
-        const bool resample = h->variant == RTCUR_RESAMPLE;
+    // Set-up of a solve: sample, loop state, zeroed factors, zeta_0 and the
+    // first gather (with the denominator of e^(k)).
+    int start(const void* X, int xdt, const Shape& sh, double zeta0, uint64_t seed) {
         int rc;
         im.recs.clear();
         im.ev_used = 0;
@@ -615,16 +620,29 @@ struct Runner {
             HIPCHK(hipGetLastError());
             HIPCHK(pe());
         }
-        if ((rc = gather(X, xdt, kFirstGather))) return rc;
+        return gather(X, xdt, kFirstGather);
+    }
+
+    int run(const void* X, int xdt, const Shape& sh, double zeta0, double gamma,
+            double tol, int max_iter, uint64_t seed) {
+        const bool resample = h->variant == RTCUR_RESAMPLE;
+        int rc;
+        if ((rc = start(X, xdt, sh, zeta0, seed))) return rc;
         DevState ds;
         const bool skip = tol >= 1.0;  // e^(0) = 1 <= tol: no iteration
         if (!skip) {
             rc = resample ? loop_resample(X, xdt, sh, gamma, tol, max_iter, seed, ds)
-                          : loop_fixed(gamma, tol, max_iter, ds);
+                          : loop_fixed(gamma, tol, max_iter, ds, 0);
             if (rc) return rc;
         } else if ((rc = read_state(ds))) {
             return rc;
         }
+        return finish(ds, skip, gamma, tol, max_iter);
+    }
+
+    // Histories, profile totals and the summary of the returned iterate.
+    int finish(const DevState& ds, bool skip, double gamma, double tol, int max_iter) {
+        int rc;
         if (ds.status < 0) {
             h->last_error = ds.status == RTCUR_E_RANK ? "U_i has numerical rank below r_i"
                                                       : "non-finite value in X or e^(k)";
@@ -665,18 +683,45 @@ struct Runner {
         return info.status;
     }
 
-    // C^j lives in C[j % 2]; C^0 is X_Omega itself.
-    T* cbuf(int j) { return j == 0 ? (T*)im.XO : (T*)im.C[j % 2]; }
+    // Continue the loop from iterate k0 with the blocks re-gathered in this
+    // runner's block type (the FP32 refinement sweep).
+    int resume(const void* X, int xdt) {
+        hipLaunchKernelGGL(k_resume, dim3(1), dim3(64), 0, s, im.st);
+        HIPCHK(hipGetLastError());
+        return gather(X, xdt, 0);
+    }
 
-    int loop_fixed(double gamma, double tol, int max_iter, DevState& ds) {
-        int done = 0;
+    // The returned iterate's blocks in float after bfloat16 iterations: X_Omega
+    // re-gathered, C^K widened (through the other C buffer).
+    int widen(const void* X, int xdt, int K) {
+        int rc;
+        if ((rc = gather(X, xdt, 0))) return rc;
+        if (K > 0) {
+            const int64_t N = im.nblk_elems;
+            float* tmp = static_cast<float*>(im.C[(K + 1) % 2]);
+            hipLaunchKernelGGL(k_widen, dim3(1024), dim3(kThreads), 0, s,
+                               static_cast<const __hip_bfloat16*>(im.C[K % 2]), N, tmp);
+            HIPCHK(hipGetLastError());
+            HIPCHK(hipMemcpyAsync(im.C[K % 2], tmp, sizeof(float) * N, hipMemcpyDeviceToDevice,
+                                  s));
+        }
+        return 0;
+    }
+
+    // C^j lives in C[j % 2]; C^0 is X_Omega itself.
+    TB* cbuf(int j) { return j == 0 ? (TB*)im.XO : (TB*)im.C[j % 2]; }
+
+    // Iterations j0 + 1 .. (stop or max_iter).  The first of them has no
+    // e^(j0) to form when j0 > 0 (it was formed before the loop was resumed).
+    int loop_fixed(double gamma, double tol, int max_iter, DevState& ds, int j0) {
+        int done = j0;
         int rc;
         if ((rc = read_state(ds))) return rc;
         if (ds.stop) return 0;
         double e_prev = -1.0, e_last = -1.0;
         std::vector<double> eh(2);
         while (done < max_iter) {
-            int chunk = done < 2 ? 2 : 8;
+            int chunk = done - j0 < 2 ? 2 : 8;
             if (e_last > 0 && e_prev > 0 && e_last < e_prev) {
                 const double rate = e_last / e_prev;
                 const double need = std::log(tol / e_last) / std::log(rate);
@@ -686,15 +731,16 @@ struct Runner {
             for (int q = 0; q < chunk; ++q) {
                 const int j = done + 1 + q;  // iteration j computes S^j, L^j
                 tag = j;
-                const int flags = kDoHT | (j > 1 ? (kHaveL | kDoE | kDecide) : 0);
+                const bool err = j > 1 && j > j0 + 1;  // e^(j-1) formed here
+                const int flags = kDoHT | (j > 1 ? kHaveL : 0) | (err ? (kDoE | kDecide) : 0);
                 if ((rc = ht(j - 1, flags, cbuf(j - 1), cbuf(j), im.mask[j % 2], gamma)))
                     return rc;
-                if ((rc = lupdate(cbuf(j), j > 1 ? 1 : 0, j > 1 ? 1 : 0, j - 1, tol))) return rc;
+                if ((rc = lupdate(cbuf(j), j > 1 ? 1 : 0, err ? 1 : 0, j - 1, tol))) return rc;
             }
             done += chunk;
             if ((rc = read_state(ds))) return rc;
             if (ds.stop) return 0;
-            if (done >= 2) {
+            if (done >= 2 && done - j0 >= 2) {
                 HIPCHK(hipMemcpy(eh.data(), im.err_hist + (done - 2), 2 * sizeof(double),
                                  hipMemcpyDeviceToHost));
                 e_prev = eh[0];
@@ -818,9 +864,47 @@ static int prepare(rtcur_s* h, Impl& im, const Shape& sh, int max_iter) {
     return 0;
 }
 
+// RTCUR_BF16: the blocks in bfloat16 (factors, arithmetic and L in float;
+// Gram, eigensolver and norms in float64) until e^(k) <= max(tol,
+// kBf16Switch), then the FP32 refinement sweep continues from that iterate
+// with the blocks re-gathered in float until e^(k) <= tol.
+constexpr double kBf16Switch = 1e-2;
+
+template <int RP>
+static int run_bf16(rtcur_s* h, Impl& im, const void* X, int xdt, const Shape& sh,
+                    double zeta0, double gamma, double tol, int max_iter, uint64_t seed) {
+    Runner<float, RP, __hip_bfloat16> R1{h, im, h->stream};
+    Runner<float, RP, float> R2{h, im, h->stream};
+    int rc;
+    if ((rc = R1.start(X, xdt, sh, zeta0, seed))) return rc;
+    DevState ds;
+    const bool skip = tol >= 1.0;
+    if (skip) {
+        if ((rc = R2.widen(X, xdt, 0)) || (rc = R2.read_state(ds))) return rc;
+        return R2.finish(ds, true, gamma, tol, max_iter);
+    }
+    if ((rc = R1.loop_fixed(gamma, std::max(tol, kBf16Switch), max_iter, ds, 0))) return rc;
+    if (ds.status < 0) return R2.finish(ds, false, gamma, tol, max_iter);
+    const int k1 = ds.stop ? ds.final_iter : max_iter;
+    double e1 = 1.0;
+    if (k1 > 0)
+        HIPCHK(hipMemcpy(&e1, im.err_hist + k1, sizeof(double), hipMemcpyDeviceToHost));
+    if (k1 >= max_iter || e1 <= tol || (ds.stop && ds.final_iter == 0)) {
+        if ((rc = R2.widen(X, xdt, k1)) || (rc = R2.read_state(ds))) return rc;
+        return R2.finish(ds, false, gamma, tol, max_iter);
+    }
+    if ((rc = R2.resume(X, xdt))) return rc;
+    if ((rc = R2.loop_fixed(gamma, tol, max_iter, ds, k1))) return rc;
+    return R2.finish(ds, false, gamma, tol, max_iter);
+}
+
 template <typename T, int RP>
 static int run_rp(rtcur_s* h, Impl& im, const void* X, int xdt, const Shape& sh,
                   double zeta0, double gamma, double tol, int max_iter, uint64_t seed) {
+    if constexpr (std::is_same<T, float>::value) {
+        if (h->dtype == RTCUR_BF16)
+            return run_bf16<RP>(h, im, X, xdt, sh, zeta0, gamma, tol, max_iter, seed);
+    }
     Runner<T, RP> R{h, im, h->stream};
     return R.run(X, xdt, sh, zeta0, gamma, tol, max_iter, seed);
 }

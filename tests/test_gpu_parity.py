@@ -280,6 +280,28 @@ def test_cube300_fp32_compute(cube300):
     assert rel(L.cpu().numpy().astype(np.float64), res.reconstruct()) < 1e-4
 
 
+@pytest.mark.parametrize("workload", ["cube100", "cube300"])
+def test_bf16_blocks_with_fp32_refinement(cube100, cube300, workload):
+    # bfloat16 blocks until e^(k) <= 1e-2, then the FP32 refinement sweep:
+    # the returned iterate meets the reduced-precision bar against the FP64
+    # oracle run for the same number of iterations
+    import paper_2108_10448_amd as rt
+    inst, I = cube100 if workload == "cube100" else cube300
+    h, info, _ = run_gpu(inst.X, inst.ranks, I, dtype=torch.bfloat16)
+    e, _ = rt.get_history(h)
+    print(f"[bf16] {workload} iters {info.iters} e {[f'{x:.3e}' for x in e]}", flush=True)
+    assert info.converged and info.eig_unconverged == 0
+    ref = oracle_rtcur(inst.X, inst.ranks, I, None, None, 0.7, 1e-5, 100, 0, "F")
+    assert abs(info.iters - ref.iters) <= 1
+    res = oracle_rtcur(inst.X, inst.ranks, I, None, None, 0.7, 0.0, info.iters, 0, "F")
+    # e^(k) of the bfloat16 iterations carries the blocks' rounding (2^-9
+    # relative per stored entry) in its numerator: bounded by 2 * 2^-9
+    compare(res, h, info, fp64=False, label=f"{workload} bf16", eabs=2 * 2.0 ** -9)
+    L = rt.reconstruct(h)
+    assert L.dtype == torch.float32
+    assert rel(L.cpu().numpy().astype(np.float64), res.reconstruct()) < 1e-4
+
+
 def _outlier_compare(S_g, L_g, S_o, L_o, exact, tol, label):
     sg, so = S_g != 0, S_o != 0
     agree = float(np.mean(sg == so))
