@@ -925,6 +925,48 @@ __device__ __forceinline__ bool gram_assemble(const double* __restrict__ src0, i
     return false;
 }
 
+// As gram_assemble for at most 4 chunks, two neighbouring entries of a tile
+// per thread and 16-byte loads: half the load instructions, so that all of
+// them (E2 x 4) are in flight at once.
+template <int E2>
+__device__ __forceinline__ bool gram_assemble2(const double* __restrict__ src0, int total,
+                                               int nkc, double* G, int sp, const int2* pairs,
+                                               const DevState* st) {
+    for (int f0 = 2 * threadIdx.x; f0 < total; f0 += 2 * E2 * kThreads) {
+        double2 v[E2][4];
+#pragma unroll
+        for (int u = 0; u < E2; ++u) {
+            const int f = f0 + 2 * u * kThreads < total ? f0 + 2 * u * kThreads : f0;
+            const double* src = src0 + (int64_t)(f >> 8) * nkc * 256 + (f & 255);
+#pragma unroll
+            for (int q = 0; q < 4; ++q)  // masked in the sum
+                v[u][q] = *reinterpret_cast<const double2*>(src + (int64_t)(q < nkc ? q : 0) * 256);
+        }
+        // uniform: same f0 in every thread
+        if (f0 == 2 * (int)threadIdx.x && stopped(st)) return true;
+#pragma unroll
+        for (int u = 0; u < E2; ++u) {
+            const int f = f0 + 2 * u * kThreads;
+            if (f >= total) continue;
+            double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (q < nkc) {
+                    s0 += v[u][q].x;
+                    s1 += v[u][q].y;
+                }
+            const int2 pr = pairs[f >> 8];
+            const int t = f & 255;
+            const int a2 = pr.x * 16 + (t >> 4), b2 = pr.y * 16 + (t & 15);
+            G[a2 * (sp + 1) + b2] = s0;
+            G[a2 * (sp + 1) + b2 + 1] = s1;
+            G[b2 * (sp + 1) + a2] = s0;
+            G[(b2 + 1) * (sp + 1) + a2] = s1;
+        }
+    }
+    return false;
+}
+
 // kLdsGram: the Gram sits in dynamic LDS (else in `gram`); a compile-time
 // choice so that its accesses compile to LDS (or global) instructions rather
 // than generic ones.
@@ -953,6 +995,11 @@ __global__ __launch_bounds__(kThreads) void k_eig(Prob P, const double* __restri
         }
         sh.pairs[threadIdx.x] = make_int2(ta, ta + rem);
     }
+    // the warm start's rows load while the Gram is assembled
+    double* Wi = W + P.woff[i];
+    double qw[RP];
+#pragma unroll
+    for (int p = 0; p < RP; ++p) qw[p] = warm ? Wi[(act ? a : 0) * RP + p] : 0.0;
     // Q and Z rows s..sp-1 stay zero for the padded products
     for (int e = s * RP + threadIdx.x; e < sp * RP; e += kThreads) {
         sh.qs[e] = 0.0;
@@ -969,7 +1016,7 @@ __global__ __launch_bounds__(kThreads) void k_eig(Prob P, const double* __restri
         // of 16 chunks, added in chunk order
         bool stop;
         if (nkc <= 4)
-            stop = gram_assemble<24, 4, false>(src0, total, nkc, G, sp, sh.pairs, st);
+            stop = gram_assemble2<12>(src0, total, nkc, G, sp, sh.pairs, st);
         else if (nkc <= 8)
             stop = gram_assemble<12, 8, false>(src0, total, nkc, G, sp, sh.pairs, st);
         else
@@ -977,13 +1024,10 @@ __global__ __launch_bounds__(kThreads) void k_eig(Prob P, const double* __restri
         if (stop) return;
     }
     if (threadIdx.x == 0) sh.ok = 1;
-    double* Wi = W + P.woff[i];
     double q[RP], z[RP];
     if (warm) {
 #pragma unroll
-        for (int p = 0; p < RP; ++p) q[p] = Wi[(act ? a : 0) * RP + p];
-#pragma unroll
-        for (int p = 0; p < RP; ++p) q[p] = (act && p < r) ? q[p] : 0.0;
+        for (int p = 0; p < RP; ++p) q[p] = (act && p < r) ? qw[p] : 0.0;
         __syncthreads();
     } else {
         // start block G * Omega, Omega a fixed +-1 pattern, then CholQR twice
