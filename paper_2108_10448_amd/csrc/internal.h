@@ -99,6 +99,7 @@ struct DevState {
     double den;          // denominator of e^(k) on the current sample
     int eig_steps;
     int eig_unconverged;
+    double e_prev, e_last;  // the last two e^(k) decided (host chunk planning)
     unsigned counter[4]; // last-workgroup counters (gather, ht, spare)
 };
 

@@ -123,7 +123,12 @@ __device__ __forceinline__ int stop_flag(const DevState* st) {
 
 // --------------------------------------------------------------- set-up
 
-__global__ void k_init_state(DevState* st, double zeta0) {
+// Loop state of a new solve, and zeroed factors (so that a k = 0 result
+// reconstructs to L = 0) and error history, in one launch.
+__global__ __launch_bounds__(kThreads) void k_init_state(DevState* st, double zeta0,
+                                                         uint32_t* bf, int64_t bf_words,
+                                                         double* bd, int64_t nbd, double* gd,
+                                                         int ngd, double* hist, int nhist) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         st->stop = 0;
         st->status = 0;
@@ -133,8 +138,16 @@ __global__ void k_init_state(DevState* st, double zeta0) {
         st->den = 0.0;
         st->eig_steps = 0;
         st->eig_unconverged = 0;
+        st->e_prev = -1.0;
+        st->e_last = -1.0;
         for (int j = 0; j < 4; ++j) st->counter[j] = 0u;
     }
+    const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    for (int64_t e = t; e < bf_words; e += stride) bf[e] = 0u;
+    for (int64_t e = t; e < nbd; e += stride) bd[e] = 0.0;
+    for (int64_t e = t; e < ngd; e += stride) gd[e] = 0.0;
+    for (int64_t e = t; e < nhist; e += stride) hist[e] = 0.0;
 }
 
 // Clear the stop flag to continue the loop from the current iterate (the
@@ -381,6 +394,8 @@ __device__ void decide_block(const Prob& P, const double* part, int kcur, double
     if (threadIdx.x == 0) {
         const double e = num / st->den;
         err_hist[kcur] = e;
+        st->e_prev = st->e_last;
+        st->e_last = e;
         if (!isfinite(e)) {
             st->stop = 1;
             st->status = RTCUR_E_NONFINITE;

@@ -597,13 +597,11 @@ struct Runner {
         im.ev_used = 0;
         draw_sample(seed, 0, sh, sh.chidori, h->sample);
         if ((rc = upload_sample(h->sample, sh))) return rc;
-        hipLaunchKernelGGL(k_init_state, dim3(1), dim3(64), 0, s, im.st, zeta0 > 0 ? zeta0 : 0.0);
+        hipLaunchKernelGGL(k_init_state, dim3(16), dim3(kThreads), 0, s, im.st,
+                           zeta0 > 0 ? zeta0 : 0.0, static_cast<uint32_t*>(im.Bf),
+                           (int64_t)(im.bf_elems * sizeof(T) / 4), im.Bd, im.bf_elems, im.Gd,
+                           im.P.core, im.err_hist, (int)im.hist_len);
         HIPCHK(hipGetLastError());
-        // zero factors so that a k = 0 result reconstructs to L = 0
-        HIPCHK(hipMemsetAsync(im.Bf, 0, im.bf_elems * sizeof(T), s));
-        HIPCHK(hipMemsetAsync(im.Bd, 0, im.bf_elems * sizeof(double), s));
-        HIPCHK(hipMemsetAsync(im.Gd, 0, im.P.core * sizeof(double), s));
-        HIPCHK(hipMemsetAsync(im.err_hist, 0, im.hist_len * sizeof(double), s));
         if (!(zeta0 > 0)) {
             int64_t N = 1;
             for (int i = 0; i < sh.n; ++i) N *= sh.d[i];
@@ -713,19 +711,20 @@ struct Runner {
 
     // Iterations j0 + 1 .. (stop or max_iter).  The first of them has no
     // e^(j0) to form when j0 > 0 (it was formed before the loop was resumed).
+    // Iterations are queued in chunks (4 first, then as many as the observed
+    // decay of e^(k) predicts, at most 12); the host reads the device state
+    // once per chunk.  A stop raised inside a chunk makes its remaining
+    // launches return at once.
     int loop_fixed(double gamma, double tol, int max_iter, DevState& ds, int j0) {
         int done = j0;
         int rc;
-        if ((rc = read_state(ds))) return rc;
-        if (ds.stop) return 0;
         double e_prev = -1.0, e_last = -1.0;
-        std::vector<double> eh(2);
         while (done < max_iter) {
-            int chunk = done - j0 < 2 ? 2 : 8;
+            int chunk = done - j0 < 4 ? 4 : 8;
             if (e_last > 0 && e_prev > 0 && e_last < e_prev) {
                 const double rate = e_last / e_prev;
                 const double need = std::log(tol / e_last) / std::log(rate);
-                if (std::isfinite(need)) chunk = (int)std::min(8.0, std::max(1.0, std::ceil(need)));
+                if (std::isfinite(need)) chunk = (int)std::min(12.0, std::max(1.0, std::ceil(need)));
             }
             chunk = std::min(chunk, max_iter - done);
             for (int q = 0; q < chunk; ++q) {
@@ -740,12 +739,8 @@ struct Runner {
             done += chunk;
             if ((rc = read_state(ds))) return rc;
             if (ds.stop) return 0;
-            if (done >= 2 && done - j0 >= 2) {
-                HIPCHK(hipMemcpy(eh.data(), im.err_hist + (done - 2), 2 * sizeof(double),
-                                 hipMemcpyDeviceToHost));
-                e_prev = eh[0];
-                e_last = eh[1];
-            }
+            e_prev = ds.e_prev;
+            e_last = ds.e_last;
         }
         // e^(max_iter): one error-only pass
         tag = max_iter + 1;
