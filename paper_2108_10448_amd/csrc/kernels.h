@@ -1409,10 +1409,18 @@ __device__ void core_slice(const Prob& P, const T* __restrict__ R, const double*
 template <int RP>
 __device__ void core_finish(const Prob& P, const double* __restrict__ W,
                             const double* __restrict__ Tbuf, double* __restrict__ Gd,
-                            double* tb, double* wb) {
+                            double* buf, int cap) {
     const int s0 = P.s[0] * P.cparts, r0 = P.r[0];  // slices: (a, part), part fastest
     const int tot = P.core / r0;
-    const int A = max(1, min((kCoreLds / 2) / tot, (kCoreLds / 2) / RP));
+    // as many slices per round as the LDS buffer holds (all of them when
+    // possible), their T rows and W_0 rows staged together
+    const int A = max(1, min(s0, cap / (tot + RP)));
+    double* tb = buf;
+    double* wb = buf + A * tot;
+    // G groups of threads split the slices of a round; the groups' partial
+    // sums are added in group order
+    const int G = P.core <= kThreads ? max(1, min(8, kThreads / P.core)) : 1;
+    const int g = threadIdx.x / P.core;
     constexpr int JM = kMaxCore / kThreads;
     double acc[JM];
 #pragma unroll
@@ -1425,14 +1433,34 @@ __device__ void core_finish(const Prob& P, const double* __restrict__ W,
         for (int e = threadIdx.x; e < na * RP; e += kThreads)
             wb[e] = W[P.woff[0] + (int64_t)((a0 + e / RP) / P.cparts) * RP + e % RP];
         __syncthreads();
-#pragma unroll
-        for (int j = 0; j < JM; ++j) {
-            const int o = threadIdx.x + j * kThreads;
-            if (o < P.core) {
+        if (G > 1) {
+            if (g < G) {
+                const int o = threadIdx.x - g * P.core;
                 const int p = o / tot, rest = o % tot;
-                acc[j] += lds_dot<double>(wb + p, RP, tb + rest, tot, na);
+                const int k0 = g * na / G, k1 = (g + 1) * na / G;
+                acc[0] += lds_dot<double>(wb + k0 * RP + p, RP, tb + k0 * tot + rest, tot, k1 - k0);
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < JM; ++j) {
+                const int o = threadIdx.x + j * kThreads;
+                if (o < P.core) {
+                    const int p = o / tot, rest = o % tot;
+                    acc[j] += lds_dot<double>(wb + p, RP, tb + rest, tot, na);
+                }
             }
         }
+    }
+    if (G > 1) {
+        __syncthreads();
+        if (g < G) buf[threadIdx.x] = acc[0];
+        __syncthreads();
+        if (threadIdx.x < P.core) {
+            double v = 0.0;
+            for (int q = 0; q < G; ++q) v += buf[q * P.core + threadIdx.x];
+            Gd[threadIdx.x] = v;
+        }
+        return;
     }
 #pragma unroll
     for (int j = 0; j < JM; ++j) {
@@ -1488,7 +1516,7 @@ __global__ __launch_bounds__(kThreads) void k_bfac(Prob P, const T* __restrict__
         // the core G = sum_a W_0[a]^T T[a] from k_zcore's slices, beside the
         // B-factor items
         if (sf) return;
-        core_finish<RP>(P, W, Tbuf, Gd, zs, zs + kCoreLds / 2);
+        core_finish<RP>(P, W, Tbuf, Gd, zs, KC * RP);
         return;
     }
     const int4 it = items[blockIdx.x];
@@ -1895,44 +1923,64 @@ __global__ __launch_bounds__(kThreads) void k_hexp(
         for (int q = 0; q < N - 1; ++q)
             rowoff[q] = P.boff[others[q]] + (int64_t)bd.cidx[(int64_t)q * ncols + cc] * RP;
     }
-    {
-        T bv[N - 1][RP];
+    T bv[N - 1][RP];
 #pragma unroll
-        for (int q = 0; q < N - 1; ++q)
+    for (int q = 0; q < N - 1; ++q)
 #pragma unroll
-            for (int k = 0; k < RP; ++k) bv[q][k] = Bf[rowoff[q] + k];
-        if (sf) return;
+        for (int k = 0; k < RP; ++k) bv[q][k] = Bf[rowoff[q] + k];
+    if (sf) return;
+    const int64_t hoff = dense ? 0 : P.blk[tl.x].hoff;
+    if constexpr (N <= 3) {
+        // the B rows stay in registers: the q and u loops are unrolled to RP
+        // and masked at the true ranks, so the core's LDS reads pipeline
+        double v0[RP], v1[RP];
 #pragma unroll
-        for (int q = 0; q < N - 1; ++q)
+        for (int k = 0; k < RP; ++k) {
+            v0[k] = (double)bv[0][k];
+            v1[k] = N == 3 ? (double)bv[N == 3 ? 1 : 0][k] : 0.0;
+        }
+        __syncthreads();  // gp staged
+        for (int p = 0; p < RP; ++p) {
+            double a = 0.0;
+            if (p < rm) {
 #pragma unroll
-            for (int k = 0; k < RP; ++k) vs[(q * RP + k) * kThreads + tid] = (double)bv[q][k];
+                for (int q = 0; q < RP; ++q) {
+                    if (q < r0) {
+                        double t1;
+                        if constexpr (N == 2) {
+                            t1 = gp[p * r0 + q];
+                        } else {
+                            t1 = 0.0;
+#pragma unroll
+                            for (int u = 0; u < RP; ++u)
+                                if (u < r1) t1 = fma(gp[(p * r0 + q) * r1 + u], v1[u], t1);
+                        }
+                        a = fma(t1, v0[q], a);
+                    }
+                }
+            }
+            if (c < ncols) H[hoff + (int64_t)p * ncols + c] = (T)a;
+        }
+        return;
     }
+#pragma unroll
+    for (int q = 0; q < N - 1; ++q)
+#pragma unroll
+        for (int k = 0; k < RP; ++k) vs[(q * RP + k) * kThreads + tid] = (double)bv[q][k];
     __syncthreads();
     const double* v0 = vs + tid;
     const double* v1 = vs + RP * kThreads + tid;
     const double* v2 = vs + 2 * RP * kThreads + tid;
-    const int64_t hoff = dense ? 0 : P.blk[tl.x].hoff;
     for (int p = 0; p < RP; ++p) {
         double a = 0.0;
         if (p < rm) {
             for (int q = 0; q < r0; ++q) {
-                double t1;
-                if constexpr (N == 2) {
-                    t1 = gp[p * r0 + q];
-                } else {
-                    t1 = 0.0;
-                    for (int u = 0; u < r1; ++u) {
-                        double t2;
-                        if constexpr (N == 3) {
-                            t2 = gp[(p * r0 + q) * r1 + u];
-                        } else {
-                            t2 = 0.0;
-                            for (int z = 0; z < r2; ++z)
-                                t2 = fma(gp[((p * r0 + q) * r1 + u) * r2 + z],
-                                         v2[z * kThreads], t2);
-                        }
-                        t1 = fma(t2, v1[u * kThreads], t1);
-                    }
+                double t1 = 0.0;
+                for (int u = 0; u < r1; ++u) {
+                    double t2 = 0.0;
+                    for (int z = 0; z < r2; ++z)
+                        t2 = fma(gp[((p * r0 + q) * r1 + u) * r2 + z], v2[z * kThreads], t2);
+                    t1 = fma(t2, v1[u * kThreads], t1);
                 }
                 a = fma(t1, v0[q * kThreads], a);
             }
