@@ -522,8 +522,9 @@ __global__ __launch_bounds__(kThreads) void k_gram(
 // Top-r eigenspace of Gram_i = U_i U_i^T in float64, one 256-thread
 // workgroup per mode, thread a owning row a of the s x r iterates: the Gram
 // is assembled (in LDS when it fits) from k_gram's tiles; subspace
-// iteration (warm-started from the previous iterate's W_i under RTCUR-F)
-// with Cholesky-QR orthonormalisation runs until the residual
+// iteration (warm-started from the previous iterate's W_i under RTCUR-F,
+// from the previous B_i's rows at the new I_i under RTCUR-R) with
+// Cholesky-QR orthonormalisation runs until the residual
 // ||G Q - Q T||_F <= rtol ||T||_F with T = Q^T G Q.  Then W_i = Q and
 // Y_i = Q T^-1, so that the truncated pseudo-inverse is
 // U_i^+ = U_i^T Y_i W_i^T: the operator V_r S_r^-1 W_r^T of the SVD written
@@ -989,7 +990,8 @@ template <int RP, bool kLdsGram>
 __global__ __launch_bounds__(kThreads) void k_eig(Prob P, const double* __restrict__ gpart,
                                                   double* __restrict__ gram,
                                                   double* __restrict__ W,
-                                                  double* __restrict__ Y, int warm,
+                                                  double* __restrict__ Y,
+                                                  const double* __restrict__ Bd, int warm,
                                                   int maxit, double rtol, DevState* st) {
     extern __shared__ double Gl[];  // sp x sp (row stride sp + 1), when it fits
     __shared__ EigShared<RP> sh;
@@ -1014,7 +1016,7 @@ __global__ __launch_bounds__(kThreads) void k_eig(Prob P, const double* __restri
     double* Wi = W + P.woff[i];
     double qw[RP];
 #pragma unroll
-    for (int p = 0; p < RP; ++p) qw[p] = warm ? Wi[(act ? a : 0) * RP + p] : 0.0;
+    for (int p = 0; p < RP; ++p) qw[p] = warm == 1 ? Wi[(act ? a : 0) * RP + p] : 0.0;
     // Q and Z rows s..sp-1 stay zero for the padded products
     for (int e = s * RP + threadIdx.x; e < sp * RP; e += kThreads) {
         sh.qs[e] = 0.0;
@@ -1040,34 +1042,43 @@ __global__ __launch_bounds__(kThreads) void k_eig(Prob P, const double* __restri
     }
     if (threadIdx.x == 0) sh.ok = 1;
     double q[RP], z[RP];
-    if (warm) {
+    if (warm == 1) {
 #pragma unroll
         for (int p = 0; p < RP; ++p) q[p] = (act && p < r) ? qw[p] : 0.0;
         __syncthreads();
     } else {
-        // start block G * Omega, Omega a fixed +-1 pattern, then CholQR twice
-        for (int e = threadIdx.x; e < s * RP; e += kThreads) {
-            const int b = e / RP, p = e % RP;
-            sh.qs[e] = p < r ? ((eig_hash(b, p) & 1u) ? 1.0 : -1.0) : 0.0;
-        }
-        __syncthreads();
-        eig_gq<RP>(G, sp, s, sh);
+        // start block G * Omega, then Cholesky-QR twice.  Omega: with
+        // warm == 2 (a new sample under RTCUR-R) the previous mode-i factor's
+        // rows at the new I_i, which span nearly the wanted subspace; else,
+        // or if that block loses rank, a fixed +-1 pattern
+        bool ok = false;
+        for (int att = warm == 2 ? 0 : 1; att < 2 && !ok; ++att) {
+            __syncthreads();
+            for (int e = threadIdx.x; e < s * RP; e += kThreads) {
+                const int b = e / RP, p = e % RP;
+                const double pm = (eig_hash(b, p) & 1u) ? 1.0 : -1.0;
+                const double v = att == 0 ? Bd[P.boff[i] + (int64_t)P.I[i][b] * RP + p] : pm;
+                sh.qs[e] = p < r ? v : 0.0;
+            }
+            __syncthreads();
+            eig_gq<RP>(G, sp, s, sh);
 #pragma unroll
-        for (int p = 0; p < RP; ++p) z[p] = act ? sh.zs[a * RP + p] : 0.0;
-        bool ok = true;
-        for (int rep = 0; rep < 2 && ok; ++rep) {
-            eig_tm<RP>(sp, false, sh);  // M = Z^T Z
-            double R[RP][RP], di[RP];
-            ok = eig_chol<RP>(sh.mm, r, R, di);
-            if (ok) {
-                eig_trsm<RP>(z, R, di, q);
+            for (int p = 0; p < RP; ++p) z[p] = act ? sh.zs[a * RP + p] : 0.0;
+            ok = true;
+            for (int rep = 0; rep < 2 && ok; ++rep) {
+                eig_tm<RP>(sp, false, sh);  // M = Z^T Z
+                double R[RP][RP], di[RP];
+                ok = eig_chol<RP>(sh.mm, r, R, di);  // same value in every thread
+                if (ok) {
+                    eig_trsm<RP>(z, R, di, q);
 #pragma unroll
-                for (int p = 0; p < RP; ++p) z[p] = q[p];
-                if (rep == 0 && act) {
+                    for (int p = 0; p < RP; ++p) z[p] = q[p];
+                    if (rep == 0 && act) {
 #pragma unroll
-                    for (int p = 0; p < RP; ++p) sh.zs[a * RP + p] = z[p];
+                        for (int p = 0; p < RP; ++p) sh.zs[a * RP + p] = z[p];
+                    }
+                    __syncthreads();
                 }
-                __syncthreads();
             }
         }
         if (!ok) {

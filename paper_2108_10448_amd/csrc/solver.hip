@@ -523,11 +523,11 @@ struct Runner {
         HIPCHK(pb(PK_EIG));
         if (use_lds)
             hipLaunchKernelGGL((k_eig<RP, true>), dim3(n), dim3(kThreads), lds_g, s, P,
-                               (const double*)im.gpart, im.gram, im.W, im.Y, warm, 200, rtol,
+                               (const double*)im.gpart, im.gram, im.W, im.Y, im.Bd, warm, 200, rtol,
                                im.st);
         else
             hipLaunchKernelGGL((k_eig<RP, false>), dim3(n), dim3(kThreads), 0, s, P,
-                               (const double*)im.gpart, im.gram, im.W, im.Y, warm, 200, rtol,
+                               (const double*)im.gpart, im.gram, im.W, im.Y, im.Bd, warm, 200, rtol,
                                im.st);
         HIPCHK(hipGetLastError());
         HIPCHK(pe());
@@ -766,7 +766,9 @@ struct Runner {
             }
             const int flags = kDoHT | (j > 1 ? kHaveL : 0);
             if ((rc = ht(j - 1, flags, nullptr, cbuf(j), im.mask[j % 2], gamma))) return rc;
-            if ((rc = lupdate(cbuf(j), 0, 0, j - 1, tol))) return rc;
+            // the eigensolver starts from the previous factors' rows at the
+            // new sample (j > 1)
+            if ((rc = lupdate(cbuf(j), j > 1 ? 2 : 0, 0, j - 1, tol))) return rc;
             // e^(j) on this sample
             if ((rc = ht(j, kHaveL | kDoE | kDecide, cbuf(j), nullptr, nullptr, gamma))) return rc;
             if ((rc = decide(j, tol))) return rc;
