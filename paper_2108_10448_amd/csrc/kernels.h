@@ -31,7 +31,8 @@ constexpr int kGramKCGroup = 4;    // chunks summed per load round in the eigens
 constexpr int kBfacRowsPerWave = 4;
 constexpr int kBfacRows = 4 * kBfacRowsPerWave;
 
-enum HtFlags { kHaveL = 1, kDoE = 2, kDoHT = 4, kDecide = 8, kFirstGather = 16 };
+enum HtFlags { kHaveL = 1, kDoE = 2, kDoHT = 4, kDecide = 8, kFirstGather = 16,
+               kIfRunning = 32 /* gather: skip once the stop flag is raised */ };
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
@@ -161,6 +162,18 @@ __global__ void k_resume(DevState* st) {
     }
 }
 
+// The next sample's index data from its staging slot into the index region
+// (RTCUR-R with iterations queued ahead), unless the loop has stopped: the
+// returned iterate keeps its own sample.  nbytes is a multiple of 16.
+__global__ __launch_bounds__(kThreads) void k_take_sample(uint4* __restrict__ dst,
+                                                          const uint4* __restrict__ src,
+                                                          int64_t n16, const DevState* st) {
+    if (stopped(st)) return;
+    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < n16;
+         e += (int64_t)gridDim.x * kThreads)
+        dst[e] = src[e];
+}
+
 // bfloat16 block entries to float (exact).
 __global__ __launch_bounds__(kThreads) void k_widen(const __hip_bfloat16* __restrict__ in,
                                                     int64_t N, float* __restrict__ out) {
@@ -226,8 +239,9 @@ __global__ __launch_bounds__(kThreads) void k_absmax_fin(const double* part, int
 template <typename TX, typename T>
 __global__ __launch_bounds__(kThreads) void k_gather(
     const TX* __restrict__ X, Prob P, const int4* __restrict__ tiles,
-    T* __restrict__ XO, double* part) {
+    T* __restrict__ XO, double* part, const DevState* st, int flags) {
     __shared__ double red[4];
+    if ((flags & kIfRunning) && stopped(st)) return;  // uniform
     const int4 tl = tiles[blockIdx.x];
     const BlockDev& bd = P.blk[tl.x];
     const int c = tl.z + threadIdx.x;
@@ -266,6 +280,7 @@ __global__ __launch_bounds__(kThreads) void k_gather(
 __global__ __launch_bounds__(kThreads) void k_den(Prob P, const double* part, int flags,
                                                   DevState* st) {
     __shared__ double red[4];
+    if ((flags & kIfRunning) && stopped(st)) return;  // uniform
     double den = 0.0, badall = 0.0;
     for (int b = 0; b < P.nblk; ++b) {
         double v = 0.0, w = 0.0;

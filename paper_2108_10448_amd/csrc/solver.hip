@@ -79,6 +79,9 @@ struct Impl {
     void* scratch = nullptr;        // getters / reconstruct temporaries
     size_t scratch_bytes = 0;
     DevState* st_host = nullptr;    // pinned mirror of the device state
+    char* d_stage = nullptr;        // RTCUR-R: index data of queued samples
+    char* h_stage = nullptr;        //   (device slots and their pinned source)
+    size_t stage_bytes = 0;
     int max_dyn_lds[3] = {0, 0, 0};  // k_eig<4|8|16, true>: room for the Gram
 
     // layout of the current solve
@@ -120,6 +123,8 @@ void release(rtcur_s* h) {
     if (im->arena) (void)hipFree(im->arena);
     if (im->scratch) (void)hipFree(im->scratch);
     if (im->st_host) (void)hipHostFree(im->st_host);
+    if (im->d_stage) (void)hipFree(im->d_stage);
+    if (im->h_stage) (void)hipHostFree(im->h_stage);
     for (hipEvent_t e : im->events) (void)hipEventDestroy(e);
     delete im;
     h->impl = nullptr;
@@ -402,6 +407,8 @@ static void launch_hexp(const Prob& P, bool runs, unsigned grid, hipStream_t st,
     }
 }
 
+constexpr int kRChunk = 8;  // RTCUR-R: iterations queued per state read
+
 // T: factor and arithmetic type; TB: block storage type (T, or bfloat16
 // with T = float for the bfloat16 iterations).
 template <typename T, int RP, typename TB = T>
@@ -458,10 +465,12 @@ struct Runner {
         HIPCHK(pb(PK_GATHER));
         if (xdt == RTCUR_F64)
             hipLaunchKernelGGL((k_gather<double, TB>), dim3(nt), dim3(kThreads), 0, s,
-                               (const double*)X, im.P, im.d_ht_tiles, (TB*)im.XO, im.part);
+                               (const double*)X, im.P, im.d_ht_tiles, (TB*)im.XO, im.part,
+                               (const DevState*)im.st, flags);
         else
             hipLaunchKernelGGL((k_gather<float, TB>), dim3(nt), dim3(kThreads), 0, s,
-                               (const float*)X, im.P, im.d_ht_tiles, (TB*)im.XO, im.part);
+                               (const float*)X, im.P, im.d_ht_tiles, (TB*)im.XO, im.part,
+                               (const DevState*)im.st, flags);
         HIPCHK(hipGetLastError());
         hipLaunchKernelGGL(k_den, dim3(1), dim3(kThreads), 0, s, im.P, (const double*)im.part,
                            flags, im.st);
@@ -586,6 +595,42 @@ struct Runner {
             P.blk[b].colx = reinterpret_cast<const int64_t*>(im.d_idx + pk.colx_off[b]);
             P.blk[b].cidx = reinterpret_cast<const int32_t*>(im.d_idx + pk.cidx_off[b]);
         }
+        return 0;
+    }
+
+    // Queue a sample's index data for an iteration ahead (RTCUR-R): packed
+    // into pinned slot `slot`, copied to its device slot in stream order and
+    // taken into the index region by k_take_sample unless the loop stopped.
+    int stage_sample(const SampleHost& smp, const Shape& sh, int slot) {
+        IdxPack pk;
+        pack_indices(sh, smp, pk);
+        if (pk.bytes.size() != im.idx_bytes || im.idx_bytes % 16) {
+            h->last_error = "internal: index layout changed";
+            return RTCUR_E_STATE;
+        }
+        const size_t need = (size_t)kRChunk * im.idx_bytes;
+        if (need > im.stage_bytes) {
+            if (im.d_stage) HIPCHK(hipFree(im.d_stage));
+            if (im.h_stage) HIPCHK(hipHostFree(im.h_stage));
+            im.d_stage = im.h_stage = nullptr;
+            im.stage_bytes = 0;
+            if (hipMalloc(reinterpret_cast<void**>(&im.d_stage), need) != hipSuccess ||
+                hipHostMalloc(reinterpret_cast<void**>(&im.h_stage), need,
+                              hipHostMallocDefault) != hipSuccess) {
+                (void)hipGetLastError();
+                h->last_error = "staging allocation failed";
+                return RTCUR_E_NOMEM;
+            }
+            im.stage_bytes = need;
+        }
+        char* hs = im.h_stage + (size_t)slot * im.idx_bytes;
+        char* ds = im.d_stage + (size_t)slot * im.idx_bytes;
+        std::memcpy(hs, pk.bytes.data(), im.idx_bytes);
+        HIPCHK(hipMemcpyAsync(ds, hs, im.idx_bytes, hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_take_sample, dim3(64), dim3(kThreads), 0, s,
+                           reinterpret_cast<uint4*>(im.d_idx), reinterpret_cast<const uint4*>(ds),
+                           (int64_t)(im.idx_bytes / 16), (const DevState*)im.st);
+        HIPCHK(hipGetLastError());
         return 0;
     }
 
@@ -750,30 +795,56 @@ struct Runner {
         return read_state(ds);
     }
 
+    // RTCUR-R with iterations queued in chunks as under RTCUR-F: the host
+    // draws the chunk's samples ahead and stages their index data; a stop
+    // raised inside the chunk makes the rest of it (sample take, gathers and
+    // kernels) return at once, so the device keeps the returned iterate's
+    // sample and blocks, and the host keeps that sample too.
     int loop_resample(const void* X, int xdt, const Shape& sh, double gamma, double tol,
                       int max_iter, uint64_t seed, DevState& ds) {
         int rc;
-        if ((rc = read_state(ds))) return rc;
-        if (ds.stop) return 0;
-        for (int j = 1; j <= max_iter; ++j) {
-            tag = j;
-            if (j > 1) {
-                // new sample (t = j-1), gather there, L^(j-1) on its columns
-                draw_sample(seed, j - 1, sh, sh.chidori, h->sample);
-                if ((rc = upload_sample(h->sample, sh))) return rc;
-                if ((rc = gather(X, xdt, 0))) return rc;
-                if ((rc = hexp())) return rc;
+        std::vector<SampleHost> smp(kRChunk);
+        int done = 0;
+        double e_prev = -1.0, e_last = -1.0;
+        while (done < max_iter) {
+            int chunk = done < 4 ? 4 : kRChunk;
+            if (e_last > 0 && e_prev > 0 && e_last < e_prev) {
+                const double rate = e_last / e_prev;
+                const double need = std::log(tol / e_last) / std::log(rate);
+                if (std::isfinite(need))
+                    chunk = (int)std::min<double>(kRChunk, std::max(1.0, std::ceil(need)));
             }
-            const int flags = kDoHT | (j > 1 ? kHaveL : 0);
-            if ((rc = ht(j - 1, flags, nullptr, cbuf(j), im.mask[j % 2], gamma))) return rc;
-            // the eigensolver starts from the previous factors' rows at the
-            // new sample (j > 1)
-            if ((rc = lupdate(cbuf(j), j > 1 ? 2 : 0, 0, j - 1, tol))) return rc;
-            // e^(j) on this sample
-            if ((rc = ht(j, kHaveL | kDoE | kDecide, cbuf(j), nullptr, nullptr, gamma))) return rc;
-            if ((rc = decide(j, tol))) return rc;
+            chunk = std::min(chunk, max_iter - done);
+            for (int q = 0; q < chunk; ++q) {
+                const int j = done + 1 + q;
+                tag = j;
+                if (j > 1) {
+                    // new sample (t = j-1), gather there, L^(j-1) on its columns
+                    draw_sample(seed, j - 1, sh, sh.chidori, smp[q]);
+                    if ((rc = stage_sample(smp[q], sh, q))) return rc;
+                    if ((rc = gather(X, xdt, kIfRunning))) return rc;
+                    if ((rc = hexp())) return rc;
+                }
+                const int flags = kDoHT | (j > 1 ? kHaveL : 0);
+                if ((rc = ht(j - 1, flags, nullptr, cbuf(j), im.mask[j % 2], gamma))) return rc;
+                // the eigensolver starts from the previous factors' rows at the
+                // new sample (j > 1)
+                if ((rc = lupdate(cbuf(j), j > 1 ? 2 : 0, 0, j - 1, tol))) return rc;
+                // e^(j) on this sample
+                if ((rc = ht(j, kHaveL | kDoE | kDecide, cbuf(j), nullptr, nullptr, gamma)))
+                    return rc;
+                if ((rc = decide(j, tol))) return rc;
+            }
             if ((rc = read_state(ds))) return rc;
+            const int last = ds.stop ? ds.final_iter : done + chunk;
+            // iteration j > 1 of this chunk drew smp[j - done - 1]; iteration 1
+            // kept the sample of the set-up
+            if (last > 1 && last > done && last <= done + chunk)
+                h->sample = std::move(smp[last - done - 1]);
             if (ds.stop) return 0;
+            done += chunk;
+            e_prev = ds.e_prev;
+            e_last = ds.e_last;
         }
         return 0;
     }
