@@ -956,21 +956,21 @@ __device__ __forceinline__ bool gram_assemble(const double* __restrict__ src0, i
     return false;
 }
 
-// As gram_assemble for at most 4 chunks, two neighbouring entries of a tile
+// As gram_assemble for at most KG chunks, two neighbouring entries of a tile
 // per thread and 16-byte loads: half the load instructions, so that all of
-// them (E2 x 4) are in flight at once.
-template <int E2>
+// them (E2 x KG) are in flight at once.
+template <int E2, int KG>
 __device__ __forceinline__ bool gram_assemble2(const double* __restrict__ src0, int total,
                                                int nkc, double* G, int sp, const int2* pairs,
                                                const DevState* st) {
     for (int f0 = 2 * threadIdx.x; f0 < total; f0 += 2 * E2 * kThreads) {
-        double2 v[E2][4];
+        double2 v[E2][KG];
 #pragma unroll
         for (int u = 0; u < E2; ++u) {
             const int f = f0 + 2 * u * kThreads < total ? f0 + 2 * u * kThreads : f0;
             const double* src = src0 + (int64_t)(f >> 8) * nkc * 256 + (f & 255);
 #pragma unroll
-            for (int q = 0; q < 4; ++q)  // masked in the sum
+            for (int q = 0; q < KG; ++q)  // masked in the sum
                 v[u][q] = *reinterpret_cast<const double2*>(src + (int64_t)(q < nkc ? q : 0) * 256);
         }
         // uniform: same f0 in every thread
@@ -981,7 +981,7 @@ __device__ __forceinline__ bool gram_assemble2(const double* __restrict__ src0, 
             if (f >= total) continue;
             double s0 = 0.0, s1 = 0.0;
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
+            for (int q = 0; q < KG; ++q)
                 if (q < nkc) {
                     s0 += v[u][q].x;
                     s1 += v[u][q].y;
@@ -1048,9 +1048,9 @@ __global__ __launch_bounds__(kThreads) void k_eig(Prob P, const double* __restri
         // of 16 chunks, added in chunk order
         bool stop;
         if (nkc <= 4)
-            stop = gram_assemble2<12>(src0, total, nkc, G, sp, sh.pairs, st);
+            stop = gram_assemble2<12, 4>(src0, total, nkc, G, sp, sh.pairs, st);
         else if (nkc <= 8)
-            stop = gram_assemble<12, 8, false>(src0, total, nkc, G, sp, sh.pairs, st);
+            stop = gram_assemble2<6, 8>(src0, total, nkc, G, sp, sh.pairs, st);
         else
             stop = gram_assemble<4, 16, true>(src0, total, nkc, G, sp, sh.pairs, st);
         if (stop) return;
