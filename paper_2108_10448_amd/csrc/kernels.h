@@ -554,6 +554,13 @@ __device__ __forceinline__ uint32_t eig_hash(uint32_t a, uint32_t b) {
     return h;
 }
 
+// Start-block entry (row a, column p) uniform in (-1, 1) from the hash's top
+// 24 bits: such a block has full column rank with probability one (a +-1
+// pattern need not: the 10 x 5 one of this hash has rank 4).
+__device__ __forceinline__ double eig_start(uint32_t a, uint32_t p, uint32_t salt) {
+    return (double)(eig_hash(a, p + 131u * salt) >> 8) * 0x1p-23 - 1.0 + 0x1p-24;
+}
+
 template <int RP>
 struct EigShared {
     double qs[kMaxS * RP];                 // Q rows; rows s..sp-1 stay zero
@@ -819,7 +826,7 @@ __device__ __noinline__ int eig_guarded(const double* G, int sp, int s, int r, i
     for (int p = 0; p < RP; ++p) q[p] = act ? sh.qs[a * RP + p] : 0.0;
 #pragma unroll
     for (int p = 0; p < RP; ++p)
-        x[p] = p < r ? q[p] : ((act && p < m) ? ((eig_hash(a, p + 977) & 1u) ? 1.0 : -1.0) : 0.0);
+        x[p] = p < r ? q[p] : ((act && p < m) ? eig_start(a, p, 7u) : 0.0);
     int res = 0;
     for (int it = 0; it <= kEigGuardMax; ++it, ++steps) {
         __syncthreads();
@@ -1065,14 +1072,16 @@ __global__ __launch_bounds__(kThreads) void k_eig(Prob P, const double* __restri
         // start block G * Omega, then Cholesky-QR twice.  Omega: with
         // warm == 2 (a new sample under RTCUR-R) the previous mode-i factor's
         // rows at the new I_i, which span nearly the wanted subspace; else,
-        // or if that block loses rank, a fixed +-1 pattern
+        // or if that block loses rank, a fixed pseudo-random block (a second
+        // one if G * Omega still loses rank; only a Gram of rank below r
+        // fails both)
         bool ok = false;
-        for (int att = warm == 2 ? 0 : 1; att < 2 && !ok; ++att) {
+        for (int att = warm == 2 ? 0 : 1; att < 3 && !ok; ++att) {
             __syncthreads();
             for (int e = threadIdx.x; e < s * RP; e += kThreads) {
                 const int b = e / RP, p = e % RP;
-                const double pm = (eig_hash(b, p) & 1u) ? 1.0 : -1.0;
-                const double v = att == 0 ? Bd[P.boff[i] + (int64_t)P.I[i][b] * RP + p] : pm;
+                const double v = att == 0 ? Bd[P.boff[i] + (int64_t)P.I[i][b] * RP + p]
+                                          : eig_start(b, p, att);
                 sh.qs[e] = p < r ? v : 0.0;
             }
             __syncthreads();

@@ -1,0 +1,54 @@
+"""GPU parity on seeded random problem shapes: 2 to 4 modes, uneven sizes
+and ranks, chidori and fibre sampling, RTCUR-F and RTCUR-R, float64 and
+float32 blocks, each against the FP64 oracle for a fixed number of
+iterations (tol = 0), at the same bars as the named workloads."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import rtcur as oracle_rtcur
+
+from _parity import compare, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _case(k):
+    rng = np.random.default_rng(1000 + k)
+    n = int(rng.integers(2, 5))
+    dims = [int(rng.integers(6, 40 if n == 4 else 90)) for _ in range(n)]
+    ranks = [int(rng.integers(1, min(6, d) + 1)) for d in dims]
+    # sample sizes between r_i and d_i; the core slice stays within its limit
+    I = [int(rng.integers(r, d + 1)) for r, d in zip(ranks, dims)]
+    fiber = bool(rng.integers(0, 2)) and n >= 3
+    J = None
+    if fiber:
+        J = []
+        for i in range(n):
+            P = int(np.prod([dims[j] for j in range(n) if j != i]))
+            J.append(int(rng.integers(ranks[i], min(P, 400) + 1)))
+    variant = "R" if rng.integers(0, 3) == 0 else "F"
+    dtype = "f32" if rng.integers(0, 3) == 0 else "f64"
+    alpha = float(rng.uniform(0.0, 0.3))
+    return n, dims, ranks, I, J, variant, dtype, alpha
+
+
+@pytest.mark.parametrize("k", range(12))
+def test_random_shape(k):
+    n, dims, ranks, I, J, variant, dtype, alpha = _case(k)
+    slice_ = ranks[-1] * int(np.prod(I[1:-1])) if n > 2 else ranks[-1]
+    if slice_ > 2048 or int(np.prod(ranks)) > 4096:
+        pytest.skip("outside the library's documented limits")
+    inst = synth.tucker_plus_sparse(dims, ranks, alpha=alpha, seed=50 + k)
+    X = inst.X if dtype == "f64" else inst.X.astype(np.float32)
+    K = 4
+    label = f"{dims} r={ranks} I={I} J={J} {variant} {dtype}"
+    res = oracle_rtcur(X, inst.ranks, I, J, None, 0.7, 0.0, K, 7 + k, variant)
+    h, info, _ = run_gpu(X, inst.ranks, I, J, tol=0.0, max_iter=K, seed=7 + k,
+                         variant=variant, check=False,
+                         dtype=torch.float64 if dtype == "f64" else torch.float32)
+    assert info.status >= 0, label
+    assert info.iters == res.iters == K, label
+    compare(res, h, info, fp64=dtype == "f64", label=label)
