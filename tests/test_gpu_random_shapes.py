@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import synth
-from oracle import E_RANK, OracleError
+from oracle import E_INVAL, E_RANK, OracleError
 from oracle import rtcur as oracle_rtcur
 
 from _parity import compare, run_gpu
@@ -61,16 +61,46 @@ def test_random_shape(k):
     label = f"{dims} r={ranks} I={I} J={J} {variant} {dtype}"
     try:
         res = oracle_rtcur(X, inst.ranks, I, J, None, 0.7, 0.0, K, 7 + k, variant)
+        want = None
     except OracleError as e:
-        # the oracle's rank floor: the library's test flags whenever it does
-        assert e.status == E_RANK, label
-        res = None
+        # invalid sizes, or the oracle's rank floor (the library's rank test
+        # flags whenever the oracle's does): the library must agree
+        assert e.status in (E_INVAL, E_RANK), label
+        res, want = None, e.status
     h, info, _ = run_gpu(X, inst.ranks, I, J, tol=0.0, max_iter=K, seed=7 + k,
                          variant=variant, check=False,
                          dtype=torch.float64 if dtype == "f64" else torch.float32)
     if res is None:
-        assert info.status == E_RANK, label
+        assert info.status == want, (label, info.status, want)
         return
     assert info.status >= 0, label
     assert info.iters == res.iters == K, label
     compare(res, h, info, fp64=dtype == "f64", label=label)
+
+
+@pytest.mark.parametrize("j", range(8))
+def test_random_shape_to_tolerance(j):
+    # to tol 1e-6 in float64: the iteration count must match the oracle's
+    # (unless e^(k) sits within 1e-9 of tol) and so must the returned iterate
+    n, dims, ranks, I, J, variant, _, alpha = _case(200 + j)
+    slice_ = ranks[-1] * int(np.prod(I[1:-1])) if n > 2 else ranks[-1]
+    if slice_ > 2048 or int(np.prod(ranks)) > 4096:
+        pytest.skip("outside the library's documented limits")
+    inst = synth.tucker_plus_sparse(dims, ranks, alpha=min(alpha, 0.15), seed=300 + j)
+    label = f"{dims} r={ranks} I={I} J={J} {variant} to tol"
+    try:
+        res = oracle_rtcur(inst.X, inst.ranks, I, J, None, 0.7, 1e-6, 100, 3 + j, variant)
+    except OracleError as e:
+        assert e.status in (E_INVAL, E_RANK), label
+        h, info, _ = run_gpu(inst.X, inst.ranks, I, J, tol=1e-6, max_iter=100, seed=3 + j,
+                             variant=variant, check=False)
+        assert info.status == e.status, (label, info.status, e.status)
+        return
+    h, info, _ = run_gpu(inst.X, inst.ranks, I, J, tol=1e-6, max_iter=100, seed=3 + j,
+                         variant=variant, check=False)
+    assert info.status >= 0, label
+    near = any(abs(e - 1e-6) <= 1e-9 * 1e-6 for e in res.err_hist)
+    if not near:
+        assert info.iters == res.iters, (label, info.iters, res.iters)
+    if info.iters == res.iters:
+        compare(res, h, info, fp64=True, label=label)
