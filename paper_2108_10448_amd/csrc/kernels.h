@@ -567,6 +567,7 @@ struct EigShared {
     double zs[kMaxS * RP];                 // Z = G Q rows; rows s..sp-1 stay zero
     double tm[RP * RP], mm[RP * RP];       // T = Q^T Z, M = Z^T Z
     double part[4][256];                   // per-wave 16 x 16 MFMA partials
+    double part2[4][256];                  // second set (T and M together)
     double red[4];
     int2 pairs[(kMaxS / 16) * (kMaxS / 16 + 1) / 2];  // Gram tile pair -> (ta, tb)
     double vv[RP * RP];                    // Rayleigh-Ritz: eigenvectors of T
@@ -1005,6 +1006,58 @@ __device__ __forceinline__ bool gram_assemble2(const double* __restrict__ src0, 
     return false;
 }
 
+// Z = G Q into zs as eig_gq, with T = Q^T Z and M = Z^T Z formed from each
+// Z tile while it is still in the accumulators: register v of lane l holds
+// Z[16t + 4v + l/16][l%16], which is exactly the B operand (row k = l/16,
+// column l%16) of the k-step v over the tile's rows, and for M also its A
+// operand (A[m][k] = Z[k][m]).  Per-wave partials are added in wave order.
+template <int RP>
+__device__ __forceinline__ void eig_gq_tm(const double* G, int sp, int s, EigShared<RP>& sh) {
+    const int ldg = sp + 1;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int col = lane & 15, kq = lane >> 4, cc = col < RP ? col : RP - 1;
+    const int nt = sp >> 4;
+    v4d tacc = {0.0, 0.0, 0.0, 0.0}, macc = {0.0, 0.0, 0.0, 0.0};
+    for (int t = w; t < nt; t += 4) {
+        const double* ga = G + (int64_t)(16 * t + col) * ldg + kq;
+        v4d acc = {0.0, 0.0, 0.0, 0.0};
+        for (int j = 0; j < sp; j += 16) {  // sp is a multiple of 16
+            double av[4], bv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                av[u] = ga[j + 4 * u];
+                bv[u] = sh.qs[(j + 4 * u + kq) * RP + cc];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], col < RP ? bv[u] : 0.0, acc,
+                                                           0, 0, 0);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = 16 * t + 4 * v + kq;
+            if (row < s && col < RP) sh.zs[row * RP + col] = acc[v];
+            // Q^T as the A operand of this k-step: A[p][k] = Q[16t + 4v + k][p]
+            const double qa = col < RP ? sh.qs[row * RP + cc] : 0.0;
+            tacc = __builtin_amdgcn_mfma_f64_16x16x4f64(qa, acc[v], tacc, 0, 0, 0);
+            macc = __builtin_amdgcn_mfma_f64_16x16x4f64(acc[v], acc[v], macc, 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        sh.part[w][(4 * v + kq) * 16 + col] = tacc[v];
+        sh.part2[w][(4 * v + kq) * 16 + col] = macc[v];
+    }
+    __syncthreads();
+    if (threadIdx.x < RP * RP) {
+        const int p = threadIdx.x / RP, t = threadIdx.x % RP;
+        const int e = p * 16 + t;
+        sh.tm[threadIdx.x] = ((sh.part[0][e] + sh.part[1][e]) + sh.part[2][e]) + sh.part[3][e];
+        sh.mm[threadIdx.x] = ((sh.part2[0][e] + sh.part2[1][e]) + sh.part2[2][e]) + sh.part2[3][e];
+    }
+    __syncthreads();
+}
+
 // kLdsGram: the Gram sits in dynamic LDS (else in `gram`); a compile-time
 // choice so that its accesses compile to LDS (or global) instructions rather
 // than generic ones.
@@ -1129,10 +1182,9 @@ __global__ __launch_bounds__(kThreads) void k_eig(Prob P, const double* __restri
                 for (int p = 0; p < RP; ++p) sh.qs[a * RP + p] = q[p];
             }
             __syncthreads();
-            eig_gq<RP>(G, sp, s, sh);
+            eig_gq_tm<RP>(G, sp, s, sh);  // Z = G Q, T = Q^T Z, M = Z^T Z
 #pragma unroll
             for (int p = 0; p < RP; ++p) z[p] = act ? sh.zs[a * RP + p] : 0.0;
-            eig_tm<RP>(sp, true, sh);  // T = Q^T Z, M = Z^T Z
             double rn = 0.0, tn = 0.0;
             {
                 double Tr[RP][RP];
