@@ -5,10 +5,14 @@ kernels.  PyTorch supplies device memory and the stream.  The functions
 mirror the C ABI in include/rtcur.h:
 
     create(device=0, stream=None, variant="F", dtype=torch.float64) -> Handle
+        (dtype torch.bfloat16: bfloat16 blocks, then the FP32 refinement sweep)
     solve(handle, X, ranks, I_sizes=None, J_sizes=None, ...) -> Info
+    solve_batch(handles, Xs, ranks, I_sizes=None, ...) -> (infos, Ls)
     reconstruct(handle, out=None, dtype=None) -> torch.Tensor
+    outliers(handle, X, zeta=None, with_L=False) -> S or (S, L)
     destroy(handle)
     get_indices / get_history / get_block / get_tucker / sample
+    set_profiling / get_profile
 
 The library must have been built (``python -m paper_2108_10448_amd.build``);
 importing the binding never falls back to anything else.
