@@ -1422,8 +1422,6 @@ __device__ void core_slice(const Prob& P, const T* __restrict__ R, const double*
     for (int l = 1; l < n - 1; ++l) rows *= P.s[l];
     const int K = P.s[n - 1];
     const int rq = P.r[n - 1];
-    for (int e = tid; e < K * RP; e += kThreads) ws[e] = W[P.woff[n - 1] + e];
-    if (sf) return;
     // this item's rows [rb, re) of the slice (the whole slice unless the
     // middle mode is split into P.cparts parts; the parts' partial cores
     // are added by core_finish)
@@ -1432,6 +1430,32 @@ __device__ void core_slice(const Prob& P, const T* __restrict__ R, const double*
     const int rb = part * P.crows, re = min(rows, rb + P.crows);
     const T* Ra = R + (int64_t)a * rows * K;
     const int RC = max(1, kSliceBytes / (int)sizeof(T) / K);
+    // every load of the first pass (its R rows and W_{n-1}) and of the next
+    // mode's W rows is issued before the first store
+    constexpr int NV = kSliceBytes / (int)sizeof(T) / kThreads;  // R entries per thread
+    constexpr int NW = kMaxS * RP / kThreads;                   // W entries per thread
+    const int nr0 = min(RC, re - rb), ne0 = nr0 * K;
+    T v0[NV];
+#pragma unroll
+    for (int u = 0; u < NV; ++u) {
+        const int e = tid + u * kThreads;
+        v0[u] = Ra[(int64_t)rb * K + (e < ne0 ? e : 0)];
+    }
+    double w0[NW], w1[NW];
+    const int l1 = n - 2;  // the next mode contracted (none when n == 2)
+#pragma unroll
+    for (int u = 0; u < NW; ++u) {
+        const int e = tid + u * kThreads;
+        w0[u] = W[P.woff[n - 1] + (e < K * RP ? e : 0)];
+        w1[u] = l1 >= 1 ? W[P.woff[l1 >= 1 ? l1 : 0] + (e < P.s[l1 >= 1 ? l1 : 0] * RP ? e : 0)]
+                        : 0.0;
+    }
+    if (sf) return;
+#pragma unroll
+    for (int u = 0; u < NW; ++u) {
+        const int e = tid + u * kThreads;
+        if (e < K * RP) ws[e] = w0[u];
+    }
     if (P.cparts > 1) {
         for (int o = tid; o < rq * rows; o += kThreads) {
             const int row = o % rows;
@@ -1442,17 +1466,25 @@ __device__ void core_slice(const Prob& P, const T* __restrict__ R, const double*
         const int nr = min(RC, re - r0);
         const int ne = nr * K;
         __syncthreads();
-        for (int e0 = tid; e0 < ne; e0 += 8 * kThreads) {
-            T v[8];
+        if (r0 == rb) {
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int e = e0 + u * kThreads;
-                v[u] = Ra[(int64_t)r0 * K + (e < ne ? e : e0)];
+            for (int u = 0; u < NV; ++u) {
+                const int e = tid + u * kThreads;
+                if (e < ne) rs[e] = v0[u];
             }
+        } else {
+            for (int e0 = tid; e0 < ne; e0 += 8 * kThreads) {
+                T v[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int e = e0 + u * kThreads;
-                if (e < ne) rs[e] = v[u];
+                for (int u = 0; u < 8; ++u) {
+                    const int e = e0 + u * kThreads;
+                    v[u] = Ra[(int64_t)r0 * K + (e < ne ? e : e0)];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int e = e0 + u * kThreads;
+                    if (e < ne) rs[e] = v[u];
+                }
             }
         }
         __syncthreads();
@@ -1472,7 +1504,15 @@ __device__ void core_slice(const Prob& P, const T* __restrict__ R, const double*
         rest /= Kl;
         const int M = lead * rest;
         __syncthreads();
-        for (int e = tid; e < Kl * RP; e += kThreads) ws[e] = W[P.woff[l] + e];
+        if (l == l1) {
+#pragma unroll
+            for (int u = 0; u < NW; ++u) {
+                const int e = tid + u * kThreads;
+                if (e < Kl * RP) ws[e] = w1[u];
+            }
+        } else {
+            for (int e = tid; e < Kl * RP; e += kThreads) ws[e] = W[P.woff[l] + e];
+        }
         __syncthreads();
         for (int o = tid; o < rl * M; o += kThreads) {
             const int p = o / M, row = o % M;
@@ -1491,8 +1531,8 @@ __device__ void core_slice(const Prob& P, const T* __restrict__ R, const double*
 }
 
 // G = sum_a W_0[a]^T T[a] (the last contraction of the core, the parts of
-// each slice added in order with it), one workgroup, T staged through LDS
-// (tb, wb: kCoreLds / 2 doubles each).
+// each slice added in order with it), one workgroup, T and W_0 rows staged
+// through the caller's LDS buffer of `cap` doubles.
 template <int RP>
 __device__ void core_finish(const Prob& P, const double* __restrict__ W,
                             const double* __restrict__ Tbuf, double* __restrict__ Gd,
