@@ -145,6 +145,58 @@ def test_solve_batch_uneven_instances():
         rt.destroy(h)
 
 
+@pytest.fixture(scope="module")
+def video_full():
+    # the video-shaped workload at its full size (240 x 320 x 3 x 400, float32
+    # storage, upsilon = 2), the oracle run for three iterations
+    inst = synth.video_like()
+    I, _ = synth.sample_sizes(inst.dims, inst.ranks, 2.0)
+    res = oracle_rtcur(inst.X, inst.ranks, I, None, None, 0.7, 0.0, 3, 0, "F")
+    return inst, I, res
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_video_full_size(video_full, dtype):
+    inst, I, res = video_full
+    h, info, _ = run_gpu(inst.X, inst.ranks, I, tol=0.0, max_iter=3, seed=0, check=False,
+                         dtype=torch.float64 if dtype == "f64" else torch.float32)
+    assert info.eig_unconverged == 0
+    compare(res, h, info, fp64=dtype == "f64", label=f"video 240x320x3x400 {dtype}")
+
+
+def test_batch_recipe_instances():
+    # the first six instances of the 64-tensor batch recipe (shapes up to
+    # 256^3, ranks 2..8): solved together over three handles, each equals
+    # its single solve bit for bit and converges
+    import paper_2108_10448_amd as rt
+    specs = synth.batch_specs()[:6]
+    Xs, ranks, I, seeds = [], [], [], []
+    for sp in specs:
+        inst = synth.tucker_plus_sparse(sp["dims"], sp["ranks"], sp["alpha"], seed=sp["seed"],
+                                        storage=np.float32, keep_parts=False)
+        Xs.append(torch.from_numpy(inst.X).to("cuda:0"))
+        ranks.append(sp["ranks"])
+        I.append(synth.sample_sizes(sp["dims"], sp["ranks"], 3.0)[0])
+        seeds.append(sp["seed"])
+    streams = [torch.cuda.Stream() for _ in range(3)]
+    hs = [rt.create(0, stream=st, dtype=torch.float32) for st in streams]
+    infos, Ls = rt.solve_batch(hs, Xs, ranks, I, seeds=seeds, with_L=True, check=False)
+    torch.cuda.synchronize()
+    for j in range(len(Xs)):
+        print(f"[batch] {specs[j]['dims']} r={specs[j]['ranks']} iters {infos[j].iters} "
+              f"err {infos[j].err:.3e}", flush=True)
+        assert infos[j].status == rt.OK and infos[j].converged
+        h1 = rt.create(0, dtype=torch.float32)
+        info1 = rt.solve(h1, Xs[j], ranks[j], I[j], seed=seeds[j], check=False)
+        L1 = rt.reconstruct(h1)
+        torch.cuda.synchronize()
+        assert info1.iters == infos[j].iters and info1.err == infos[j].err
+        assert torch.equal(L1, Ls[j])
+        rt.destroy(h1)
+    for h in hs:
+        rt.destroy(h)
+
+
 def test_two_modes_fp64():
     inst = synth.tucker_plus_sparse((300, 257), (4, 4), alpha=0.1, seed=8)
     I = (40, 37)
