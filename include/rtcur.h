@@ -133,13 +133,17 @@ int rtcur_outliers(rtcur_t h, const void* X, int x_dtype, double zeta, void* S_o
                    void* L_out, int out_dtype);
 
 /* Many independent instances (a batch of tensors of uneven shapes and
- * ranks), solved concurrently: instance j runs on handle hs[j % nh], each
- * handle driven by its own host thread, so handles bound to distinct streams
- * overlap their kernels on the device; the instances of one handle run in
- * increasing j.  Each instance is Algorithm 1 exactly as rtcur_solve runs it
- * (same results bit for bit).
+ * ranks), solved concurrently: each of the nh handles is driven by its own
+ * host thread, so handles bound to distinct streams overlap their kernels on
+ * the device.  Schedule (fixed before any solve starts): the instances are
+ * taken in decreasing number of entries (ties: lower j first), each given to
+ * the handle with the fewest entries assigned so far (ties: lower handle
+ * index); a handle solves its instances in the order they were given to it.
+ * Each instance is Algorithm 1 exactly as rtcur_solve runs it (same results
+ * bit for bit, whichever handle runs it).
  *   hs, nh     nh >= 1 distinct handles (their variant and compute dtype
- *              apply); after the call each holds its last instance's state
+ *              apply); after the call each holds the state of the last
+ *              instance the schedule gave it
  *   count      number of instances (>= 0)
  *   X[j]       device tensor of instance j, x_dtype, C-contiguous, read-only
  *   n[j]       its number of modes; dims, ranks, I_sizes (and J_sizes when

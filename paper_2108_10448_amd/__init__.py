@@ -249,14 +249,30 @@ def solve(h: Handle, X, ranks: Sequence[int], I_sizes: Optional[Sequence[int]] =
                 info.eig_steps, info.eig_unconverged)
 
 
+def batch_schedule(shapes, nh: int):
+    """The instance lists rtcur_solve_batch gives to each of nh handles:
+    instances in decreasing number of entries (ties: lower index first), each
+    to the handle with the fewest entries so far (ties: lower handle)."""
+    ent = [float(math.prod(int(d) for d in sh)) for sh in shapes]
+    order = sorted(range(len(shapes)), key=lambda j: -ent[j])
+    nt = min(nh, len(shapes))
+    lists, load = [[] for _ in range(nt)], [0.0] * nt
+    for j in order:
+        t = min(range(nt), key=lambda u: (load[u], u))
+        lists[t].append(j)
+        load[t] += ent[j]
+    return lists
+
+
 def solve_batch(handles: Sequence[Handle], Xs, ranks, I_sizes=None, J_sizes=None, *,
                 upsilon: float = 3.0, zeta0=None, gamma: float = 0.7, tol: float = 1e-5,
                 max_iter: int = 100, seeds=None, with_L: bool = False, L_dtype=None,
                 check: bool = True):
-    """rtcur_solve_batch: instance j (device tensor Xs[j], ranks[j], I_sizes[j]
-    (default upsilon sizes), J_sizes[j] or chidori) on handles[j % len(handles)],
-    one host thread per handle.  All Xs share one dtype.  Returns (infos, Ls)
-    with Ls the full reconstructions when with_L, else None."""
+    """rtcur_solve_batch: instance j is device tensor Xs[j] with ranks[j],
+    I_sizes[j] (default upsilon sizes) and J_sizes[j] (or chidori); one host
+    thread per handle, instances spread over the handles by batch_schedule.
+    All Xs share one dtype.  Returns (infos, Ls) with Ls the full
+    reconstructions when with_L, else None."""
     torch = _torch()
     count = len(Xs)
     if count == 0:
@@ -305,9 +321,9 @@ def solve_batch(handles: Sequence[Handle], Xs, ranks, I_sizes=None, J_sizes=None
                                  F64 if dt == torch.float64 else F32, nn, dims, rk, Is, Js,
                                  z0, float(gamma), float(tol), int(max_iter), sd, lo,
                                  F64 if odt == torch.float64 else F32, infos, st)
-    for j, X in enumerate(Xs):
-        h = handles[j % len(handles)]
-        h.dims, h.ranks = list(X.shape), list(ranks[j])
+    for t, js in enumerate(batch_schedule([X.shape for X in Xs], len(handles))):
+        if js:
+            handles[t].dims, handles[t].ranks = list(Xs[js[-1]].shape), list(ranks[js[-1]])
     if rc < 0 and check:
         raise RTCURError(rc, f"rtcur_solve_batch: {strerror(rc)}")
     out = [Info(st[j], infos[j].iters, bool(infos[j].converged), infos[j].err,

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <algorithm>
 #include <thread>
 #include <vector>
 
@@ -168,9 +169,31 @@ int rtcur_solve_batch(rtcur_t* hs, int32_t nh, int32_t count, const void* const*
             if (hs[u] == hs[t]) return RTCUR_E_INVAL;  // one thread per handle
     }
     const int32_t nt = count < nh ? count : nh;
-    // worker t solves instances t, t + nh, ... on handle t, in order
+    // static longest-first schedule: instances in decreasing number of
+    // entries (ties by index), each given to the handle with the fewest
+    // entries assigned so far (ties: lowest handle); every handle then solves
+    // its list in that order
+    std::vector<int32_t> order(count);
+    for (int32_t j = 0; j < count; ++j) order[j] = j;
+    auto entries = [&](int32_t j) {
+        double v = 1.0;
+        for (int32_t q = 0; q < n[j] && q < rtcur::kMaxModes; ++q)
+            v *= (double)dims[(int64_t)j * rtcur::kMaxModes + q];
+        return v;
+    };
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t x, int32_t y) { return entries(x) > entries(y); });
+    std::vector<std::vector<int32_t>> list(nt > 0 ? nt : 0);
+    std::vector<double> load(nt > 0 ? nt : 0, 0.0);
+    for (int32_t j : order) {
+        int32_t t = 0;
+        for (int32_t u = 1; u < nt; ++u)
+            if (load[u] < load[t]) t = u;
+        list[t].push_back(j);
+        load[t] += entries(j);
+    }
     auto work = [&](int32_t t) {
-        for (int32_t j = t; j < count; j += nh) {
+        for (int32_t j : list[t]) {
             const int64_t* Js = J_sizes ? J_sizes + (int64_t)j * rtcur::kMaxModes : nullptr;
             rtcur_info inf;
             std::memset(&inf, 0, sizeof(inf));

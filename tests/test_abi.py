@@ -104,3 +104,18 @@ def test_library_sampler_matches_oracle(L, seed):
             for i in range(len(dims)):
                 assert np.array_equal(rt.sample(seed, t, dims, I, J, i, 0), o.I[i])
                 assert np.array_equal(rt.sample(seed, t, dims, I, J, i, 1), o.J_cols[i])
+
+
+def test_batch_schedule_longest_first():
+    # the schedule rtcur_solve_batch documents, worked by hand: entries
+    # 8, 27, 8, 64, 1 over two handles -> 64 to handle 0, then 27, 8, 8, 1
+    # all to handle 1 (its load stays below 64)
+    import paper_2108_10448_amd as rt
+    shapes = [(2, 2, 2), (3, 3, 3), (2, 4), (4, 4, 4), (1, 1)]
+    assert rt.batch_schedule(shapes, 2) == [[3], [1, 0, 2, 4]]
+    assert rt.batch_schedule(shapes, 8) == [[3], [1], [0], [2], [4]]
+    assert rt.batch_schedule([], 3) == []
+    # entries 35, 15, 45, 45, 5, 20, 30 over three handles
+    lists = rt.batch_schedule([(d, 5) for d in (7, 3, 9, 9, 1, 4, 6)], 3)
+    assert sorted(j for js in lists for j in js) == list(range(7))
+    assert lists == [[2, 5], [3, 1, 4], [0, 6]]

@@ -141,6 +141,11 @@ def test_solve_batch_uneven_instances():
         torch.cuda.synchronize()
         assert torch.equal(L1, Ls[j])
         rt.destroy(h1)
+    # each handle keeps the state of the last instance its schedule gave it
+    for t, js in enumerate(rt.batch_schedule([X.shape for X in Xs], len(hs))):
+        Lt = rt.reconstruct(hs[t])
+        torch.cuda.synchronize()
+        assert js and torch.equal(Lt, Ls[js[-1]])
     for h in hs:
         rt.destroy(h)
 
