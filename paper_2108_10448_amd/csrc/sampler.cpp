@@ -68,9 +68,10 @@ std::vector<int64_t> floyd(SplitMix& g, int64_t m, int64_t N) {
 void draw_sample(uint64_t seed, int64_t t, const Shape& sh, bool chidori,
                  SampleHost& out) {
     const int n = sh.n;
-    out.I.assign(n, {});
-    out.Jcols.assign(n, {});
-    out.Jtup.assign(n, {});
+    // resized, not cleared: a reused sample keeps its vectors' storage
+    out.I.resize(n);
+    out.Jcols.resize(n);
+    out.Jtup.resize(n);
     for (int i = 0; i < n; ++i) {
         SplitMix g = stream_for(seed, t, i, 0);
         out.I[i] = floyd(g, sh.s[i], sh.d[i]);
@@ -88,20 +89,25 @@ void draw_sample(uint64_t seed, int64_t t, const Shape& sh, bool chidori,
             for (int q = 0; q < nr; ++q) m *= sh.s[rest[q]];
             cols.resize((size_t)m);
             tup.resize((size_t)m * nr);
+            // column c <-> positions (pos_0, .., pos_{nr-1}) in the I of the
+            // remaining modes, last fastest: an odometer over the positions;
+            // the unfolding column is sum_q I[pos_q] * prod_{q' > q} d
+            int64_t stride[kMaxModes];
+            stride[nr - 1] = 1;
+            for (int q = nr - 2; q >= 0; --q) stride[q] = stride[q + 1] * sh.d[rest[q + 1]];
+            int64_t pos[kMaxModes] = {0, 0, 0, 0};
             for (int64_t c = 0; c < m; ++c) {
-                int64_t rem = c, col = 0;
-                int32_t pos[kMaxModes];
-                for (int q = nr - 1; q >= 0; --q) {
-                    int64_t sq = sh.s[rest[q]];
-                    pos[q] = (int32_t)(rem % sq);
-                    rem /= sq;
-                }
+                int64_t col = 0;
                 for (int q = 0; q < nr; ++q) {
-                    int64_t v = out.I[rest[q]][pos[q]];
+                    const int64_t v = out.I[rest[q]][pos[q]];
                     tup[(size_t)c * nr + q] = (int32_t)v;
-                    col = col * sh.d[rest[q]] + v;
+                    col += v * stride[q];
                 }
                 cols[(size_t)c] = col;
+                for (int q = nr - 1; q >= 0; --q) {
+                    if (++pos[q] < sh.s[rest[q]]) break;
+                    pos[q] = 0;
+                }
             }
         } else {
             int64_t P = 1;

@@ -82,7 +82,12 @@ struct Impl {
     char* d_stage = nullptr;        // RTCUR-R: index data of queued samples
     char* h_stage = nullptr;        //   (device slots and their pinned source)
     size_t stage_bytes = 0;
+    char* h_idx = nullptr;          // pinned source of the index upload
+    size_t h_idx_bytes = 0;
+    hipEvent_t idx_ev = nullptr;    // recorded after that upload
+    bool idx_pending = false;       //   (the buffer is rewritten only after it)
     int max_dyn_lds[3] = {0, 0, 0};  // k_eig<4|8|16, true>: room for the Gram
+    std::vector<int64_t> plan_key;  // sizes the current layout was planned for
 
     // layout of the current solve
     Prob P{};
@@ -125,6 +130,9 @@ void release(rtcur_s* h) {
     if (im->st_host) (void)hipHostFree(im->st_host);
     if (im->d_stage) (void)hipFree(im->d_stage);
     if (im->h_stage) (void)hipHostFree(im->h_stage);
+    if (im->idx_ev) (void)hipEventSynchronize(im->idx_ev);
+    if (im->h_idx) (void)hipHostFree(im->h_idx);
+    if (im->idx_ev) (void)hipEventDestroy(im->idx_ev);
     for (hipEvent_t e : im->events) (void)hipEventDestroy(e);
     delete im;
     h->impl = nullptr;
@@ -134,11 +142,12 @@ void release(rtcur_s* h) {
 
 // Host-side index data for one sample, packed for a single upload.
 struct IdxPack {
-    std::vector<char> bytes;
+    size_t bytes = 0;
     size_t I_off[kMaxModes], rowidx_off, colx_off[kMaxBlocks], cidx_off[kMaxBlocks];
 };
 
-static void pack_indices(const Shape& sh, const SampleHost& smp, IdxPack& pk) {
+// Offsets of the index regions for this shape (they depend on sizes only).
+static void index_layout(const Shape& sh, IdxPack& pk) {
     const int n = sh.n;
     size_t off = 0;
     auto reserve = [&](size_t bytes) {
@@ -156,8 +165,14 @@ static void pack_indices(const Shape& sh, const SampleHost& smp, IdxPack& pk) {
         pk.colx_off[b] = reserve(sizeof(int64_t) * ncol[b]);
         pk.cidx_off[b] = reserve(sizeof(int32_t) * ncol[b] * (n - 1));
     }
-    pk.bytes.assign(off, 0);
-    char* base = pk.bytes.data();
+    pk.bytes = off;
+}
+
+// The sample's index data into base (pk.bytes bytes, laid out by
+// index_layout; the alignment gaps are left as they are).
+static void pack_indices(const Shape& sh, const SampleHost& smp, const IdxPack& pk,
+                         char* base) {
+    const int n = sh.n;
     for (int i = 0; i < n; ++i) {
         int32_t* p = reinterpret_cast<int32_t*>(base + pk.I_off[i]);
         for (int64_t a = 0; a < sh.s[i]; ++a) p[a] = (int32_t)smp.I[i][a];
@@ -165,33 +180,39 @@ static void pack_indices(const Shape& sh, const SampleHost& smp, IdxPack& pk) {
     int64_t xstride[kMaxModes];
     xstride[n - 1] = 1;
     for (int j = n - 2; j >= 0; --j) xstride[j] = xstride[j + 1] * sh.d[j + 1];
-    // R block: columns = product of I_1..I_{n-1}, last fastest
+    // R block: columns = product of I_1..I_{n-1}, last fastest (an odometer
+    // over the positions in I_1..I_{n-1})
     {
+        int64_t nc = 1;
+        for (int j = 1; j < n; ++j) nc *= sh.s[j];
         int64_t* cx = reinterpret_cast<int64_t*>(base + pk.colx_off[0]);
         int32_t* ci = reinterpret_cast<int32_t*>(base + pk.cidx_off[0]);
-        for (int64_t c = 0; c < ncol[0]; ++c) {
-            int64_t rem = c, off2 = 0;
-            for (int j = n - 1; j >= 1; --j) {
-                const int64_t a = rem % sh.s[j];
-                rem /= sh.s[j];
-                const int64_t v = smp.I[j][a];
+        int64_t pos[kMaxModes] = {0, 0, 0, 0};
+        for (int64_t c = 0; c < nc; ++c) {
+            int64_t off2 = 0;
+            for (int j = 1; j < n; ++j) {
+                const int64_t v = smp.I[j][pos[j]];
                 off2 += v * xstride[j];
-                ci[(int64_t)(j - 1) * ncol[0] + c] = (int32_t)v;
+                ci[(int64_t)(j - 1) * nc + c] = (int32_t)v;
             }
             cx[c] = off2;
+            for (int j = n - 1; j >= 1; --j) {
+                if (++pos[j] < sh.s[j]) break;
+                pos[j] = 0;
+            }
         }
     }
     for (int i = 0; i < n; ++i) {
         int64_t* cx = reinterpret_cast<int64_t*>(base + pk.colx_off[1 + i]);
         int32_t* ci = reinterpret_cast<int32_t*>(base + pk.cidx_off[1 + i]);
         const int64_t m = sh.m[i];
-        const std::vector<int32_t>& tup = smp.Jtup[i];
+        const int32_t* tup = smp.Jtup[i].data();
         for (int64_t c = 0; c < m; ++c) {
             int64_t off2 = 0;
             int q = 0;
             for (int j = 0; j < n; ++j) {
                 if (j == i) continue;
-                const int64_t v = tup[(size_t)c * (n - 1) + q];
+                const int64_t v = tup[c * (n - 1) + q];
                 off2 += v * xstride[j];
                 ci[(int64_t)q * m + c] = (int32_t)v;
                 ++q;
@@ -578,14 +599,35 @@ struct Runner {
 
     int upload_sample(const SampleHost& smp, const Shape& sh) {
         IdxPack pk;
-        pack_indices(sh, smp, pk);
-        if (pk.bytes.size() > im.idx_bytes) {
+        index_layout(sh, pk);
+        if (pk.bytes > im.idx_bytes) {
             h->last_error = "internal: index region too small";
             return RTCUR_E_STATE;
         }
-        HIPCHK(hipMemcpyAsync(im.d_idx, pk.bytes.data(), pk.bytes.size(),
-                              hipMemcpyHostToDevice, s));
-        HIPCHK(hipStreamSynchronize(s));
+        // packed into pinned memory and copied in stream order; the host
+        // rewrites that memory only once the previous copy has finished
+        if (im.idx_pending) {
+            HIPCHK(hipEventSynchronize(im.idx_ev));
+            im.idx_pending = false;
+        }
+        if (pk.bytes > im.h_idx_bytes) {
+            if (im.h_idx) HIPCHK(hipHostFree(im.h_idx));
+            im.h_idx = nullptr;
+            im.h_idx_bytes = 0;
+            if (hipHostMalloc(reinterpret_cast<void**>(&im.h_idx), pk.bytes,
+                              hipHostMallocDefault) != hipSuccess) {
+                (void)hipGetLastError();
+                h->last_error = "pinned index buffer allocation failed";
+                return RTCUR_E_NOMEM;
+            }
+            im.h_idx_bytes = pk.bytes;
+        }
+        if (!im.idx_ev)
+            HIPCHK(hipEventCreateWithFlags(&im.idx_ev, hipEventDisableTiming));
+        pack_indices(sh, smp, pk, im.h_idx);
+        HIPCHK(hipMemcpyAsync(im.d_idx, im.h_idx, pk.bytes, hipMemcpyHostToDevice, s));
+        HIPCHK(hipEventRecord(im.idx_ev, s));
+        im.idx_pending = true;
         Prob& P = im.P;
         for (int i = 0; i < sh.n; ++i)
             P.I[i] = reinterpret_cast<const int32_t*>(im.d_idx + pk.I_off[i]);
@@ -603,8 +645,8 @@ struct Runner {
     // taken into the index region by k_take_sample unless the loop stopped.
     int stage_sample(const SampleHost& smp, const Shape& sh, int slot) {
         IdxPack pk;
-        pack_indices(sh, smp, pk);
-        if (pk.bytes.size() != im.idx_bytes || im.idx_bytes % 16) {
+        index_layout(sh, pk);
+        if (pk.bytes != im.idx_bytes || im.idx_bytes % 16) {
             h->last_error = "internal: index layout changed";
             return RTCUR_E_STATE;
         }
@@ -625,7 +667,7 @@ struct Runner {
         }
         char* hs = im.h_stage + (size_t)slot * im.idx_bytes;
         char* ds = im.d_stage + (size_t)slot * im.idx_bytes;
-        std::memcpy(hs, pk.bytes.data(), im.idx_bytes);
+        pack_indices(sh, smp, pk, hs);
         HIPCHK(hipMemcpyAsync(ds, hs, im.idx_bytes, hipMemcpyHostToDevice, s));
         hipLaunchKernelGGL(k_take_sample, dim3(64), dim3(kThreads), 0, s,
                            reinterpret_cast<uint4*>(im.d_idx), reinterpret_cast<const uint4*>(ds),
@@ -854,18 +896,22 @@ struct Runner {
 template <typename T>
 static int prepare(rtcur_s* h, Impl& im, const Shape& sh, int max_iter) {
     IdxPack pk;
-    // index bytes depend only on sizes: size them with a zero sample
-    SampleHost zero;
-    zero.I.assign(sh.n, {});
-    zero.Jtup.assign(sh.n, {});
+    index_layout(sh, pk);
+    // the layout and work lists depend on the sizes only: a solve of the
+    // same sizes as the previous one on this handle reuses them
+    std::vector<int64_t> key = {sh.n, sh.chidori ? 1 : 0, (int64_t)sizeof(T), max_iter,
+                                (int64_t)pk.bytes};
     for (int i = 0; i < sh.n; ++i) {
-        zero.I[i].assign(sh.s[i], 0);
-        zero.Jtup[i].assign((size_t)sh.m[i] * (sh.n - 1), 0);
+        key.push_back(sh.d[i]);
+        key.push_back(sh.r[i]);
+        key.push_back(sh.s[i]);
+        key.push_back(sh.m[i]);
     }
-    pack_indices(sh, zero, pk);
+    if (im.arena && key == im.plan_key) return 0;
+    im.plan_key.clear();
     Arena ar;
     Regions rg;
-    plan(im, sh, sizeof(T), pk.bytes.size(), max_iter, ar, rg);
+    plan(im, sh, sizeof(T), pk.bytes, max_iter, ar, rg);
     if (ar.total > im.arena_bytes) {
         if (im.arena) HIPCHK(hipFree(im.arena));
         im.arena = nullptr;
@@ -912,7 +958,7 @@ static int prepare(rtcur_s* h, Impl& im, const Shape& sh, int max_iter) {
     t += sizeof(int2) * im.z_tiles.size();
     im.d_h_tiles = reinterpret_cast<int2*>(t);
     im.d_idx = a + rg.idx;
-    im.idx_bytes = pk.bytes.size();
+    im.idx_bytes = pk.bytes;
     // work lists (one upload)
     std::vector<char> tb(sizeof(int4) * (im.ht_tiles.size() + im.gram_items.size() +
                                          im.bfac_items.size()) +
@@ -929,6 +975,7 @@ static int prepare(rtcur_s* h, Impl& im, const Shape& sh, int max_iter) {
     put(im.h_tiles.data(), sizeof(int2) * im.h_tiles.size());
     HIPCHK(hipMemcpyAsync(a + rg.tiles, tb.data(), tb.size(), hipMemcpyHostToDevice, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
+    im.plan_key = std::move(key);
     return 0;
 }
 
