@@ -238,6 +238,15 @@ int rtcur_get_indices(rtcur_t h, int32_t mode, int32_t which, int64_t* out, int6
     if (!h->have_result) return fail(h, RTCUR_E_STATE, "no successful solve");
     if (mode < 0 || mode >= h->shape.n || (which != 0 && which != 1))
         return fail(h, RTCUR_E_INVAL, "mode or which out of range");
+    // chidori column lists are formed from the I_i on first request
+    if (which == 1 && h->shape.chidori &&
+        (int64_t)h->sample.Jcols[mode].size() != h->shape.m[mode]) {
+        try {
+            rtcur::chidori_columns(h->shape, h->sample);
+        } catch (...) {
+            return fail(h, RTCUR_E_NOMEM, "column list allocation failed");
+        }
+    }
     const std::vector<int64_t>& v = which == 0 ? h->sample.I[mode] : h->sample.Jcols[mode];
     if (len) *len = (int64_t)v.size();
     if (out) {

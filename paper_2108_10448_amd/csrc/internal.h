@@ -36,8 +36,11 @@ struct SampleHost {
     std::vector<std::vector<int32_t>> Jtup;   // per mode: [m_i][n-1] tuples
 };
 
+// I_i always; under fiber sampling also J_i; under chidori J_i only when
+// with_cols (else left empty: chidori_columns forms them from the I_i).
 void draw_sample(uint64_t seed, int64_t t, const Shape& sh, bool chidori,
-                 SampleHost& out);
+                 SampleHost& out, bool with_cols = true);
+void chidori_columns(const Shape& sh, SampleHost& out);
 
 // ------------------------------------------------------- device descriptors
 

@@ -174,6 +174,41 @@ __global__ __launch_bounds__(kThreads) void k_take_sample(uint4* __restrict__ ds
         dst[e] = src[e];
 }
 
+// Column index data of the blocks whose columns are the Cartesian product
+// of the other modes' sampled indices (bit b of prod_mask: block b; the R
+// block always, the C_i under chidori sampling): column c of block b takes
+// the other modes in increasing order, the last fastest, and gets
+// cidx[q][c] = I_{j_q}[pos_q] and colx[c] = sum_q I_{j_q}[pos_q] * xstride_{j_q}.
+// Block b = blockIdx.y.  With st, returns at once when the loop has stopped
+// (the index data then stays that of the returned iterate).
+__global__ __launch_bounds__(kThreads) void k_expand_cols(Prob P, int prod_mask,
+                                                          const DevState* st) {
+    if (st && stopped(st)) return;
+    const int b = blockIdx.y;
+    if (!((prod_mask >> b) & 1)) return;
+    const BlockDev& bd = P.blk[b];
+    int rest[kMaxModes - 1];
+    int nr = 0;
+    for (int j = 0; j < P.n; ++j)
+        if (j != bd.mode) rest[nr++] = j;
+    const int64_t nc = bd.ncols;
+    int64_t* colx = const_cast<int64_t*>(bd.colx);
+    int32_t* cidx = const_cast<int32_t*>(bd.cidx);
+    for (int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x; c < nc;
+         c += (int64_t)gridDim.x * kThreads) {
+        int64_t rem = c, off = 0;
+        for (int q = nr - 1; q >= 0; --q) {
+            const int j = rest[q];
+            const int64_t pos = rem % P.s[j];
+            rem /= P.s[j];
+            const int32_t v = P.I[j][pos];
+            off += (int64_t)v * P.xstride[j];
+            cidx[(int64_t)q * nc + c] = v;
+        }
+        colx[c] = off;
+    }
+}
+
 // bfloat16 block entries to float (exact).
 __global__ __launch_bounds__(kThreads) void k_widen(const __hip_bfloat16* __restrict__ in,
                                                     int64_t N, float* __restrict__ out) {

@@ -65,8 +65,47 @@ std::vector<int64_t> floyd(SplitMix& g, int64_t m, int64_t N) {
 
 }  // namespace
 
+void chidori_columns(const Shape& sh, SampleHost& out) {
+    const int n = sh.n;
+    out.Jcols.resize(n);
+    out.Jtup.resize(n);
+    for (int i = 0; i < n; ++i) {
+        // remaining modes, increasing; last fastest
+        int rest[kMaxModes];
+        int nr = 0;
+        for (int j = 0; j < n; ++j)
+            if (j != i) rest[nr++] = j;
+        std::vector<int64_t>& cols = out.Jcols[i];
+        std::vector<int32_t>& tup = out.Jtup[i];  // [ncols][n-1]
+        int64_t m = 1;
+        for (int q = 0; q < nr; ++q) m *= sh.s[rest[q]];
+        cols.resize((size_t)m);
+        tup.resize((size_t)m * nr);
+        // column c <-> positions (pos_0, .., pos_{nr-1}) in the I of the
+        // remaining modes, last fastest: an odometer over the positions; the
+        // unfolding column is sum_q I[pos_q] * prod_{q' > q} d
+        int64_t stride[kMaxModes];
+        stride[nr - 1] = 1;
+        for (int q = nr - 2; q >= 0; --q) stride[q] = stride[q + 1] * sh.d[rest[q + 1]];
+        int64_t pos[kMaxModes] = {0, 0, 0, 0};
+        for (int64_t c = 0; c < m; ++c) {
+            int64_t col = 0;
+            for (int q = 0; q < nr; ++q) {
+                const int64_t v = out.I[rest[q]][pos[q]];
+                tup[(size_t)c * nr + q] = (int32_t)v;
+                col += v * stride[q];
+            }
+            cols[(size_t)c] = col;
+            for (int q = nr - 1; q >= 0; --q) {
+                if (++pos[q] < sh.s[rest[q]]) break;
+                pos[q] = 0;
+            }
+        }
+    }
+}
+
 void draw_sample(uint64_t seed, int64_t t, const Shape& sh, bool chidori,
-                 SampleHost& out) {
+                 SampleHost& out, bool with_cols) {
     const int n = sh.n;
     // resized, not cleared: a reused sample keeps its vectors' storage
     out.I.resize(n);
@@ -76,52 +115,35 @@ void draw_sample(uint64_t seed, int64_t t, const Shape& sh, bool chidori,
         SplitMix g = stream_for(seed, t, i, 0);
         out.I[i] = floyd(g, sh.s[i], sh.d[i]);
     }
+    if (chidori) {
+        if (with_cols) {
+            chidori_columns(sh, out);
+        } else {
+            for (int i = 0; i < n; ++i) {
+                out.Jcols[i].clear();
+                out.Jtup[i].clear();
+            }
+        }
+        return;
+    }
     for (int i = 0; i < n; ++i) {
-        // remaining modes, increasing; last fastest
         int rest[kMaxModes];
         int nr = 0;
         for (int j = 0; j < n; ++j)
             if (j != i) rest[nr++] = j;
         std::vector<int64_t>& cols = out.Jcols[i];
         std::vector<int32_t>& tup = out.Jtup[i];  // [ncols][n-1]
-        if (chidori) {
-            int64_t m = 1;
-            for (int q = 0; q < nr; ++q) m *= sh.s[rest[q]];
-            cols.resize((size_t)m);
-            tup.resize((size_t)m * nr);
-            // column c <-> positions (pos_0, .., pos_{nr-1}) in the I of the
-            // remaining modes, last fastest: an odometer over the positions;
-            // the unfolding column is sum_q I[pos_q] * prod_{q' > q} d
-            int64_t stride[kMaxModes];
-            stride[nr - 1] = 1;
-            for (int q = nr - 2; q >= 0; --q) stride[q] = stride[q + 1] * sh.d[rest[q + 1]];
-            int64_t pos[kMaxModes] = {0, 0, 0, 0};
-            for (int64_t c = 0; c < m; ++c) {
-                int64_t col = 0;
-                for (int q = 0; q < nr; ++q) {
-                    const int64_t v = out.I[rest[q]][pos[q]];
-                    tup[(size_t)c * nr + q] = (int32_t)v;
-                    col += v * stride[q];
-                }
-                cols[(size_t)c] = col;
-                for (int q = nr - 1; q >= 0; --q) {
-                    if (++pos[q] < sh.s[rest[q]]) break;
-                    pos[q] = 0;
-                }
-            }
-        } else {
-            int64_t P = 1;
-            for (int q = 0; q < nr; ++q) P *= sh.d[rest[q]];
-            SplitMix g = stream_for(seed, t, i, 1);
-            cols = floyd(g, sh.m[i], P);
-            tup.resize(cols.size() * nr);
-            for (size_t c = 0; c < cols.size(); ++c) {
-                int64_t rem = cols[c];
-                for (int q = nr - 1; q >= 0; --q) {
-                    int64_t dq = sh.d[rest[q]];
-                    tup[c * nr + q] = (int32_t)(rem % dq);
-                    rem /= dq;
-                }
+        int64_t P = 1;
+        for (int q = 0; q < nr; ++q) P *= sh.d[rest[q]];
+        SplitMix g = stream_for(seed, t, i, 1);
+        cols = floyd(g, sh.m[i], P);
+        tup.resize(cols.size() * nr);
+        for (size_t c = 0; c < cols.size(); ++c) {
+            int64_t rem = cols[c];
+            for (int q = nr - 1; q >= 0; --q) {
+                int64_t dq = sh.d[rest[q]];
+                tup[c * nr + q] = (int32_t)(rem % dq);
+                rem /= dq;
             }
         }
     }

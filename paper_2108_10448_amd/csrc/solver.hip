@@ -142,11 +142,16 @@ void release(rtcur_s* h) {
 
 // Host-side index data for one sample, packed for a single upload.
 struct IdxPack {
-    size_t bytes = 0;
+    size_t bytes = 0;        // whole index region
+    size_t host_bytes = 0;   // leading part the host fills (the rest: k_expand_cols)
+    int prod_mask = 0;       // blocks whose column data k_expand_cols forms
     size_t I_off[kMaxModes], rowidx_off, colx_off[kMaxBlocks], cidx_off[kMaxBlocks];
 };
 
-// Offsets of the index regions for this shape (they depend on sizes only).
+// Offsets of the index regions for this shape (they depend on sizes only):
+// first the sampled indices I_i and the column data of the fiber-sampled
+// blocks (packed on the host), then the column data of the blocks whose
+// columns are products of the I_j (formed on the device).
 static void index_layout(const Shape& sh, IdxPack& pk) {
     const int n = sh.n;
     size_t off = 0;
@@ -161,15 +166,22 @@ static void index_layout(const Shape& sh, IdxPack& pk) {
     ncol[0] = 1;
     for (int j = 1; j < n; ++j) ncol[0] *= sh.s[j];
     for (int i = 0; i < n; ++i) ncol[1 + i] = sh.m[i];
-    for (int b = 0; b <= n; ++b) {
-        pk.colx_off[b] = reserve(sizeof(int64_t) * ncol[b]);
-        pk.cidx_off[b] = reserve(sizeof(int32_t) * ncol[b] * (n - 1));
+    pk.prod_mask = 0;
+    for (int b = 0; b <= n; ++b)
+        if (b == 0 || sh.chidori) pk.prod_mask |= 1 << b;
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int b = 0; b <= n; ++b) {
+            if (((pk.prod_mask >> b) & 1) != pass) continue;
+            pk.colx_off[b] = reserve(sizeof(int64_t) * ncol[b]);
+            pk.cidx_off[b] = reserve(sizeof(int32_t) * ncol[b] * (n - 1));
+        }
+        if (pass == 0) pk.host_bytes = off;
     }
     pk.bytes = off;
 }
 
-// The sample's index data into base (pk.bytes bytes, laid out by
-// index_layout; the alignment gaps are left as they are).
+// The host part of the sample's index data into base (pk.host_bytes bytes,
+// laid out by index_layout; the alignment gaps are left as they are).
 static void pack_indices(const Shape& sh, const SampleHost& smp, const IdxPack& pk,
                          char* base) {
     const int n = sh.n;
@@ -177,31 +189,11 @@ static void pack_indices(const Shape& sh, const SampleHost& smp, const IdxPack& 
         int32_t* p = reinterpret_cast<int32_t*>(base + pk.I_off[i]);
         for (int64_t a = 0; a < sh.s[i]; ++a) p[a] = (int32_t)smp.I[i][a];
     }
+    if (sh.chidori) return;
     int64_t xstride[kMaxModes];
     xstride[n - 1] = 1;
     for (int j = n - 2; j >= 0; --j) xstride[j] = xstride[j + 1] * sh.d[j + 1];
-    // R block: columns = product of I_1..I_{n-1}, last fastest (an odometer
-    // over the positions in I_1..I_{n-1})
-    {
-        int64_t nc = 1;
-        for (int j = 1; j < n; ++j) nc *= sh.s[j];
-        int64_t* cx = reinterpret_cast<int64_t*>(base + pk.colx_off[0]);
-        int32_t* ci = reinterpret_cast<int32_t*>(base + pk.cidx_off[0]);
-        int64_t pos[kMaxModes] = {0, 0, 0, 0};
-        for (int64_t c = 0; c < nc; ++c) {
-            int64_t off2 = 0;
-            for (int j = 1; j < n; ++j) {
-                const int64_t v = smp.I[j][pos[j]];
-                off2 += v * xstride[j];
-                ci[(int64_t)(j - 1) * nc + c] = (int32_t)v;
-            }
-            cx[c] = off2;
-            for (int j = n - 1; j >= 1; --j) {
-                if (++pos[j] < sh.s[j]) break;
-                pos[j] = 0;
-            }
-        }
-    }
+    // fiber-sampled C_i: the drawn unfolding columns
     for (int i = 0; i < n; ++i) {
         int64_t* cx = reinterpret_cast<int64_t*>(base + pk.colx_off[1 + i]);
         int32_t* ci = reinterpret_cast<int32_t*>(base + pk.cidx_off[1 + i]);
@@ -625,7 +617,7 @@ struct Runner {
         if (!im.idx_ev)
             HIPCHK(hipEventCreateWithFlags(&im.idx_ev, hipEventDisableTiming));
         pack_indices(sh, smp, pk, im.h_idx);
-        HIPCHK(hipMemcpyAsync(im.d_idx, im.h_idx, pk.bytes, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(im.d_idx, im.h_idx, pk.host_bytes, hipMemcpyHostToDevice, s));
         HIPCHK(hipEventRecord(im.idx_ev, s));
         im.idx_pending = true;
         Prob& P = im.P;
@@ -637,6 +629,20 @@ struct Runner {
             P.blk[b].colx = reinterpret_cast<const int64_t*>(im.d_idx + pk.colx_off[b]);
             P.blk[b].cidx = reinterpret_cast<const int32_t*>(im.d_idx + pk.cidx_off[b]);
         }
+        return expand_cols(pk, nullptr);
+    }
+
+    // The product blocks' column data from the I_i now in the index region.
+    int expand_cols(const IdxPack& pk, const DevState* stp) {
+        if (!pk.prod_mask) return 0;
+        int64_t cmax = 0;
+        for (int b = 0; b < im.P.nblk; ++b)
+            if ((pk.prod_mask >> b) & 1) cmax = std::max<int64_t>(cmax, im.P.blk[b].ncols);
+        const unsigned gx = (unsigned)std::max<int64_t>(
+            1, std::min<int64_t>(256, (cmax + kThreads - 1) / kThreads));
+        hipLaunchKernelGGL(k_expand_cols, dim3(gx, im.P.nblk), dim3(kThreads), 0, s, im.P,
+                           pk.prod_mask, stp);
+        HIPCHK(hipGetLastError());
         return 0;
     }
 
@@ -668,12 +674,12 @@ struct Runner {
         char* hs = im.h_stage + (size_t)slot * im.idx_bytes;
         char* ds = im.d_stage + (size_t)slot * im.idx_bytes;
         pack_indices(sh, smp, pk, hs);
-        HIPCHK(hipMemcpyAsync(ds, hs, im.idx_bytes, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(ds, hs, pk.host_bytes, hipMemcpyHostToDevice, s));
         hipLaunchKernelGGL(k_take_sample, dim3(64), dim3(kThreads), 0, s,
                            reinterpret_cast<uint4*>(im.d_idx), reinterpret_cast<const uint4*>(ds),
-                           (int64_t)(im.idx_bytes / 16), (const DevState*)im.st);
+                           (int64_t)(pk.host_bytes / 16), (const DevState*)im.st);
         HIPCHK(hipGetLastError());
-        return 0;
+        return expand_cols(pk, im.st);
     }
 
     // Set-up of a solve: sample, loop state, zeroed factors, zeta_0 and the
@@ -682,7 +688,7 @@ struct Runner {
         int rc;
         im.recs.clear();
         im.ev_used = 0;
-        draw_sample(seed, 0, sh, sh.chidori, h->sample);
+        draw_sample(seed, 0, sh, sh.chidori, h->sample, false);
         if ((rc = upload_sample(h->sample, sh))) return rc;
         hipLaunchKernelGGL(k_init_state, dim3(16), dim3(kThreads), 0, s, im.st,
                            zeta0 > 0 ? zeta0 : 0.0, static_cast<uint32_t*>(im.Bf),
@@ -862,7 +868,7 @@ struct Runner {
                 tag = j;
                 if (j > 1) {
                     // new sample (t = j-1), gather there, L^(j-1) on its columns
-                    draw_sample(seed, j - 1, sh, sh.chidori, smp[q]);
+                    draw_sample(seed, j - 1, sh, sh.chidori, smp[q], false);
                     if ((rc = stage_sample(smp[q], sh, q))) return rc;
                     if ((rc = gather(X, xdt, kIfRunning))) return rc;
                     if ((rc = hexp())) return rc;
