@@ -1055,26 +1055,46 @@ __device__ __forceinline__ void eig_gq_tm(const double* G, int sp, int s, EigSha
     v4d tacc = {0.0, 0.0, 0.0, 0.0}, macc = {0.0, 0.0, 0.0, 0.0};
     for (int t = w; t < nt; t += 4) {
         const double* ga = G + (int64_t)(16 * t + col) * ldg + kq;
+        // Q^T as the A operand of the T product: A[p][k] = Q[16t + 4v + k][p]
+        // (loaded up front, so that the tile's epilogue does not wait on LDS)
+        double qa[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) qa[v] = col < RP ? sh.qs[(16 * t + 4 * v + kq) * RP + cc] : 0.0;
         v4d acc = {0.0, 0.0, 0.0, 0.0};
-        for (int j = 0; j < sp; j += 16) {  // sp is a multiple of 16
-            double av[4], bv[4];
+        // two operand sets of 16 columns, each loaded while the other one's
+        // products run
+        double a0[4], b0[4], a1[4], b1[4];
+        auto load = [&](double (&av)[4], double (&bv)[4], int j) {
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 av[u] = ga[j + 4 * u];
                 bv[u] = sh.qs[(j + 4 * u + kq) * RP + cc];
             }
+        };
+        auto mul = [&](const double (&av)[4], const double (&bv)[4]) {
 #pragma unroll
             for (int u = 0; u < 4; ++u)
                 acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], col < RP ? bv[u] : 0.0, acc,
                                                            0, 0, 0);
+        };
+        // (the scheduling barriers keep each set's loads ahead of the other
+        // set's products instead of next to their own use)
+        load(a0, b0, 0);
+        int j = 0;
+        for (; j + 32 <= sp; j += 32) {  // sp is a multiple of 16
+            load(a1, b1, j + 16);
+            __builtin_amdgcn_sched_barrier(0);
+            mul(a0, b0);
+            load(a0, b0, j + 32 < sp ? j + 32 : j);  // (at the end: reloaded, unused)
+            __builtin_amdgcn_sched_barrier(0);
+            mul(a1, b1);
         }
+        if (j < sp) mul(a0, b0);  // an odd number of 16-column sets
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int row = 16 * t + 4 * v + kq;
             if (row < s && col < RP) sh.zs[row * RP + col] = acc[v];
-            // Q^T as the A operand of this k-step: A[p][k] = Q[16t + 4v + k][p]
-            const double qa = col < RP ? sh.qs[row * RP + cc] : 0.0;
-            tacc = __builtin_amdgcn_mfma_f64_16x16x4f64(qa, acc[v], tacc, 0, 0, 0);
+            tacc = __builtin_amdgcn_mfma_f64_16x16x4f64(qa[v], acc[v], tacc, 0, 0, 0);
             macc = __builtin_amdgcn_mfma_f64_16x16x4f64(acc[v], acc[v], macc, 0, 0, 0);
         }
     }

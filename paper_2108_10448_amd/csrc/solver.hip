@@ -78,7 +78,8 @@ struct Impl {
     size_t arena_bytes = 0;
     void* scratch = nullptr;        // getters / reconstruct temporaries
     size_t scratch_bytes = 0;
-    DevState* st_host = nullptr;    // pinned mirror of the device state
+    DevState* st_host = nullptr;    // pinned mirror of the device state and,
+    size_t st_host_bytes = 0;       //   behind it, of the e^(k) history
     char* d_stage = nullptr;        // RTCUR-R: index data of queued samples
     char* h_stage = nullptr;        //   (device slots and their pinned source)
     size_t stage_bytes = 0;
@@ -87,6 +88,7 @@ struct Impl {
     hipEvent_t idx_ev = nullptr;    // recorded after that upload
     bool idx_pending = false;       //   (the buffer is rewritten only after it)
     int max_dyn_lds[3] = {0, 0, 0};  // k_eig<4|8|16, true>: room for the Gram
+    bool max_dyn_set = false;
     std::vector<int64_t> plan_key;  // sizes the current layout was planned for
 
     // layout of the current solve
@@ -378,8 +380,8 @@ static void plan(Impl& im, const Shape& sh, int esize, size_t idx_bytes, int max
     rg.part = ar.add(sizeof(double) * 2 * std::max<size_t>(im.ht_tiles.size(), kAbsmaxWG));
     rg.hpart = ar.add(sizeof(double) * im.ht_tiles.size());
     im.hist_len = (size_t)max_iter + 2;
+    rg.st = ar.add(sizeof(DevState));  // the history right behind: one read-back
     rg.hist = ar.add(sizeof(double) * im.hist_len);
-    rg.st = ar.add(sizeof(DevState));
     rg.tiles = ar.add(sizeof(int4) * (im.ht_tiles.size() + im.gram_items.size() +
                                       im.bfac_items.size()) +
                       sizeof(int2) * (im.z_tiles.size() + im.h_tiles.size()));
@@ -583,7 +585,18 @@ struct Runner {
     }
 
     int read_state(DevState& out) {
-        HIPCHK(hipMemcpyAsync(im.st_host, im.st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+        // the state and the e^(k) history behind it in one copy
+        const size_t bytes = (size_t)(reinterpret_cast<char*>(im.err_hist + im.hist_len) -
+                                      reinterpret_cast<char*>(im.st));
+        if (bytes > im.st_host_bytes) {
+            if (im.st_host) HIPCHK(hipHostFree(im.st_host));
+            im.st_host = nullptr;
+            im.st_host_bytes = 0;
+            HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&im.st_host), bytes,
+                                 hipHostMallocDefault));
+            im.st_host_bytes = bytes;
+        }
+        HIPCHK(hipMemcpyAsync(im.st_host, im.st, bytes, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         out = *im.st_host;
         return 0;
@@ -750,9 +763,10 @@ struct Runner {
         // histories
         h->err_hist.assign(K, 0.0);
         if (K > 0) {
-            std::vector<double> eh(K + 1);
-            HIPCHK(hipMemcpy(eh.data(), im.err_hist, sizeof(double) * (K + 1),
-                             hipMemcpyDeviceToHost));
+            // every path reads the state (and the history behind it) last
+            const double* eh = reinterpret_cast<const double*>(
+                reinterpret_cast<const char*>(im.st_host) +
+                (reinterpret_cast<const char*>(im.err_hist) - reinterpret_cast<const char*>(im.st)));
             for (int j = 1; j <= K; ++j) h->err_hist[j - 1] = eh[j];
         }
         h->zeta_hist.assign(K, 0.0);
@@ -1047,9 +1061,8 @@ int solve(rtcur_s* h, const void* X, int x_dtype, const Shape& sh, double zeta0,
     Impl& im = *impl_of(h);
     h->have_result = false;
     HIPCHK(hipSetDevice(h->device));
-    if (!im.st_host) {
-        HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&im.st_host), sizeof(DevState),
-                             hipHostMallocDefault));
+    if (!im.max_dyn_set) {
+        im.max_dyn_set = true;
         hipDeviceProp_t prop;
         HIPCHK(hipGetDeviceProperties(&prop, h->device));
         // k_eig keeps the Gram in dynamic LDS when it fits beside its
