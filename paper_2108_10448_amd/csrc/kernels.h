@@ -597,19 +597,23 @@ __device__ __forceinline__ double eig_start(uint32_t a, uint32_t p, uint32_t sal
 }
 
 template <int RP>
+// The small arrays come first so that their fixed addresses fit the 16-bit
+// immediate offset of LDS instructions (no address register each); the row
+// arrays, addressed per thread anyway, come last.
 struct EigShared {
-    double qs[kMaxS * RP];                 // Q rows; rows s..sp-1 stay zero
-    double zs[kMaxS * RP];                 // Z = G Q rows; rows s..sp-1 stay zero
     double tm[RP * RP], mm[RP * RP];       // T = Q^T Z, M = Z^T Z
-    double part[4][256];                   // per-wave 16 x 16 MFMA partials
-    double part2[4][256];                  // second set (T and M together)
-    double red[4];
-    int2 pairs[(kMaxS / 16) * (kMaxS / 16 + 1) / 2];  // Gram tile pair -> (ta, tb)
     double vv[RP * RP];                    // Rayleigh-Ritz: eigenvectors of T
+    double dv[RP];                         // RP = 16: 1 / R_jj of the factor in mm
     double th[RP], jc[RP], js[RP];         // eigenvalues; one Jacobi round's rotations
+    double red[4];
     int jp[RP], ord[RP];                   // rotation partners; decreasing order
     int gsteps;                            // steps of the guarded iteration
     int ok;
+    int cok;                               // RP = 16: the factor's pivots were positive
+    double part[4][256];                   // per-wave 16 x 16 MFMA partials
+    double part2[4][256];                  // second set (T and M together)
+    double qs[kMaxS * RP];                 // Q rows; rows s..sp-1 stay zero
+    double zs[kMaxS * RP];                 // Z = G Q rows; rows s..sp-1 stay zero
 };
 
 // T = Q^T Z (when wantT) and M = Z^T Z from the rows in LDS (sp = s rounded
@@ -700,27 +704,115 @@ __device__ __forceinline__ void eig_trsm(const double (&z)[RP], const double (&R
     }
 }
 
-// Z = G Q into zs (rows < s, columns < RP) on the float64 matrix cores; G
-// is sp x sp with row stride sp + 1 (zero beyond s), Q's rows s..sp-1 are
-// zero.  Wave w takes the 16-row tiles w, w + 4, ...; per tile one
-// accumulator chain over the rows of Q, its LDS operands loaded four
-// products ahead: lane l feeds G row 16t + l%16 and Q column l%16 at row
-// 4j + l/16 of product j; accumulator register v of lane l is row
-// 4v + l/16, column l%16.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Cholesky-QR factor of an RP x RP matrix M in LDS (its r x r block; the
+// identity beyond r) and the solve q = z R^-1 of a thread's row.  RP <= 8: R
+// in the registers of every thread (eig_chol, eig_trsm).  RP = 16 (where R
+// would not fit in registers): M is factored in place, in LDS, by wave 0
+// (right-looking: row j scaled by 1 / sqrt(pivot), then the trailing upper
+// triangle updated, lanes over its entries, steps in increasing j as in
+// eig_chol) and the solve reads R from there; M must be sh.mm and is
+// overwritten (its upper triangle becomes R).  Called by every thread.
+template <int RP, bool kLds = (RP > 8)>
+struct EigChol {
+    double R[RP][RP], di[RP];
+    __device__ __forceinline__ bool factor(double* M, int r, EigShared<RP>& sh) {
+        (void)sh;
+        return eig_chol<RP>(M, r, R, di);  // same value in every thread
+    }
+    __device__ __forceinline__ void solve(const double (&z)[RP], double (&q)[RP],
+                                          const EigShared<RP>& sh) const {
+        (void)sh;
+        eig_trsm<RP>(z, R, di, q);
+    }
+};
+
+template <int RP>
+struct EigChol<RP, true> {
+    __device__ __forceinline__ bool factor(double* M, int r, EigShared<RP>& sh) {
+        if (threadIdx.x < 64) {
+            const int lane = threadIdx.x;
+            bool ok = true;
+            for (int j = 0; j < r; ++j) {
+                const double d = M[j * RP + j];  // the pivot after steps 0..j-1
+                ok = ok && d > 0.0;
+                const double ri = rsqrt(d > 0.0 ? d : 1.0);
+                wave_sync();
+                if (lane >= j && lane < r) {
+                    const double v = M[j * RP + lane];
+                    M[j * RP + lane] = lane == j ? d * ri : v * ri;
+                }
+                if (lane == 0) sh.dv[j] = ri;
+                wave_sync();
+                for (int e = lane; e < RP * RP; e += 64) {
+                    const int i = e / RP, c = e % RP;
+                    if (i > j && c >= i && c < r) M[e] -= M[j * RP + i] * M[j * RP + c];
+                }
+                wave_sync();
+            }
+            // the identity beyond r: R_jj = 1 (j >= r), R_jc = 0 (c > j, j or c >= r)
+            for (int e = lane; e < RP * RP; e += 64) {
+                const int i = e / RP, c = e % RP;
+                if (c >= i && (i >= r || c >= r)) M[e] = i == c ? 1.0 : 0.0;
+            }
+            if (lane >= r && lane < RP) sh.dv[lane] = 1.0;
+            if (lane == 0) sh.cok = ok ? 1 : 0;
+        }
+        __syncthreads();
+        return sh.cok != 0;
+    }
+    __device__ __forceinline__ void solve(const double (&z)[RP], double (&q)[RP],
+                                          const EigShared<RP>& sh) const {
+        // (a scheduling barrier per column keeps the compiler from hoisting
+        // all of R's loads at once, which would not fit in registers)
+#pragma unroll
+        for (int p = 0; p < RP; ++p) {
+            double v = z[p];
+#pragma unroll
+            for (int k = 0; k < p; ++k) v -= q[k] * sh.mm[k * RP + p];
+            q[p] = v * sh.dv[p];
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+};
+
+// The Gram of a mode (sp x sp, sp = s rounded up to 16, zero beyond s) is
+// kept as its upper-triangular 16 x 16 tiles (ta <= tb) in the order
+// ta-major, tb increasing -- the order of k_gram's tile pairs -- 256 doubles
+// each, entry (r, c) of a tile at r * 16 + (c ^ r): the XOR spreads both a
+// tile's rows and its columns over the LDS banks.  Entry (a, b) of a lower
+// tile is entry (b, a) of its mirror.  Returns the offset of G[16 t + x][16 kt + y]
+// for x, y < 16.
+__device__ __forceinline__ int gram_at(int t, int kt, int x, int y, int nt) {
+    const bool up = t <= kt;
+    const int ta = up ? t : kt, tb = up ? kt : t;
+    const int tile = ta * nt - ta * (ta - 1) / 2 + (tb - ta);
+    const int r = up ? x : y, c = up ? y : x;
+    return tile * 256 + r * 16 + (c ^ r);
+}
+
+// Z = G Q into zs (rows < s, columns < RP) on the float64 matrix cores, G in
+// the tile layout above, Q's rows s..sp-1 zero.  Wave w takes the 16-row
+// tiles w, w + 4, ...; per tile one accumulator chain over the rows of Q:
+// lane l feeds G row 16t + l%16 and Q column l%16 at row 4j + l/16 of
+// product j; accumulator register v of lane l is row 4v + l/16, column l%16.
 template <int RP>
 __device__ __forceinline__ void eig_gq(const double* G, int sp, int s, EigShared<RP>& sh) {
-    const int ldg = sp + 1;  // odd row stride: a tile's 16 rows fall in different banks
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int col = lane & 15, kq = lane >> 4, cc = col < RP ? col : RP - 1;
     const int nt = sp >> 4;
     for (int t = w; t < nt; t += 4) {
-        const double* ga = G + (int64_t)(16 * t + col) * ldg + kq;
         v4d acc = {0.0, 0.0, 0.0, 0.0};
         for (int j = 0; j < sp; j += 16) {  // sp is a multiple of 16
             double av[4], bv[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                av[u] = ga[j + 4 * u];
+                av[u] = G[gram_at(t, j >> 4, col, 4 * u + kq, nt)];
                 bv[u] = sh.qs[(j + 4 * u + kq) * RP + cc];
             }
 #pragma unroll
@@ -735,12 +827,6 @@ __device__ __forceinline__ void eig_gq(const double* G, int sp, int s, EigShared
         }
     }
     __syncthreads();
-}
-
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // Eigen-decomposition of the symmetric RP x RP matrix in sh.mm by cyclic
@@ -924,10 +1010,10 @@ __device__ __noinline__ int eig_guarded(const double* G, int sp, int s, int r, i
         bool ok = true;
         for (int rep = 0; rep < 2; ++rep) {
             eig_tm<RP>(sp, false, sh);  // M = Z^T Z
-            double R[RP][RP], di[RP];
-            ok = eig_chol<RP>(sh.mm, m, R, di);  // same value in every thread
+            EigChol<RP> ch;
+            ok = ch.factor(sh.mm, m, sh);
             if (!ok) break;
-            eig_trsm<RP>(z, R, di, x);
+            ch.solve(z, x, sh);
             if (rep == 0) {
 #pragma unroll
                 for (int p = 0; p < RP; ++p) z[p] = x[p];
@@ -953,15 +1039,14 @@ __device__ __noinline__ int eig_guarded(const double* G, int sp, int s, int r, i
     return res;
 }
 
-// The Gram of one mode from k_gram's per-chunk 16 x 16 tiles into G (row
-// stride sp + 1, both triangles): E entries per thread and KG chunks per
+// The Gram of one mode from k_gram's per-chunk 16 x 16 tiles into G (the
+// tile layout of gram_at): E entries per thread and KG chunks per
 // load round, every load of a round issued before the first add; with
 // kMulti the rounds repeat over the chunks, which are always added in chunk
 // order.  Returns true (in every thread) if the stop flag was raised.
 template <int E, int KG, bool kMulti>
 __device__ __forceinline__ bool gram_assemble(const double* __restrict__ src0, int total,
-                                              int nkc, double* G, int sp, const int2* pairs,
-                                              const DevState* st) {
+                                              int nkc, double* G, const DevState* st) {
     for (int f0 = threadIdx.x; f0 < total; f0 += E * kThreads) {
         double sum[E];
 #pragma unroll
@@ -988,12 +1073,10 @@ __device__ __forceinline__ bool gram_assemble(const double* __restrict__ src0, i
         for (int u = 0; u < E; ++u) {
             const int f = f0 + u * kThreads;
             if (f >= total) continue;
-            const int2 pr = pairs[f >> 8];
-            const int t = f & 255;
-            const int a2 = pr.x * 16 + (t >> 4), b2 = pr.y * 16 + (t & 15);
-            // rows and columns beyond s come out of k_gram as zeros
-            G[a2 * (sp + 1) + b2] = sum[u];
-            G[b2 * (sp + 1) + a2] = sum[u];
+            // tile f / 256, entry (r, c); rows and columns beyond s come out
+            // of k_gram as zeros
+            const int r = (f >> 4) & 15, c = f & 15;
+            G[(f & ~255) + r * 16 + (c ^ r)] = sum[u];
         }
     }
     return false;
@@ -1004,8 +1087,7 @@ __device__ __forceinline__ bool gram_assemble(const double* __restrict__ src0, i
 // them (E2 x KG) are in flight at once.
 template <int E2, int KG>
 __device__ __forceinline__ bool gram_assemble2(const double* __restrict__ src0, int total,
-                                               int nkc, double* G, int sp, const int2* pairs,
-                                               const DevState* st) {
+                                               int nkc, double* G, const DevState* st) {
     for (int f0 = 2 * threadIdx.x; f0 < total; f0 += 2 * E2 * kThreads) {
         double2 v[E2][KG];
 #pragma unroll
@@ -1029,13 +1111,9 @@ __device__ __forceinline__ bool gram_assemble2(const double* __restrict__ src0, 
                     s0 += v[u][q].x;
                     s1 += v[u][q].y;
                 }
-            const int2 pr = pairs[f >> 8];
-            const int t = f & 255;
-            const int a2 = pr.x * 16 + (t >> 4), b2 = pr.y * 16 + (t & 15);
-            G[a2 * (sp + 1) + b2] = s0;
-            G[a2 * (sp + 1) + b2 + 1] = s1;
-            G[b2 * (sp + 1) + a2] = s0;
-            G[(b2 + 1) * (sp + 1) + a2] = s1;
+            const int r = (f >> 4) & 15, c = f & 15;  // c even: c, c + 1 in one row
+            G[(f & ~255) + r * 16 + (c ^ r)] = s0;
+            G[(f & ~255) + r * 16 + ((c + 1) ^ r)] = s1;
         }
     }
     return false;
@@ -1048,13 +1126,11 @@ __device__ __forceinline__ bool gram_assemble2(const double* __restrict__ src0, 
 // operand (A[m][k] = Z[k][m]).  Per-wave partials are added in wave order.
 template <int RP>
 __device__ __forceinline__ void eig_gq_tm(const double* G, int sp, int s, EigShared<RP>& sh) {
-    const int ldg = sp + 1;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int col = lane & 15, kq = lane >> 4, cc = col < RP ? col : RP - 1;
     const int nt = sp >> 4;
     v4d tacc = {0.0, 0.0, 0.0, 0.0}, macc = {0.0, 0.0, 0.0, 0.0};
     for (int t = w; t < nt; t += 4) {
-        const double* ga = G + (int64_t)(16 * t + col) * ldg + kq;
         // Q^T as the A operand of the T product: A[p][k] = Q[16t + 4v + k][p]
         // (loaded up front, so that the tile's epilogue does not wait on LDS)
         double qa[4];
@@ -1067,7 +1143,7 @@ __device__ __forceinline__ void eig_gq_tm(const double* G, int sp, int s, EigSha
         auto load = [&](double (&av)[4], double (&bv)[4], int j) {
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                av[u] = ga[j + 4 * u];
+                av[u] = G[gram_at(t, j >> 4, col, 4 * u + kq, nt)];
                 bv[u] = sh.qs[(j + 4 * u + kq) * RP + cc];
             }
         };
@@ -1113,206 +1189,14 @@ __device__ __forceinline__ void eig_gq_tm(const double* G, int sp, int s, EigSha
     __syncthreads();
 }
 
-// kLdsGram: the Gram sits in dynamic LDS (else in `gram`); a compile-time
-// choice so that its accesses compile to LDS (or global) instructions rather
-// than generic ones.
-template <int RP, bool kLdsGram>
-__global__ __launch_bounds__(kThreads) void k_eig(Prob P, const double* __restrict__ gpart,
-                                                  double* __restrict__ gram,
-                                                  double* __restrict__ W,
-                                                  double* __restrict__ Y,
-                                                  const double* __restrict__ Bd, int warm,
-                                                  int maxit, double rtol, DevState* st) {
-    extern __shared__ double Gl[];  // sp x sp (row stride sp + 1), when it fits
-    __shared__ EigShared<RP> sh;
-    const int i = blockIdx.x;
-    const int s = P.s[i], r = P.r[i];
-    const int sp = (s + 15) & ~15;
-    const int a = threadIdx.x;
-    const bool act = a < s;
-    double* G = kLdsGram ? Gl : gram + P.goff[i];
-    const int nt = sp >> 4;
-    const int npairs = nt * (nt + 1) / 2;
-    if (threadIdx.x < npairs) {
-        // pair index -> (ta, tb), ta <= tb, ta-major (the order of k_gram's items)
-        int ta = 0, rem = threadIdx.x;
-        while (rem >= nt - ta) {
-            rem -= nt - ta;
-            ++ta;
-        }
-        sh.pairs[threadIdx.x] = make_int2(ta, ta + rem);
-    }
-    // the warm start's rows load while the Gram is assembled
-    double* Wi = W + P.woff[i];
-    double qw[RP];
-#pragma unroll
-    for (int p = 0; p < RP; ++p) qw[p] = warm == 1 ? Wi[(act ? a : 0) * RP + p] : 0.0;
-    // Q and Z rows s..sp-1 stay zero for the padded products
-    for (int e = s * RP + threadIdx.x; e < sp * RP; e += kThreads) {
-        sh.qs[e] = 0.0;
-        sh.zs[e] = 0.0;
-    }
-    __syncthreads();
-    {
-        // the Gram from k_gram's per-chunk 16 x 16 tiles, chunks added in
-        // order; every load of a thread is issued before the first use
-        const int nkc = P.gnkc[i];
-        const int total = npairs * 256;
-        const double* src0 = gpart + (int64_t)P.gitem0[i] * 256;
-        // chunk counts up to 4 or 8: one load round per entry; more: rounds
-        // of 16 chunks, added in chunk order
-        bool stop;
-        if (nkc <= 4)
-            stop = gram_assemble2<12, 4>(src0, total, nkc, G, sp, sh.pairs, st);
-        else if (nkc <= 8)
-            stop = gram_assemble2<6, 8>(src0, total, nkc, G, sp, sh.pairs, st);
-        else
-            stop = gram_assemble<4, 16, true>(src0, total, nkc, G, sp, sh.pairs, st);
-        if (stop) return;
-    }
-    if (threadIdx.x == 0) sh.ok = 1;
-    double q[RP], z[RP];
-    if (warm == 1) {
-#pragma unroll
-        for (int p = 0; p < RP; ++p) q[p] = (act && p < r) ? qw[p] : 0.0;
-        __syncthreads();
-    } else {
-        // start block G * Omega, then Cholesky-QR twice.  Omega: with
-        // warm == 2 (a new sample under RTCUR-R) the previous mode-i factor's
-        // rows at the new I_i, which span nearly the wanted subspace; else,
-        // or if that block loses rank, a fixed pseudo-random block (a second
-        // one if G * Omega still loses rank; only a Gram of rank below r
-        // fails both)
-        bool ok = false;
-        for (int att = warm == 2 ? 0 : 1; att < 3 && !ok; ++att) {
-            __syncthreads();
-            for (int e = threadIdx.x; e < s * RP; e += kThreads) {
-                const int b = e / RP, p = e % RP;
-                const double v = att == 0 ? Bd[P.boff[i] + (int64_t)P.I[i][b] * RP + p]
-                                          : eig_start(b, p, att);
-                sh.qs[e] = p < r ? v : 0.0;
-            }
-            __syncthreads();
-            eig_gq<RP>(G, sp, s, sh);
-#pragma unroll
-            for (int p = 0; p < RP; ++p) z[p] = act ? sh.zs[a * RP + p] : 0.0;
-            ok = true;
-            for (int rep = 0; rep < 2 && ok; ++rep) {
-                eig_tm<RP>(sp, false, sh);  // M = Z^T Z
-                double R[RP][RP], di[RP];
-                ok = eig_chol<RP>(sh.mm, r, R, di);  // same value in every thread
-                if (ok) {
-                    eig_trsm<RP>(z, R, di, q);
-#pragma unroll
-                    for (int p = 0; p < RP; ++p) z[p] = q[p];
-                    if (rep == 0 && act) {
-#pragma unroll
-                        for (int p = 0; p < RP; ++p) sh.zs[a * RP + p] = z[p];
-                    }
-                    __syncthreads();
-                }
-            }
-        }
-        if (!ok) {
-            if (threadIdx.x == 0) {
-                st->stop = 1;
-                st->status = RTCUR_E_RANK;
-            }
-            return;
-        }
-    }
-    int steps = 0;
-    const int m = s < RP ? s : RP;  // columns available to the guarded iteration
-    // Plain subspace iteration on r columns for at most `limit` steps:
-    // 0 = converged, 1 = limit reached, 2 = too slow (the contraction per
-    // step predicts more than 30 further steps; only with allow_guard),
-    // 3 = Cholesky breakdown (sh.ok cleared).  Every branch is uniform: rn
-    // and tn come out of a block-wide sum.
-    auto plain = [&](int limit, bool allow_guard) -> int {
-        double prev = 0.0;
-        for (int it = 0;; ++it, ++steps) {
-            __syncthreads();
-            if (act) {
-#pragma unroll
-                for (int p = 0; p < RP; ++p) sh.qs[a * RP + p] = q[p];
-            }
-            __syncthreads();
-            eig_gq_tm<RP>(G, sp, s, sh);  // Z = G Q, T = Q^T Z, M = Z^T Z
-#pragma unroll
-            for (int p = 0; p < RP; ++p) z[p] = act ? sh.zs[a * RP + p] : 0.0;
-            double rn = 0.0, tn = 0.0;
-            {
-                double Tr[RP][RP];
-#pragma unroll
-                for (int k = 0; k < RP; ++k)
-#pragma unroll
-                    for (int p = 0; p < RP; ++p) {
-                        Tr[k][p] = sh.tm[k * RP + p];
-                        tn += Tr[k][p] * Tr[k][p];
-                    }
-#pragma unroll
-                for (int p = 0; p < RP; ++p) {
-                    double v = z[p];
-#pragma unroll
-                    for (int k = 0; k < RP; ++k) v -= q[k] * Tr[k][p];
-                    rn += act ? v * v : 0.0;
-                }
-            }
-            rn = block_sum<4>(rn, sh.red);
-            if (rn <= rtol * rtol * tn) return 0;
-            if (it >= limit) return 1;
-            if (allow_guard && m > r && it >= 4 && prev > 0.0) {
-                // more than 30 further steps at this contraction rho = rn / prev:
-                // rtol^2 tn / rn < rho^30 (a tiny rho underflows to 0: fast)
-                const double r2 = (rn / prev) * (rn / prev), r4 = r2 * r2, r8 = r4 * r4;
-                const double r30 = r8 * r8 * r8 * r4 * r2;
-                if (rn >= prev || rtol * rtol * tn < r30 * rn) return 2;
-            }
-            prev = rn;
-            double R[RP][RP], di[RP];
-            if (!eig_chol<RP>(sh.mm, r, R, di)) {
-                if (threadIdx.x == 0) sh.ok = 0;
-                return 3;
-            }
-            eig_trsm<RP>(z, R, di, q);
-        }
-    };
-    int pr = plain(maxit, true);
-    if (pr == 2) {
-        __syncthreads();
-        if (act) {
-#pragma unroll
-            for (int p = 0; p < RP; ++p) sh.qs[a * RP + p] = q[p];
-        }
-        if (threadIdx.x == 0) sh.gsteps = 0;
-        __syncthreads();
-        const int g = eig_guarded<RP>(G, sp, s, r, m, rtol, &sh, &sh.gsteps);
-#pragma unroll
-        for (int p = 0; p < RP; ++p) q[p] = act ? sh.qs[a * RP + p] : 0.0;
-        steps += sh.gsteps;
-        // a few plain steps from the Ritz vectors (or, after a breakdown of
-        // the guarded iterate, the plain iterate) polish the basis and form
-        // the T used below
-        pr = plain(g >= 0 ? 8 : maxit, false);
-    }
-    const bool conv = pr == 0;
-    __syncthreads();
-    if (!sh.ok) {
-        if (threadIdx.x == 0) {
-            st->stop = 1;
-            st->status = RTCUR_E_RANK;
-        }
-        return;
-    }
-    // Q spans the top-r eigenspace and T = Q^T G Q, so the truncated
-    // pseudo-inverse of the Gram is Q T^-1 Q^T: W_i = Q, Y_i = Q T^-1 with
-    // T = R^T R (Cholesky of the symmetrised T, every thread).
-    __syncthreads();
-    if (threadIdx.x < RP * RP) {
-        const int p = threadIdx.x / RP, t = threadIdx.x % RP;
-        sh.mm[threadIdx.x] = 0.5 * (sh.tm[p * RP + t] + sh.tm[t * RP + p]);
-    }
-    __syncthreads();
+// W_i = Q and Y_i = Q T^-1 with T = R^T R (Cholesky of the symmetrised T,
+// in sh.mm), the rank test on T, and the step counts; RP <= 8: R and R^-1 in
+// the registers of every thread.
+template <int RP>
+__device__ __forceinline__ void eig_finish_regs(const Prob& P, int i, int s, int r, int a, bool act,
+                                                const double (&q)[RP], bool conv, int steps,
+                                                double* __restrict__ Wi, double* __restrict__ Y,
+                                                DevState* st, EigShared<RP>& sh) {
     double R[RP][RP], di[RP];
     const bool tok = eig_chol<RP>(sh.mm, r, R, di);
     // Rinv = R^-1 (upper triangular)
@@ -1382,6 +1266,370 @@ __global__ __launch_bounds__(kThreads) void k_eig(Prob P, const double* __restri
             Wi[a * RP + p] = p < r ? q[p] : 0.0;
             Yi[a * RP + p] = p < r ? v : 0.0;
         }
+    }
+}
+
+// As eig_finish_regs for RP = 16: R factored in LDS (EigChol), R^-1 formed
+// column by column by the lanes of wave 0 into sh.vv, the rank test's sums
+// spread over wave 0's lanes, and Y read back from LDS by every thread.
+template <int RP>
+__device__ __forceinline__ void eig_finish_lds(const Prob& P, int i, int s, int r, int a, bool act,
+                                               bool conv, int steps,
+                                               double* __restrict__ Wi, double* __restrict__ Y,
+                                               DevState* st, EigShared<RP>& sh) {
+    EigChol<RP> ch;
+    const bool tok = ch.factor(sh.mm, r, sh);  // R in the upper triangle of sh.mm
+    if (threadIdx.x < RP) {
+        // column c of R^-1: Ri[c][c] = 1 / R_cc, Ri[j][c] = -(sum_{j < k <= c}
+        // R[j][k] Ri[k][c]) / R_jj for j < c, zero below the diagonal
+        const int c = threadIdx.x;
+        double col[RP];
+#pragma unroll
+        for (int j = RP - 1; j >= 0; --j) {
+            double v = 0.0;
+#pragma unroll
+            for (int k = j + 1; k < RP; ++k) v += k <= c ? sh.mm[j * RP + k] * col[k] : 0.0;
+            col[j] = j > c ? 0.0 : (j == c ? sh.dv[j] : -v * sh.dv[j]);
+        }
+#pragma unroll
+        for (int k = 0; k < RP; ++k) sh.vv[k * RP + c] = col[k];
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        // rank test on ||T||_F >= lambda_1 and 1/||T^-1||_F <= lambda_r
+        // (flag when lambda_r / lambda_1 may be <= 64 s 2^-52); the padded
+        // rows and columns of T and R^-1 are masked out
+        double tf = 0.0, tif = 0.0;
+        for (int e = threadIdx.x; e < RP * RP; e += 64) {
+            const int p = e / RP, t = e % RP;
+            const bool in = p < r && t < r;
+            const double tv = in ? 0.5 * (sh.tm[p * RP + t] + sh.tm[t * RP + p]) : 0.0;
+            double v = 0.0;  // (R^-1 R^-T)[p][t]
+#pragma unroll
+            for (int k = 0; k < RP; ++k)
+                v += (k >= p && k >= t) ? sh.vv[p * RP + k] * sh.vv[t * RP + k] : 0.0;
+            tf += tv * tv;
+            tif += in ? v * v : 0.0;
+        }
+        tf = wave_sum(tf);
+        tif = wave_sum(tif);
+        if (threadIdx.x == 0) {
+            atomicAdd(&st->eig_steps, steps);
+            if (!conv) atomicAdd(&st->eig_unconverged, 1);
+            if (!isfinite(tf) || !isfinite(tif)) {
+                st->stop = 1;
+                st->status = RTCUR_E_NONFINITE;
+            } else if (!tok || !(tf > 0.0) || 1.0 <= 64.0 * s * 0x1p-52 * sqrt(tf * tif)) {
+                st->stop = 1;
+                st->status = RTCUR_E_RANK;
+            }
+        }
+    }
+    if (act) {
+        // y = q T^-1 = (q R^-1) R^-T, q the thread's row of sh.qs
+        double qr[RP], u[RP];
+#pragma unroll
+        for (int k = 0; k < RP; ++k) qr[k] = sh.qs[a * RP + k];
+        double* Yi = Y + P.woff[i];
+#pragma unroll
+        for (int p = 0; p < RP; ++p) Wi[a * RP + p] = p < r ? qr[p] : 0.0;
+#pragma unroll
+        for (int p = 0; p < RP; ++p) {
+            double v = 0.0;
+#pragma unroll
+            for (int k = 0; k <= p; ++k) v += qr[k] * sh.vv[k * RP + p];
+            u[p] = v;
+            __builtin_amdgcn_sched_barrier(0);
+        }
+#pragma unroll
+        for (int p = 0; p < RP; ++p) {
+            double v = 0.0;
+#pragma unroll
+            for (int k = p; k < RP; ++k) v += u[k] * sh.vv[p * RP + k];
+            Yi[a * RP + p] = p < r ? v : 0.0;
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+}
+
+// kLdsGram: the Gram sits in dynamic LDS (else in `gram`); a compile-time
+// choice so that its accesses compile to LDS (or global) instructions rather
+// than generic ones.
+template <int RP, bool kLdsGram>
+__global__ __launch_bounds__(kThreads) void k_eig(Prob P, const double* __restrict__ gpart,
+                                                  double* __restrict__ gram,
+                                                  double* __restrict__ W,
+                                                  double* __restrict__ Y,
+                                                  const double* __restrict__ Bd, int warm,
+                                                  int maxit, double rtol, DevState* st) {
+    extern __shared__ double Gl[];  // the Gram's tiles (layout of gram_at), when they fit
+    __shared__ EigShared<RP> sh;
+    const int i = blockIdx.x;
+    const int s = P.s[i], r = P.r[i];
+    const int sp = (s + 15) & ~15;
+    const int a = threadIdx.x;
+    const bool act = a < s;
+    double* G = kLdsGram ? Gl : gram + P.goff[i];
+    const int nt = sp >> 4;
+    const int npairs = nt * (nt + 1) / 2;
+    // the warm start's rows load while the Gram is assembled
+    double* Wi = W + P.woff[i];
+    double qw[RP];
+#pragma unroll
+    for (int p = 0; p < RP; ++p) qw[p] = warm == 1 ? Wi[(act ? a : 0) * RP + p] : 0.0;
+    // Q and Z rows s..sp-1 stay zero for the padded products
+    for (int e = s * RP + threadIdx.x; e < sp * RP; e += kThreads) {
+        sh.qs[e] = 0.0;
+        sh.zs[e] = 0.0;
+    }
+    __syncthreads();
+    {
+        // the Gram from k_gram's per-chunk 16 x 16 tiles, chunks added in
+        // order; every load of a thread is issued before the first use
+        const int nkc = P.gnkc[i];
+        const int total = npairs * 256;
+        const double* src0 = gpart + (int64_t)P.gitem0[i] * 256;
+        // chunk counts up to 4 or 8: one load round per entry; more: rounds
+        // of 16 chunks, added in chunk order
+        bool stop;
+        if (nkc <= 4)
+            stop = gram_assemble2<12, 4>(src0, total, nkc, G, st);
+        else if (nkc <= 8)
+            stop = gram_assemble2<6, 8>(src0, total, nkc, G, st);
+        else
+            stop = gram_assemble<4, 16, true>(src0, total, nkc, G, st);
+        if (stop) return;
+    }
+    if (threadIdx.x == 0) sh.ok = 1;
+    double q[RP], z[RP];
+    if (warm == 1) {
+#pragma unroll
+        for (int p = 0; p < RP; ++p) q[p] = (act && p < r) ? qw[p] : 0.0;
+        __syncthreads();
+    } else {
+        // start block G * Omega, then Cholesky-QR twice.  Omega: with
+        // warm == 2 (a new sample under RTCUR-R) the previous mode-i factor's
+        // rows at the new I_i, which span nearly the wanted subspace; else,
+        // or if that block loses rank, a fixed pseudo-random block (a second
+        // one if G * Omega still loses rank; only a Gram of rank below r
+        // fails both)
+        bool ok = false;
+        for (int att = warm == 2 ? 0 : 1; att < 3 && !ok; ++att) {
+            __syncthreads();
+            for (int e = threadIdx.x; e < s * RP; e += kThreads) {
+                const int b = e / RP, p = e % RP;
+                const double v = att == 0 ? Bd[P.boff[i] + (int64_t)P.I[i][b] * RP + p]
+                                          : eig_start(b, p, att);
+                sh.qs[e] = p < r ? v : 0.0;
+            }
+            __syncthreads();
+            eig_gq<RP>(G, sp, s, sh);
+#pragma unroll
+            for (int p = 0; p < RP; ++p) z[p] = act ? sh.zs[a * RP + p] : 0.0;
+            ok = true;
+            for (int rep = 0; rep < 2 && ok; ++rep) {
+                eig_tm<RP>(sp, false, sh);  // M = Z^T Z
+                EigChol<RP> ch;
+                ok = ch.factor(sh.mm, r, sh);
+                if (ok) {
+                    ch.solve(z, q, sh);
+#pragma unroll
+                    for (int p = 0; p < RP; ++p) z[p] = q[p];
+                    if (rep == 0 && act) {
+#pragma unroll
+                        for (int p = 0; p < RP; ++p) sh.zs[a * RP + p] = z[p];
+                    }
+                    __syncthreads();
+                }
+            }
+        }
+        if (!ok) {
+            if (threadIdx.x == 0) {
+                st->stop = 1;
+                st->status = RTCUR_E_RANK;
+            }
+            return;
+        }
+    }
+    // RP = 16: the iterate's rows stay in sh.qs (and Z's in sh.zs) from here
+    // on instead of in registers, which would not hold them beside the rest
+    constexpr bool kRowsLds = RP > 8;
+    if constexpr (kRowsLds) {
+        __syncthreads();
+        if (act) {
+#pragma unroll
+            for (int p = 0; p < RP; ++p) sh.qs[a * RP + p] = q[p];
+        }
+    }
+    int steps = 0;
+    const int m = s < RP ? s : RP;  // columns available to the guarded iteration
+    // Plain subspace iteration on r columns for at most `limit` steps:
+    // 0 = converged, 1 = limit reached, 2 = too slow (the contraction per
+    // step predicts more than 30 further steps; only with allow_guard),
+    // 3 = Cholesky breakdown (sh.ok cleared).  Every branch is uniform: rn
+    // and tn come out of a block-wide sum.
+    auto plain = [&](int limit, bool allow_guard) -> int {
+        double prev = 0.0;
+        for (int it = 0;; ++it, ++steps) {
+            __syncthreads();
+            if (act) {
+#pragma unroll
+                for (int p = 0; p < RP; ++p) sh.qs[a * RP + p] = q[p];
+            }
+            __syncthreads();
+            eig_gq_tm<RP>(G, sp, s, sh);  // Z = G Q, T = Q^T Z, M = Z^T Z
+#pragma unroll
+            for (int p = 0; p < RP; ++p) z[p] = act ? sh.zs[a * RP + p] : 0.0;
+            double rn = 0.0, tn = 0.0;
+            if constexpr (RP <= 8) {
+                double Tr[RP][RP];
+#pragma unroll
+                for (int k = 0; k < RP; ++k)
+#pragma unroll
+                    for (int p = 0; p < RP; ++p) {
+                        Tr[k][p] = sh.tm[k * RP + p];
+                        tn += Tr[k][p] * Tr[k][p];
+                    }
+#pragma unroll
+                for (int p = 0; p < RP; ++p) {
+                    double v = z[p];
+#pragma unroll
+                    for (int k = 0; k < RP; ++k) v -= q[k] * Tr[k][p];
+                    rn += act ? v * v : 0.0;
+                }
+            } else {
+                // T read from LDS as it is used (no register copy; one
+                // column's loads at a time)
+#pragma unroll
+                for (int p = 0; p < RP; ++p) {
+                    double v = z[p];
+#pragma unroll
+                    for (int k = 0; k < RP; ++k) {
+                        const double t = sh.tm[k * RP + p];
+                        v -= q[k] * t;
+                        tn += t * t;
+                    }
+                    rn += act ? v * v : 0.0;
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+            rn = block_sum<4>(rn, sh.red);
+            if (rn <= rtol * rtol * tn) return 0;
+            if (it >= limit) return 1;
+            if (allow_guard && m > r && it >= 4 && prev > 0.0) {
+                // more than 30 further steps at this contraction rho = rn / prev:
+                // rtol^2 tn / rn < rho^30 (a tiny rho underflows to 0: fast)
+                const double r2 = (rn / prev) * (rn / prev), r4 = r2 * r2, r8 = r4 * r4;
+                const double r30 = r8 * r8 * r8 * r4 * r2;
+                if (rn >= prev || rtol * rtol * tn < r30 * rn) return 2;
+            }
+            prev = rn;
+            EigChol<RP> ch;
+            if (!ch.factor(sh.mm, r, sh)) {
+                if (threadIdx.x == 0) sh.ok = 0;
+                return 3;
+            }
+            ch.solve(z, q, sh);
+        }
+    };
+    // As plain, with the rows of Q (and Z) kept in LDS between steps (read
+    // into registers within a step): q_a = Z_a R^-1 goes back to the thread's
+    // row of sh.qs.
+    auto plain_lds = [&](int limit, bool allow_guard) -> int {
+        double prev = 0.0;
+        for (int it = 0;; ++it, ++steps) {
+            __syncthreads();
+            eig_gq_tm<RP>(G, sp, s, sh);  // Z = G Q, T = Q^T Z, M = Z^T Z
+            // the thread's rows of Q and Z in registers for this step only
+            // (every row index below kMaxS is in range; the inactive rows'
+            // terms are dropped); T read from LDS one column at a time
+            double qr[RP], zr[RP];
+#pragma unroll
+            for (int k = 0; k < RP; ++k) {
+                qr[k] = sh.qs[a * RP + k];
+                zr[k] = sh.zs[a * RP + k];
+            }
+            double rn = 0.0, tn = 0.0;
+#pragma unroll
+            for (int p = 0; p < RP; ++p) {
+                double v = zr[p];
+#pragma unroll
+                for (int k = 0; k < RP; ++k) {
+                    const double t = sh.tm[k * RP + p];
+                    v -= qr[k] * t;
+                    tn += t * t;
+                }
+                rn += v * v;
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            rn = block_sum<4>(act ? rn : 0.0, sh.red);
+            if (rn <= rtol * rtol * tn) return 0;
+            if (it >= limit) return 1;
+            if (allow_guard && m > r && it >= 4 && prev > 0.0) {
+                const double r2 = (rn / prev) * (rn / prev), r4 = r2 * r2, r8 = r4 * r4;
+                const double r30 = r8 * r8 * r8 * r4 * r2;
+                if (rn >= prev || rtol * rtol * tn < r30 * rn) return 2;
+            }
+            prev = rn;
+            EigChol<RP> ch;
+            if (!ch.factor(sh.mm, r, sh)) {
+                if (threadIdx.x == 0) sh.ok = 0;
+                return 3;
+            }
+            ch.solve(zr, qr, sh);
+            if (act) {
+#pragma unroll
+                for (int p = 0; p < RP; ++p) sh.qs[a * RP + p] = qr[p];
+            }
+        }
+    };
+    int pr;
+    if constexpr (kRowsLds) pr = plain_lds(maxit, true);
+    else pr = plain(maxit, true);
+    if (pr == 2) {
+        __syncthreads();
+        if constexpr (!kRowsLds) {
+            if (act) {
+#pragma unroll
+                for (int p = 0; p < RP; ++p) sh.qs[a * RP + p] = q[p];
+            }
+        }
+        if (threadIdx.x == 0) sh.gsteps = 0;
+        __syncthreads();
+        const int g = eig_guarded<RP>(G, sp, s, r, m, rtol, &sh, &sh.gsteps);
+        if constexpr (!kRowsLds) {
+#pragma unroll
+            for (int p = 0; p < RP; ++p) q[p] = act ? sh.qs[a * RP + p] : 0.0;
+        }
+        steps += sh.gsteps;
+        // a few plain steps from the Ritz vectors (or, after a breakdown of
+        // the guarded iterate, the plain iterate) polish the basis and form
+        // the T used below
+        if constexpr (kRowsLds) pr = plain_lds(g >= 0 ? 8 : maxit, false);
+        else pr = plain(g >= 0 ? 8 : maxit, false);
+    }
+    const bool conv = pr == 0;
+    __syncthreads();
+    if (!sh.ok) {
+        if (threadIdx.x == 0) {
+            st->stop = 1;
+            st->status = RTCUR_E_RANK;
+        }
+        return;
+    }
+    // Q spans the top-r eigenspace and T = Q^T G Q, so the truncated
+    // pseudo-inverse of the Gram is Q T^-1 Q^T: W_i = Q, Y_i = Q T^-1 with
+    // T = R^T R (Cholesky of the symmetrised T, every thread).
+    __syncthreads();
+    if (threadIdx.x < RP * RP) {
+        const int p = threadIdx.x / RP, t = threadIdx.x % RP;
+        sh.mm[threadIdx.x] = 0.5 * (sh.tm[p * RP + t] + sh.tm[t * RP + p]);
+    }
+    __syncthreads();
+    if constexpr (RP <= 8) {
+        eig_finish_regs<RP>(P, i, s, r, a, act, q, conv, steps, Wi, Y, st, sh);
+    } else {
+        eig_finish_lds<RP>(P, i, s, r, a, act, conv, steps, Wi, Y, st, sh);
     }
 }
 

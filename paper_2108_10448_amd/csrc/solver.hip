@@ -540,7 +540,7 @@ struct Runner {
         HIPCHK(pe());
         int smax = 0;
         for (int i = 0; i < n; ++i) smax = std::max(smax, (P.s[i] + 15) / 16 * 16);
-        const size_t lds_g = sizeof(double) * (size_t)smax * (smax + 1);
+        const size_t lds_g = sizeof(double) * 256 * (size_t)(smax / 16) * (smax / 16 + 1) / 2;
         const int use_lds = lds_g <= (size_t)im.max_dyn_lds[RP == 4 ? 0 : RP == 8 ? 1 : 2];
         // float64 blocks: subspace to 1e-13; float32 blocks need far less
         const double rtol = sizeof(T) == 8 ? 1e-13 : 1e-10;
