@@ -410,3 +410,25 @@ def test_outliers_without_iterations():
     S_o, L_o = oracle_outliers(res, inst.X)
     assert not np.any(L_g.cpu().numpy())
     assert np.array_equal(S_g.cpu().numpy(), S_o)
+
+
+def test_handle_reuse_across_sizes_and_samplings():
+    # one handle solves, in turn: A, B (same sizes as A, other data and seed:
+    # the layout and work lists of A are reused), C (other sizes and fibre
+    # sampling), then A again; each equals the oracle (FP64 bar)
+    import paper_2108_10448_amd as rt
+    h = rt.create(0)
+    a = synth.tucker_plus_sparse((40, 36, 30), (3, 2, 3), alpha=0.2, seed=21)
+    b = synth.tucker_plus_sparse((40, 36, 30), (3, 2, 3), alpha=0.3, seed=22)
+    c = synth.tucker_plus_sparse((28, 33, 25), (2, 3, 2), alpha=0.2, seed=23)
+    Ia = synth.sample_sizes(a.dims, a.ranks, 3.0)[0]
+    Ic, Jc = synth.sample_sizes(c.dims, c.ranks, 3.0, fiber=True)
+    cases = [(a, Ia, None, 5), (b, Ia, None, 6), (c, Ic, Jc, 7), (a, Ia, None, 8)]
+    for inst, I, J, seed in cases:
+        X = torch.from_numpy(inst.X).to("cuda:0")
+        info = rt.solve(h, X, inst.ranks, I, J, tol=0.0, max_iter=5, seed=seed, check=False)
+        torch.cuda.synchronize()
+        res = oracle_rtcur(inst.X, inst.ranks, I, J, None, 0.7, 0.0, 5, seed, "F")
+        assert info.iters == res.iters == 5
+        compare(res, h, info, label=f"reuse {inst.dims} seed {seed}")
+    rt.destroy(h)
