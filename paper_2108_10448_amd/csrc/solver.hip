@@ -289,9 +289,9 @@ static void plan(Impl& im, const Shape& sh, int esize, size_t idx_bytes, int max
         P.woff[i] = im.w_elems;
         im.w_elems += sh.s[i] * RP;
         P.goff[i] = im.g_elems;
-        // Gram padded to whole 16 x 16 tiles, row stride sp + 1
-        const int64_t sp = (sh.s[i] + 15) / 16 * 16;
-        im.g_elems += sp * (sp + 1);
+        // the upper-triangular 16 x 16 tiles of the Gram
+        const int64_t nt = (sh.s[i] + 15) / 16;
+        im.g_elems += 256 * (nt * (nt + 1) / 2);
         P.zoff[i] = im.z_elems;
         im.z_elems += (int64_t)RP * sh.m[i];
     }
