@@ -29,10 +29,10 @@
  *   - A handle is not thread-safe.  All device work runs on the stream given
  *     to rtcur_create, in stream order; rtcur_solve returns after its device
  *     work has finished.
- *   - Limits: 2 <= n <= 4; 1 <= r_i <= 16 (r_i <= 8 when n = 4);
- *     prod(r_i) <= 4096; s_i <= 256; r_{n-1} * prod_{0<l<n-1} s_l <= 2048
- *     (one slice of the sampled core); prod(d_i) <= 2^40.  Shapes beyond
- *     them return RTCUR_E_INVAL before any device work.
+ *   - Limits: 2 <= n <= 4; 1 <= r_i <= 16 for every n; prod(r_i) <= 4096;
+ *     s_i <= 256; r_{n-1} * prod_{0<l<n-1} s_l <= 2048 (one slice of the
+ *     sampled core); prod(d_i) <= 2^40.  Shapes beyond them return
+ *     RTCUR_E_INVAL before any device work.
  */
 #ifndef RTCUR_H
 #define RTCUR_H

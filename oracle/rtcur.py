@@ -25,9 +25,17 @@ Readings of the paper where it is silent (each listed in the design doc):
 * RTCUR-R draws a fresh sample before every iteration after the first
   (resample counter t = k before iteration k+1), gathers X there, evaluates the
   stored L^(k) there, and computes e^(k+1) and its denominator on that sample;
-* rank test: the truncated SVD is rejected (status E_RANK) when
-  sigma_r <= sqrt(64 * |I_i| * 2^-52) * sigma_1, the smallest singular-value
-  ratio both this oracle and a Gram-matrix eigensolver resolve reliably.
+* rank test: Theorem 2.5 needs rank(U_i) = r_i; the truncated SVD is rejected
+  (status E_RANK) when sigma_r <= max(|I_i|, |J_i|) * 2^-52 * sigma_1, the
+  level below which LAPACK's SVD of U_i cannot tell sigma_r from rounding
+  (its backward error is a small multiple of max(|I_i|, |J_i|) eps sigma_1).
+  The library's eigensolver works on the Gram U_i U_i^T and resolves less
+  (reading R14): it may report E_RANK where this oracle does
+  not, never the other way round.
+
+Besides the result, each run records the smallest sigma_r / sigma_1 met in
+any truncated SVD (Result.min_sig_ratio), so that a test can tell whether a
+rank report of the library lies in that documented band.
 """
 
 from __future__ import annotations
@@ -54,9 +62,10 @@ class OracleError(Exception):
         self.status = status
 
 
-def rank_rtol(s: int) -> float:
-    """Relative singular-value floor for the rank test (see module doc)."""
-    return math.sqrt(64.0 * s * 2.0 ** -52)
+def rank_rtol(s: int, m: int) -> float:
+    """Relative singular-value floor of the rank test for an s x m U_i:
+    max(s, m) * 2^-52 (see module doc)."""
+    return max(int(s), int(m)) * 2.0 ** -52
 
 
 @dataclass
@@ -86,6 +95,7 @@ class Result:
     LB: List[np.ndarray]           # L^(k) on the blocks
     factors: Optional[Factors]
     dims: tuple = ()
+    min_sig_ratio: float = 1.0     # smallest sigma_r / sigma_1 of any U_i seen
 
     @property
     def err(self) -> float:
@@ -114,7 +124,7 @@ def truncated_pinv(U: np.ndarray, r: int):
     W, sig, Vt = np.linalg.svd(U, full_matrices=False)
     if not np.all(np.isfinite(sig)):
         raise OracleError(E_NONFINITE, "non-finite singular values")
-    if sig[0] == 0.0 or sig[r - 1] <= rank_rtol(U.shape[0]) * sig[0]:
+    if sig[0] == 0.0 or sig[r - 1] <= rank_rtol(U.shape[0], U.shape[1]) * sig[0]:
         raise OracleError(E_RANK, "U_i has numerical rank below r_i")
     Wr, sr, Vr = W[:, :r], sig[:r], Vt[:r].T
     pinv = Vr @ (Wr / sr).T
@@ -198,6 +208,7 @@ def rtcur(X: np.ndarray, ranks: Sequence[int], I_sizes: Sequence[int],
     zeta = float(zeta0)
     k = 0
     e = 1.0
+    min_ratio = 1.0
     e_hist: List[float] = []
     z_hist: List[float] = []
     while e > tol and k < max_iter:
@@ -212,6 +223,7 @@ def rtcur(X: np.ndarray, ranks: Sequence[int], I_sizes: Sequence[int],
         CB = [XB[b] - SB[b] for b in range(n + 1)]
         # Step (II): Fiber CUR L-update (equations 8 and 9)
         f = l_update(CB, samp, ranks)
+        min_ratio = min([min_ratio] + [float(sg[-1] / sg[0]) for sg in f.sig])
         LB = evaluate(f, samp)
         k += 1
         # Stopping rule (equation 14): E = X - L - S = C - L on the blocks
@@ -222,7 +234,7 @@ def rtcur(X: np.ndarray, ranks: Sequence[int], I_sizes: Sequence[int],
         z_hist.append(zeta)
     status = OK if e <= tol else NOT_CONVERGED
     return Result(status, k, e_hist, z_hist, float(zeta0), den, samp, XB, CB,
-                  SB, LB, f, dims)
+                  SB, LB, f, dims, min_ratio)
 
 
 def outliers(res: Result, X: np.ndarray, zeta: Optional[float] = None):

@@ -170,11 +170,12 @@ class Info:
 class Handle:
     """Owns an rtcur_t; closes it on destroy() or garbage collection."""
 
-    def __init__(self, ptr, device, variant, dtype):
+    def __init__(self, ptr, device, variant, dtype, stream=None):
         self.ptr = ptr
         self.device = device
         self.variant = variant
         self.dtype = dtype
+        self.stream = stream   # the torch stream the library launches on
         self.dims = None
         self.ranks = None
 
@@ -194,20 +195,37 @@ def _torch():
 
 
 def create(device: int = 0, stream=None, variant: str = "F", dtype=None) -> Handle:
-    """rtcur_create on `device`, bound to `stream` (default: torch's current
-    stream of that device).  variant "F" (fixed samples) or "R" (resample)."""
+    """rtcur_create on `device`, bound to `stream` (a torch stream or a raw
+    hipStream_t; default: torch's current stream of that device).  variant
+    "F" (fixed samples) or "R" (resample).  Every call on the handle first
+    makes its stream wait for the work queued so far on torch's current
+    stream (which produced X and last used the output buffers)."""
     torch = _torch()
     dtype = torch.float64 if dtype is None else dtype
     cdt = F64 if dtype == torch.float64 else (BF16 if dtype == torch.bfloat16 else F32)
     if stream is None:
         stream = torch.cuda.current_stream(device)
-    sptr = ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else stream)
+    elif not hasattr(stream, "cuda_stream"):
+        stream = torch.cuda.ExternalStream(int(stream), device=f"cuda:{device}")
+    sptr = ctypes.c_void_p(stream.cuda_stream)
     out = ctypes.c_void_p()
     rc = lib().rtcur_create(ctypes.byref(out), device, sptr,
                             FIXED if variant == "F" else RESAMPLE, cdt)
     if rc != OK:
         raise RTCURError(rc, f"rtcur_create: {strerror(rc)}")
-    return Handle(out, device, variant, dtype)
+    return Handle(out, device, variant, dtype, stream)
+
+
+def _order(h: Handle) -> None:
+    """The handle's stream waits for everything queued so far on torch's
+    current stream of its device: the producer of X, and the last users of
+    any output buffer the caching allocator hands out on that stream.  The
+    library's calls return after their own device work has finished, so
+    the results need no ordering the other way."""
+    torch = _torch()
+    cur = torch.cuda.current_stream(h.device)
+    if h.stream is not None and h.stream.cuda_stream != cur.cuda_stream:
+        h.stream.wait_stream(cur)
 
 
 def destroy(h: Handle) -> None:
@@ -233,6 +251,7 @@ def solve(h: Handle, X, ranks: Sequence[int], I_sizes: Optional[Sequence[int]] =
         I_sizes, _ = default_sizes(dims, ranks, upsilon)
     info = RtcurInfo()
     r32 = (ctypes.c_int32 * len(ranks))(*[int(r) for r in ranks])
+    _order(h)
     rc = lib().rtcur_solve(h.ptr, ctypes.c_void_p(X.data_ptr()),
                            F64 if X.dtype == torch.float64 else F32, len(dims),
                            _i64(dims), r32, _i64(I_sizes),
@@ -315,6 +334,8 @@ def solve_batch(handles: Sequence[Handle], Xs, ranks, I_sizes=None, J_sizes=None
         Ls = [torch.empty(X.shape, dtype=odt, device=X.device) for X in Xs]
         lo = (ctypes.c_void_p * count)(*[L.data_ptr() for L in Ls])
     hs = (ctypes.c_void_p * len(handles))(*[h.ptr for h in handles])
+    for h in handles:
+        _order(h)
     infos = (RtcurInfo * count)()
     st = (ctypes.c_int32 * count)()
     rc = lib().rtcur_solve_batch(hs, len(handles), count, xs,
@@ -345,6 +366,7 @@ def reconstruct(h: Handle, out=None, dtype=None):
         out = torch.empty(h.dims, dtype=dtype or _out_dtype(h), device=f"cuda:{h.device}")
     if out.dtype not in (torch.float32, torch.float64) or not out.is_contiguous():
         raise TypeError("out must be a C-contiguous float32/float64 tensor")
+    _order(h)
     rc = lib().rtcur_reconstruct(h.ptr, ctypes.c_void_p(out.data_ptr()),
                                  F64 if out.dtype == torch.float64 else F32)
     if rc != OK:
@@ -369,6 +391,7 @@ def outliers(h: Handle, X, zeta: Optional[float] = None, *, with_L: bool = False
         raise TypeError("output dtype must be float32 or float64")
     S = torch.empty(h.dims, dtype=odt, device=X.device)
     L_ = torch.empty(h.dims, dtype=odt, device=X.device) if with_L else None
+    _order(h)
     rc = lib().rtcur_outliers(h.ptr, ctypes.c_void_p(X.data_ptr()),
                               F64 if X.dtype == torch.float64 else F32,
                               float(zeta) if zeta is not None else 0.0,

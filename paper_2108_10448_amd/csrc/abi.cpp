@@ -173,7 +173,20 @@ int rtcur_solve_batch(rtcur_t* hs, int32_t nh, int32_t count, const void* const*
     // entries (ties by index), each given to the handle with the fewest
     // entries assigned so far (ties: lowest handle); every handle then solves
     // its list in that order
-    std::vector<int32_t> order(count);
+    std::vector<int32_t> order;
+    std::vector<std::vector<int32_t>> list;
+    std::vector<double> load;
+    std::vector<std::thread> pool;
+    std::vector<char> inline_list;
+    try {
+        order.resize(count);
+        list.resize(nt > 0 ? nt : 0);
+        load.assign(nt > 0 ? nt : 0, 0.0);
+        inline_list.assign(nt > 0 ? nt : 0, 0);
+        pool.reserve(nt > 1 ? nt - 1 : 0);
+    } catch (...) {
+        return RTCUR_E_NOMEM;
+    }
     for (int32_t j = 0; j < count; ++j) order[j] = j;
     auto entries = [&](int32_t j) {
         double v = 1.0;
@@ -181,16 +194,18 @@ int rtcur_solve_batch(rtcur_t* hs, int32_t nh, int32_t count, const void* const*
             v *= (double)dims[(int64_t)j * rtcur::kMaxModes + q];
         return v;
     };
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int32_t x, int32_t y) { return entries(x) > entries(y); });
-    std::vector<std::vector<int32_t>> list(nt > 0 ? nt : 0);
-    std::vector<double> load(nt > 0 ? nt : 0, 0.0);
-    for (int32_t j : order) {
-        int32_t t = 0;
-        for (int32_t u = 1; u < nt; ++u)
-            if (load[u] < load[t]) t = u;
-        list[t].push_back(j);
-        load[t] += entries(j);
+    try {
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int32_t x, int32_t y) { return entries(x) > entries(y); });
+        for (int32_t j : order) {
+            int32_t t = 0;
+            for (int32_t u = 1; u < nt; ++u)
+                if (load[u] < load[t]) t = u;
+            list[t].push_back(j);
+            load[t] += entries(j);
+        }
+    } catch (...) {
+        return RTCUR_E_NOMEM;  // before any solve started
     }
     auto work = [&](int32_t t) {
         for (int32_t j : list[t]) {
@@ -209,15 +224,20 @@ int rtcur_solve_batch(rtcur_t* hs, int32_t nh, int32_t count, const void* const*
             if (infos) infos[j] = inf;
         }
     };
-    try {
-        std::vector<std::thread> pool;
-        pool.reserve(nt > 1 ? nt - 1 : 0);
-        for (int32_t t = 1; t < nt; ++t) pool.emplace_back(work, t);
-        if (nt > 0) work(0);
-        for (auto& th : pool) th.join();
-    } catch (...) {
-        return RTCUR_E_STATE;  // no thread could be started
+    // Handles whose thread cannot be started run their lists on the calling
+    // thread; every started thread is joined before returning, whatever
+    // happened, so no joinable std::thread is ever destroyed.
+    for (int32_t t = 1; t < nt; ++t) {
+        try {
+            pool.emplace_back(work, t);
+        } catch (...) {
+            inline_list[t] = 1;
+        }
     }
+    if (nt > 0) inline_list[0] = 1;
+    for (int32_t t = 0; t < nt; ++t)
+        if (inline_list[t]) work(t);
+    for (auto& th : pool) th.join();
     int rc = RTCUR_OK;
     for (int32_t j = 0; j < count; ++j)
         if (status[j] < 0) return status[j];

@@ -104,6 +104,8 @@ struct DevState {
     int eig_unconverged;
     double e_prev, e_last;  // the last two e^(k) decided (host chunk planning)
     unsigned counter[4]; // last-workgroup counters (gather, ht, spare)
+    double eigest[kMaxModes];  // per mode: lower bound of lambda_r / lambda_1 of
+                               // the Gram at the last eigensolver call (0: none)
 };
 
 // ------------------------------------------------------------------ handle

@@ -142,6 +142,7 @@ __global__ __launch_bounds__(kThreads) void k_init_state(DevState* st, double ze
         st->e_prev = -1.0;
         st->e_last = -1.0;
         for (int j = 0; j < 4; ++j) st->counter[j] = 0u;
+        for (int j = 0; j < kMaxModes; ++j) st->eigest[j] = 0.0;
     }
     const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * kThreads;
@@ -529,7 +530,12 @@ __global__ __launch_bounds__(kThreads) void k_gram(
     const int boff = same ? 0 : 16;
     load(va, ina, cb);
     if (cb + kGramPanel < ce) load(vb, inb, cb + kGramPanel);
-    if (sf) return;
+    // the decision workgroup of this launch may raise the stop flag while
+    // the waves of this one read it: thread 0's value decides for all
+    __shared__ int sflag;
+    if (tid == 0) sflag = sf;
+    __syncthreads();
+    if (sflag) return;  // uniform
     for (int p0 = cb; p0 < ce; p0 += 2 * kGramPanel) {
         {
             const bool in = ina;
@@ -1043,10 +1049,10 @@ __device__ __noinline__ int eig_guarded(const double* G, int sp, int s, int r, i
 // tile layout of gram_at): E entries per thread and KG chunks per
 // load round, every load of a round issued before the first add; with
 // kMulti the rounds repeat over the chunks, which are always added in chunk
-// order.  Returns true (in every thread) if the stop flag was raised.
+// order.
 template <int E, int KG, bool kMulti>
-__device__ __forceinline__ bool gram_assemble(const double* __restrict__ src0, int total,
-                                              int nkc, double* G, const DevState* st) {
+__device__ __forceinline__ void gram_assemble(const double* __restrict__ src0, int total,
+                                              int nkc, double* G) {
     for (int f0 = threadIdx.x; f0 < total; f0 += E * kThreads) {
         double sum[E];
 #pragma unroll
@@ -1061,8 +1067,6 @@ __device__ __forceinline__ bool gram_assemble(const double* __restrict__ src0, i
                 for (int q = 0; q < KG; ++q)  // masked in the sum
                     v[u][q] = src[(int64_t)(q0 + q < nkc ? q0 + q : q0) * 256];
             }
-            // uniform: same f0 and q0 in every thread
-            if (q0 == 0 && f0 == (int)threadIdx.x && stopped(st)) return true;
 #pragma unroll
             for (int u = 0; u < E; ++u)
 #pragma unroll
@@ -1079,15 +1083,14 @@ __device__ __forceinline__ bool gram_assemble(const double* __restrict__ src0, i
             G[(f & ~255) + r * 16 + (c ^ r)] = sum[u];
         }
     }
-    return false;
 }
 
 // As gram_assemble for at most KG chunks, two neighbouring entries of a tile
 // per thread and 16-byte loads: half the load instructions, so that all of
 // them (E2 x KG) are in flight at once.
 template <int E2, int KG>
-__device__ __forceinline__ bool gram_assemble2(const double* __restrict__ src0, int total,
-                                               int nkc, double* G, const DevState* st) {
+__device__ __forceinline__ void gram_assemble2(const double* __restrict__ src0, int total,
+                                               int nkc, double* G) {
     for (int f0 = 2 * threadIdx.x; f0 < total; f0 += 2 * E2 * kThreads) {
         double2 v[E2][KG];
 #pragma unroll
@@ -1098,8 +1101,6 @@ __device__ __forceinline__ bool gram_assemble2(const double* __restrict__ src0, 
             for (int q = 0; q < KG; ++q)  // masked in the sum
                 v[u][q] = *reinterpret_cast<const double2*>(src + (int64_t)(q < nkc ? q : 0) * 256);
         }
-        // uniform: same f0 in every thread
-        if (f0 == 2 * (int)threadIdx.x && stopped(st)) return true;
 #pragma unroll
         for (int u = 0; u < E2; ++u) {
             const int f = f0 + 2 * u * kThreads;
@@ -1116,7 +1117,6 @@ __device__ __forceinline__ bool gram_assemble2(const double* __restrict__ src0, 
             G[(f & ~255) + r * 16 + ((c + 1) ^ r)] = s1;
         }
     }
-    return false;
 }
 
 // Z = G Q into zs as eig_gq, with T = Q^T Z and M = Z^T Z formed from each
@@ -1238,6 +1238,10 @@ __device__ __forceinline__ void eig_finish_regs(const Prob& P, int i, int s, int
         if (threadIdx.x == 0) {
             atomicAdd(&st->eig_steps, steps);
             if (!conv) atomicAdd(&st->eig_unconverged, 1);
+            // 1 / (||T||_F ||T^-1||_F) <= lambda_r / lambda_1: the next call's
+            // stopping scale
+            const double q = tf * tif;
+            st->eigest[i] = (q > 0.0 && isfinite(q)) ? 1.0 / sqrt(q) : 0.0;
             if (!isfinite(tf) || !isfinite(tif)) {
                 st->stop = 1;
                 st->status = RTCUR_E_NONFINITE;
@@ -1316,6 +1320,10 @@ __device__ __forceinline__ void eig_finish_lds(const Prob& P, int i, int s, int 
         if (threadIdx.x == 0) {
             atomicAdd(&st->eig_steps, steps);
             if (!conv) atomicAdd(&st->eig_unconverged, 1);
+            // 1 / (||T||_F ||T^-1||_F) <= lambda_r / lambda_1: the next call's
+            // stopping scale
+            const double q = tf * tif;
+            st->eigest[i] = (q > 0.0 && isfinite(q)) ? 1.0 / sqrt(q) : 0.0;
             if (!isfinite(tf) || !isfinite(tif)) {
                 st->stop = 1;
                 st->status = RTCUR_E_NONFINITE;
@@ -1361,11 +1369,21 @@ __global__ __launch_bounds__(kThreads) void k_eig(Prob P, const double* __restri
                                                   double* __restrict__ W,
                                                   double* __restrict__ Y,
                                                   const double* __restrict__ Bd, int warm,
-                                                  int maxit, double rtol, DevState* st) {
+                                                  int maxit, double rtol_arg, DevState* st) {
     extern __shared__ double Gl[];  // the Gram's tiles (layout of gram_at), when they fit
     __shared__ EigShared<RP> sh;
     const int i = blockIdx.x;
     const int s = P.s[i], r = P.r[i];
+    // rtol_arg > 0: a fixed relative residual.  rtol_arg = -u (the blocks'
+    // unit roundoff): scaled to the weakest wanted pair, u sqrt(lambda_r /
+    // lambda_1) from the previous call's bound (1e-10 on a first call), so
+    // that the subspace error rtol lambda_1 / lambda_r stays at the level
+    // u kappa that the blocks' rounding already puts there
+    double rtol = rtol_arg;
+    if (rtol_arg < 0.0) {
+        const double est = st->eigest[i];
+        rtol = est > 0.0 ? fmax(1e-12, -rtol_arg * sqrt(est)) : 1e-10;
+    }
     const int sp = (s + 15) & ~15;
     const int a = threadIdx.x;
     const bool act = a < s;
@@ -1377,6 +1395,12 @@ __global__ __launch_bounds__(kThreads) void k_eig(Prob P, const double* __restri
     double qw[RP];
 #pragma unroll
     for (int p = 0; p < RP; ++p) qw[p] = warm == 1 ? Wi[(act ? a : 0) * RP + p] : 0.0;
+    // the stop flag, loaded by thread 0 now (its round trip overlaps the
+    // Gram assembly, whose reads stay inside this shape's partials either
+    // way) and shared through LDS afterwards, so that the whole workgroup
+    // takes the same branch: a sibling mode's workgroup of this launch may
+    // raise the flag meanwhile
+    const int sf0 = threadIdx.x == 0 ? stop_flag(st) : 0;
     // Q and Z rows s..sp-1 stay zero for the padded products
     for (int e = s * RP + threadIdx.x; e < sp * RP; e += kThreads) {
         sh.qs[e] = 0.0;
@@ -1391,15 +1415,17 @@ __global__ __launch_bounds__(kThreads) void k_eig(Prob P, const double* __restri
         const double* src0 = gpart + (int64_t)P.gitem0[i] * 256;
         // chunk counts up to 4 or 8: one load round per entry; more: rounds
         // of 16 chunks, added in chunk order
-        bool stop;
         if (nkc <= 4)
-            stop = gram_assemble2<12, 4>(src0, total, nkc, G, st);
+            gram_assemble2<12, 4>(src0, total, nkc, G);
         else if (nkc <= 8)
-            stop = gram_assemble2<6, 8>(src0, total, nkc, G, st);
+            gram_assemble2<6, 8>(src0, total, nkc, G);
         else
-            stop = gram_assemble<4, 16, true>(src0, total, nkc, G, st);
-        if (stop) return;
+            gram_assemble<4, 16, true>(src0, total, nkc, G);
     }
+    if (threadIdx.x == 0) sh.ok = sf0;
+    __syncthreads();
+    if (sh.ok) return;  // uniform: one value for the whole workgroup
+    __syncthreads();    // every thread has read sh.ok before it is reset
     if (threadIdx.x == 0) sh.ok = 1;
     double q[RP], z[RP];
     if (warm == 1) {

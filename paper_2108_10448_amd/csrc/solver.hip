@@ -542,10 +542,10 @@ struct Runner {
         for (int i = 0; i < n; ++i) smax = std::max(smax, (P.s[i] + 15) / 16 * 16);
         const size_t lds_g = sizeof(double) * 256 * (size_t)(smax / 16) * (smax / 16 + 1) / 2;
         const int use_lds = lds_g <= (size_t)im.max_dyn_lds[RP == 4 ? 0 : RP == 8 ? 1 : 2];
-        // float64 blocks: subspace to 1e-13; with float32 blocks the Gram's
-        // entries carry the blocks' rounding (about 6e-8 relative), so a
-        // residual of 1e-8 ||T|| is already below what the data resolves
-        const double rtol = sizeof(T) == 8 ? 1e-13 : 1e-8;
+        // float64 blocks: subspace to 1e-13; float32 (and bfloat16) blocks:
+        // the residual scaled to the weakest wanted pair from float32's unit
+        // roundoff (see k_eig)
+        const double rtol = sizeof(T) == 8 ? 1e-13 : -0x1p-24;
         HIPCHK(pb(PK_EIG));
         if (use_lds)
             hipLaunchKernelGGL((k_eig<RP, true>), dim3(n), dim3(kThreads), lds_g, s, P,

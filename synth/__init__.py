@@ -54,14 +54,25 @@ def _tucker(core: np.ndarray, factors: Sequence[np.ndarray]) -> np.ndarray:
 def tucker_plus_sparse(dims: Sequence[int], ranks: Sequence[int], alpha: float,
                        c: float = 1.0, seed: int = 0,
                        storage=np.float64, orthonormal: bool = True,
-                       keep_parts: bool = True) -> Instance:
-    """Low-multilinear-rank tensor plus Bernoulli(alpha) sparse outliers."""
+                       keep_parts: bool = True, spread: float = 1.0) -> Instance:
+    """Low-multilinear-rank tensor plus Bernoulli(alpha) sparse outliers.
+
+    spread > 1 scales the core's slices along every mode by a geometric
+    sequence from 1 down to 1/spread (after the draws, so the draw order is
+    unchanged): the unfoldings' singular values then spread over about that
+    factor, an ill-conditioned low-rank part."""
     dims = tuple(int(d) for d in dims)
     ranks = tuple(int(r) for r in ranks)
     if len(dims) != len(ranks):
         raise ValueError("dims and ranks must have the same length")
     rng = np.random.default_rng(seed)
     core = rng.standard_normal(ranks)
+    if spread != 1.0:
+        for k, r in enumerate(ranks):
+            w = spread ** (-np.arange(r) / max(r - 1, 1))
+            shape = [1] * len(ranks)
+            shape[k] = r
+            core = core * w.reshape(shape)
     factors = []
     for d, r in zip(dims, ranks):
         Y = rng.standard_normal((d, r))

@@ -34,6 +34,8 @@ def compare(res, h, info, *, fp64=True, label="", eabs=None):
     import torch
     print(f"[parity] {label} iters gpu={info.iters} oracle={res.iters} "
           f"err gpu={info.err:.6e} oracle={res.err:.6e}", flush=True)
+    # every eigensolver call of the solve passed its residual test
+    assert info.eig_unconverged == 0, f"{label}: {info.eig_unconverged} unconverged"
     n = len(res.dims)
     out = {}
     for i in range(n):

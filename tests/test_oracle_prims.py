@@ -96,4 +96,25 @@ def test_truncated_pinv_rank_floor():
     with pytest.raises(OracleError) as ei:
         truncated_pinv(U, 3)
     assert ei.value.status == E_RANK
-    assert rank_rtol(86) == pytest.approx((64 * 86 * 2.0 ** -52) ** 0.5, rel=1e-15)
+    assert rank_rtol(86, 7396) == 7396 * 2.0 ** -52
+    assert rank_rtol(300, 20) == 300 * 2.0 ** -52
+
+
+@pytest.mark.parametrize("shape", [(8, 30), (30, 8), (12, 12)])
+def test_truncated_pinv_rank_floor_is_sigma_ratio(shape):
+    # sigma_r / sigma_1 just above max(s, m) eps is accepted, just below is
+    # rejected: U = W diag(sig) V^T with exactly known singular values
+    s, m = shape
+    rng = np.random.default_rng(7)
+    W, _ = np.linalg.qr(rng.standard_normal((s, 3)))
+    V, _ = np.linalg.qr(rng.standard_normal((m, 3)))
+    floor = max(s, m) * 2.0 ** -52
+    ok = (W * np.array([1.0, 0.5, 1e3 * floor])) @ V.T
+    Wr, sr, Vr, P = truncated_pinv(ok, 3)
+    assert sr[2] / sr[0] == pytest.approx(1e3 * floor, rel=1e-2)
+    bad = (W * np.array([1.0, 0.5, 0.0])) @ V.T   # sigma_3 at rounding level
+    with pytest.raises(OracleError) as ei:
+        truncated_pinv(bad, 3)
+    assert ei.value.status == E_RANK
+    # rank 2 is fine on the same matrix
+    truncated_pinv(bad, 2)
