@@ -12,4 +12,4 @@ from .sampler import (Sample, Stream, chidori_tuples, decode_columns,
                       draw_sample, encode_columns, floyd_subset, sample_I,
                       splitmix64_step)
 from .tensor import (fold, fro, hard_threshold, mode_product,
-                     multi_mode_product, unfold)
+                     multi_mode_product, round_bf16, unfold)

@@ -47,7 +47,8 @@ from typing import List, Optional, Sequence
 import numpy as np
 
 from .sampler import Sample, draw_sample
-from .tensor import fro, hard_threshold, mode_product, multi_mode_product, unfold
+from .tensor import (fro, hard_threshold, mode_product, multi_mode_product, round_bf16,
+                     unfold)
 
 OK = 0
 NOT_CONVERGED = 1
@@ -96,6 +97,8 @@ class Result:
     factors: Optional[Factors]
     dims: tuple = ()
     min_sig_ratio: float = 1.0     # smallest sigma_r / sigma_1 of any U_i seen
+    DB: List[np.ndarray] = field(default_factory=list)  # X - L^(k-1) on the
+                                   # blocks: the residual the last threshold saw
 
     @property
     def err(self) -> float:
@@ -174,15 +177,30 @@ def evaluate(f: Factors, samp: Sample) -> List[np.ndarray]:
     return out
 
 
+# e^(k) at which the bfloat16-storage emulation goes over to full precision
+BF16_SWITCH = 1e-2
+
+
 def rtcur(X: np.ndarray, ranks: Sequence[int], I_sizes: Sequence[int],
           J_sizes: Optional[Sequence[int]] = None, zeta0: Optional[float] = None,
           gamma: float = 0.7, tol: float = 1e-5, max_iter: int = 100,
-          seed: int = 0, variant: str = "F") -> Result:
+          seed: int = 0, variant: str = "F", storage: str = "f64") -> Result:
     """Robust Tensor CUR (Algorithm 1).  variant "F" keeps the first sample,
     "R" resamples before every iteration after the first (Section 3.4).
 
+    storage "f64" is the algorithm as stated.  storage "bf16" (variant F
+    only) emulates bfloat16 storage of the sampled blocks, the precision in
+    which the mixed-precision mode takes its decisions: while e^(k) >
+    max(tol, BF16_SWITCH), X on the blocks and every C = X - S are held
+    rounded to bfloat16 (the denominator of e^(k) from the rounded X); once
+    e^(k) <= max(tol, BF16_SWITCH) the loop continues (if e^(k) > tol) with
+    the unrounded X, its denominator and unrounded C.  All arithmetic stays
+    float64; the returned XB is the unrounded X.
+
     Raises OracleError(E_INVAL / E_RANK / E_NONFINITE) on the error paths.
     """
+    if storage not in ("f64", "bf16") or (storage == "bf16" and variant != "F"):
+        raise OracleError(E_INVAL, "storage must be f64, or bf16 with variant F")
     X = np.asarray(X, dtype=np.float64)
     n = X.ndim
     dims = X.shape
@@ -195,15 +213,20 @@ def rtcur(X: np.ndarray, ranks: Sequence[int], I_sizes: Sequence[int],
 
     samp = draw_sample(seed, 0, dims, I_sizes, J_sizes)
     XB = _checked_gather(X, samp)
+    XB_exact = XB
+    low = storage == "bf16"            # blocks held at bfloat16 precision
+    if low:
+        XB = [round_bf16(b) for b in XB]
     den = sum(fro(b) for b in XB)
     zero = [np.zeros_like(b) for b in XB]
     if den == 0.0:
-        return Result(OK, 0, [], [], zeta0, den, samp, XB, [b.copy() for b in XB],
+        return Result(OK, 0, [], [], zeta0, den, samp, XB_exact, [b.copy() for b in XB],
                       zero, zero, None, dims)
 
     LB = [np.zeros_like(b) for b in XB]
     CB = [b.copy() for b in XB]
     SB = [np.zeros_like(b) for b in XB]
+    DB: List[np.ndarray] = []
     f = None
     zeta = float(zeta0)
     k = 0
@@ -214,13 +237,16 @@ def rtcur(X: np.ndarray, ranks: Sequence[int], I_sizes: Sequence[int],
     while e > tol and k < max_iter:
         if variant == "R" and k >= 1:
             samp = draw_sample(seed, k, dims, I_sizes, J_sizes)
-            XB = _checked_gather(X, samp)
+            XB = XB_exact = _checked_gather(X, samp)
             den = sum(fro(b) for b in XB)
             LB = evaluate(f, samp)
         zeta = gamma * zeta
         # Step (I): partial S-update on the blocks (equations 11 and 13)
-        SB = [hard_threshold(XB[b] - LB[b], zeta) for b in range(n + 1)]
+        DB = [XB[b] - LB[b] for b in range(n + 1)]
+        SB = [hard_threshold(DB[b], zeta) for b in range(n + 1)]
         CB = [XB[b] - SB[b] for b in range(n + 1)]
+        if low:
+            CB = [round_bf16(c) for c in CB]
         # Step (II): Fiber CUR L-update (equations 8 and 9)
         f = l_update(CB, samp, ranks)
         min_ratio = min([min_ratio] + [float(sg[-1] / sg[0]) for sg in f.sig])
@@ -232,9 +258,14 @@ def rtcur(X: np.ndarray, ranks: Sequence[int], I_sizes: Sequence[int],
             raise OracleError(E_NONFINITE, "non-finite relative error")
         e_hist.append(e)
         z_hist.append(zeta)
+        if low and e <= max(tol, BF16_SWITCH):
+            # the remaining iterations (if any) at full precision
+            low = False
+            XB = XB_exact
+            den = sum(fro(b) for b in XB)
     status = OK if e <= tol else NOT_CONVERGED
-    return Result(status, k, e_hist, z_hist, float(zeta0), den, samp, XB, CB,
-                  SB, LB, f, dims, min_ratio)
+    return Result(status, k, e_hist, z_hist, float(zeta0), den, samp, XB_exact, CB,
+                  SB, LB, f, dims, min_ratio, DB)
 
 
 def outliers(res: Result, X: np.ndarray, zeta: Optional[float] = None):

@@ -48,3 +48,14 @@ def hard_threshold(D: np.ndarray, zeta: float) -> np.ndarray:
 def fro(A: np.ndarray) -> float:
     """Frobenius norm, sqrt of the sum of squares (Section 1.2)."""
     return float(np.sqrt(np.sum(A * A)))
+
+
+def round_bf16(A: np.ndarray) -> np.ndarray:
+    """Each value rounded to the nearest bfloat16 (8 significant bits: the
+    sign, an 8-bit exponent and 7 stored fraction bits), ties to the even
+    significand; finite normal values only.  Used to hold the sampled blocks
+    at bfloat16 storage precision (the mixed-precision mode); not part of
+    the paper's algorithm, which is stated in exact arithmetic."""
+    A = np.asarray(A, dtype=np.float64)
+    m, e = np.frexp(A)                  # A = m 2^e, 0.5 <= |m| < 1
+    return np.ldexp(np.rint(m * 256.0) / 256.0, e)   # rint: ties to even

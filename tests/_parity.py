@@ -45,14 +45,22 @@ def compare(res, h, info, *, fp64=True, label="", eabs=None):
     assert len(e) == info.iters
     k = min(info.iters, res.iters)
     etol = 1e-9 if fp64 else 2e-3
+    # absolute floor: e^(k) = sum_b ||C_b - L_b|| / den moves by at most
+    # sum_b ||dL_b|| / den when L moves by dL, so the L bar (1e-10 / 1e-4
+    # relative) allows |de| up to that bar times sum_b ||L_b|| / den; it
+    # matters only where e^(k) itself is at rounding level (exact low rank)
+    ltol = 1e-10 if fp64 else 1e-4
+    lsum = sum(float(np.linalg.norm(Lb)) for Lb in res.LB)
+    efloor = ltol * lsum / res.den if res.den > 0 else 1e-15
     for j in range(k):
         if eabs is not None:   # bfloat16 blocks: an absolute bound on e^(k)
             assert abs(e[j] - res.err_hist[j]) <= eabs, (j, e[j], res.err_hist[j])
         else:
-            assert abs(e[j] - res.err_hist[j]) <= etol * res.err_hist[j] + 1e-15, \
+            assert abs(e[j] - res.err_hist[j]) <= etol * res.err_hist[j] + efloor, \
                 (j, e[j], res.err_hist[j])
         assert z[j] == res.zeta_hist[j], (j, z[j], res.zeta_hist[j])
     supp_agree = []
+    band_ok = True
     for b in range(n + 1):
         Xb = rt.get_block(h, b, rt.BLOCK_X).reshape(res.XB[b].shape)
         if fp64:
@@ -67,6 +75,8 @@ def compare(res, h, info, *, fp64=True, label="", eabs=None):
             Cb = rt.get_block(h, b, rt.BLOCK_C).reshape(res.XB[b].shape)
             out[f"L{b}"] = rel(Lb, res.LB[b])
             out[f"C{b}"] = rel(Cb, res.CB[b])
+            if not fp64 and agree < 1.0 and res.DB and res.iters > 0:
+                band_ok = band_ok and _flips_in_band(res, b, sup, Lb, Cb, out)
     if info.iters == res.iters:
         Lfull = rt.reconstruct(h, dtype=torch.float64).cpu().numpy()
         out["Lfull"] = rel(Lfull, res.reconstruct())
@@ -79,6 +89,30 @@ def compare(res, h, info, *, fp64=True, label="", eabs=None):
                 assert v <= ltol, (key, v)
         if fp64:
             assert out["support_min"] == 1.0
-        else:
-            assert out["support_min"] >= 0.9999
+        elif out["support_min"] < 0.9999:
+            # below the bar only where every flipped entry is one that the
+            # library's float32 rounding of L decides (see _flips_in_band)
+            assert band_ok, out
     return out
+
+
+def _flips_in_band(res, b, sup, Lb, Cb, out):
+    """Reduced precision: an entry's support bit is the strict test
+    |D| > zeta_K on D = X - L^(K-1), so the two sides can disagree only
+    where |D| lies within the discrepancy of the two L^(K-1) of zeta_K.
+    That discrepancy is measured where both supports hold (there C = X - S
+    = L^(K-1) on both sides) and at the returned iterate (L^K); every
+    flipped entry must lie within twice the larger of the two of zeta_K,
+    plus float32's rounding of X - L.  Records the flip count and band."""
+    zeta = res.zeta_hist[-1]
+    both = sup & res.support[b]
+    tau = float(np.max(np.abs(Lb - res.LB[b])))
+    if np.any(both):
+        tau = max(tau, float(np.max(np.abs(Cb[both] - res.CB[b][both]))))
+    D = res.DB[b]
+    flips = sup != res.support[b]
+    slack = 2.0 * tau + 2.0 ** -22 * (np.abs(res.XB[b]) + np.abs(D))
+    inside = np.abs(np.abs(D) - zeta) <= slack
+    out[f"flips{b}"] = int(np.sum(flips))
+    out[f"band{b}"] = float(2.0 * tau)
+    return bool(np.all(inside[flips]))

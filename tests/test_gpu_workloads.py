@@ -20,14 +20,15 @@ class _OracleRuns:
     """Oracle runs of one instance for a given number of iterations (tol =
     0), computed once each."""
 
-    def __init__(self, X, ranks, I, variant="F"):
+    def __init__(self, X, ranks, I, variant="F", storage="f64"):
         self.X, self.ranks, self.I, self.variant = X, ranks, I, variant
+        self.storage = storage
         self.cache = {}
 
     def at(self, K):
         if K not in self.cache:
             self.cache[K] = oracle_rtcur(self.X, self.ranks, self.I, None, None, 0.7, 0.0,
-                                         K, 0, self.variant)
+                                         K, 0, self.variant, storage=self.storage)
         return self.cache[K]
 
 
@@ -50,19 +51,37 @@ def test_video_to_tolerance_fp64(video_tol):
     compare(ref, h, info, label="video 120x160x3x200 to tol fp64")
 
 
-@pytest.mark.parametrize("dtype", ["f32", "bf16"])
-def test_video_to_tolerance_reduced(video_tol, dtype):
+def test_video_to_tolerance_f32(video_tol):
     import paper_2108_10448_amd as rt
     inst, I, ref, runs = video_tol
-    tdt = torch.float32 if dtype == "f32" else torch.bfloat16
-    h, info, _ = run_gpu(inst.X, inst.ranks, I, dtype=tdt, check=False)
+    h, info, _ = run_gpu(inst.X, inst.ranks, I, dtype=torch.float32, check=False)
     assert info.converged and abs(info.iters - ref.iters) <= 1
     res = runs.at(info.iters)
-    eabs = None if dtype == "f32" else 2 * 2.0 ** -9
-    compare(res, h, info, fp64=False, label=f"video to tol {dtype}", eabs=eabs)
+    compare(res, h, info, fp64=False, label="video to tol f32")
     L = rt.reconstruct(h)
     assert L.dtype == torch.float32
     assert rel(L.cpu().numpy().astype(np.float64), res.reconstruct()) < 1e-4
+
+
+def test_video_to_tolerance_bf16(video_tol):
+    # bfloat16 blocks until e^(k) <= 1e-2, then the float32 sweep, against
+    # the oracle holding its blocks at the same storage precision (the
+    # decisions of the bfloat16 phase depend on it); the distance to the
+    # plain float64 oracle is reported: on this workload, whose low-rank part
+    # does not separate (true error 0.2), the early rounding moves the path
+    import paper_2108_10448_amd as rt
+    inst, I, ref, _ = video_tol
+    h, info, _ = run_gpu(inst.X, inst.ranks, I, dtype=torch.bfloat16, check=False)
+    low = _OracleRuns(inst.X, inst.ranks, I, storage="bf16")
+    assert info.converged and abs(info.iters - ref.iters) <= 1
+    res = low.at(info.iters)
+    compare(res, h, info, fp64=False, label="video to tol bf16 (bf16-storage oracle)")
+    L = rt.reconstruct(h).cpu().numpy().astype(np.float64)
+    assert rel(L, res.reconstruct()) < 1e-4
+    full = ref if ref.iters == info.iters else oracle_rtcur(
+        inst.X, inst.ranks, I, None, None, 0.7, 0.0, info.iters, 0, "F")
+    print(f"[video bf16] L against the float64-storage oracle: "
+          f"{rel(L, full.reconstruct()):.3e}", flush=True)
 
 
 def test_cube300_resample_fp32():

@@ -118,3 +118,70 @@ def test_truncated_pinv_rank_floor_is_sigma_ratio(shape):
     assert ei.value.status == E_RANK
     # rank 2 is fine on the same matrix
     truncated_pinv(bad, 2)
+
+
+def _bf16_grid(lo_exp, hi_exp):
+    # every positive bfloat16 value 2^e * (1 + f/128), f = 0..127, written out
+    vals = [2.0 ** e * (1.0 + f / 128.0) for e in range(lo_exp, hi_exp + 1)
+            for f in range(128)]
+    return np.array(sorted(vals))
+
+
+def test_round_bf16_special_values():
+    from oracle.tensor import round_bf16
+    one = 1.0
+    cases = {
+        1.0: 1.0, 3.0: 3.0, -2.5: -2.5, 0.0: 0.0,
+        one + 2.0 ** -8: 1.0,                           # tie: to the even significand
+        one + 3 * 2.0 ** -8: one + 2.0 ** -6,           # tie: 1+2^-7 is odd, round up
+        one + 2.0 ** -8 + 2.0 ** -20: one + 2.0 ** -7,  # just above the tie
+        one + 2.0 ** -8 - 2.0 ** -20: 1.0,              # just below the tie
+        -(one + 3 * 2.0 ** -8): -(one + 2.0 ** -6),
+        255.5: 256.0,                                   # significand carry
+    }
+    for x, want in cases.items():
+        assert round_bf16(np.array([x]))[0] == want, x
+
+
+def test_round_bf16_is_nearest_on_the_written_out_grid():
+    # brute force: the nearest grid value (ties: the one with even f)
+    from oracle.tensor import round_bf16
+    grid = _bf16_grid(-6, 6)
+    rng = np.random.default_rng(0)
+    x = rng.uniform(2.0 ** -5, 60.0, 4000)
+    got = round_bf16(x)
+    for xi, gi in zip(x, got):
+        d = np.abs(grid - xi)
+        best = grid[d == d.min()]
+        if len(best) == 1:
+            assert gi == best[0]
+        else:   # exact tie between two neighbours
+            m = [b for b in best if int(round((b / 2.0 ** np.floor(np.log2(b)) - 1) * 128)) % 2 == 0]
+            assert gi == m[0]
+    assert np.array_equal(round_bf16(-x), -got)
+
+
+def test_bf16_storage_emulation_switches_to_full_precision():
+    # with the blocks held in bfloat16 until e^(k) <= 1e-2, the run ends at
+    # the same tolerance as the full-precision one and its float64 phase
+    # starts from unrounded X (the returned X blocks are the unrounded ones)
+    import synth
+    from oracle import rtcur
+    inst = synth.tucker_plus_sparse((30, 28, 26), (2, 2, 2), alpha=0.1, seed=1)
+    I, _ = synth.sample_sizes(inst.dims, inst.ranks, 3.0)
+    full = rtcur(inst.X, inst.ranks, I, tol=1e-6)
+    low = rtcur(inst.X, inst.ranks, I, tol=1e-6, storage="bf16")
+    assert low.status == 0 and low.err <= 1e-6
+    for a, b in zip(low.XB, full.XB):
+        assert np.array_equal(a, b)
+    k1 = next(k for k, e in enumerate(low.err_hist) if e <= 1e-2)
+    assert k1 + 1 < low.iters
+    # both recover the same low-rank part (a separating instance)
+    Ls = inst.L_star
+    for r in (low, full):
+        assert np.linalg.norm(r.reconstruct() - Ls) <= 1e-3 * np.linalg.norm(Ls)
+    # stopping inside the bfloat16 phase: every C block is bfloat16-exact
+    from oracle.tensor import round_bf16
+    early = rtcur(inst.X, inst.ranks, I, tol=0.5, storage="bf16")
+    for c in early.CB:
+        assert np.array_equal(round_bf16(c), c)
