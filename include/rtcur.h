@@ -115,6 +115,26 @@ int rtcur_solve(rtcur_t h, const void* X, int x_dtype, int32_t n,
  * RTCUR_E_STATE if no successful solve precedes it. */
 int rtcur_reconstruct(rtcur_t h, void* L_out, int out_dtype);
 
+/* Allocation-free variant of rtcur_reconstruct, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  It writes the same L into L_out (same
+ * kernels, same values bit for bit) but keeps its temporaries (the Tucker
+ * expansion over the full mode-0 unfolding, RP x prod_{j>0} dims[j] entries
+ * of the compute type, RP = max r_i padded to 4, 8 or 16, plus its work list)
+ * in a static device array of 64 MiB that each GPU holds once for the
+ * process, and calls no hipMalloc, hipFree, memset or host-to-device copy:
+ * every step is a kernel launch on the handle's stream.  It does not wait for
+ * the device: L_out is ready once the handle's stream has reached this point
+ * (synchronize that stream, or order later work after it).
+ *   L_out      caller's device buffer, prod(dims) elements of out_dtype
+ *              (RTCUR_F64/F32), C-contiguous; written by the queued kernels
+ * RTCUR_E_INVAL (nothing queued) when the temporaries exceed 64 MiB;
+ * RTCUR_E_STATE if no successful solve precedes it.  All calls on one GPU
+ * share that GPU's array, which keeps the last call's contents: calls that
+ * overlap on one GPU (on different streams or from different threads) race
+ * and must be ordered by the caller. */
+int rtcur_reconstruct_noalloc(rtcur_t h, void* L_out, int out_dtype);
+
 /* Full-grid outliers (the S-update of equation 11, S = HT_zeta(X - L) with
  * the strict threshold of equation 10, applied to every entry of X rather
  * than only to the sampled blocks), fused with the reconstruction of L:

@@ -9,6 +9,7 @@ mirror the C ABI in include/rtcur.h:
     solve(handle, X, ranks, I_sizes=None, J_sizes=None, ...) -> Info
     solve_batch(handles, Xs, ranks, I_sizes=None, ...) -> (infos, Ls)
     reconstruct(handle, out=None, dtype=None) -> torch.Tensor
+    reconstruct_noalloc(handle, out) -> out   (static device scratch only)
     outliers(handle, X, zeta=None, with_L=False) -> S or (S, L)
     destroy(handle)
     get_indices / get_history / get_block / get_tucker / sample
@@ -42,7 +43,8 @@ SYMBOLS = ["rtcur_create", "rtcur_solve", "rtcur_reconstruct", "rtcur_outliers",
            "rtcur_destroy",
            "rtcur_get_indices", "rtcur_get_history", "rtcur_get_block",
            "rtcur_get_tucker", "rtcur_sample", "rtcur_set_profiling",
-           "rtcur_get_profile", "rtcur_strerror", "rtcur_last_error", "rtcur_solve_batch"]
+           "rtcur_get_profile", "rtcur_strerror", "rtcur_last_error", "rtcur_solve_batch",
+           "rtcur_reconstruct_noalloc"]
 
 
 class RtcurInfo(ctypes.Structure):
@@ -83,6 +85,7 @@ def lib() -> ctypes.CDLL:
                               ctypes.POINTER(ctypes.c_int32), p64, p64, dbl, dbl,
                               dbl, i32, u64, ctypes.POINTER(RtcurInfo)]
     L.rtcur_reconstruct.argtypes = [vp, vp, ctypes.c_int]
+    L.rtcur_reconstruct_noalloc.argtypes = [vp, vp, ctypes.c_int]
     L.rtcur_solve_batch.argtypes = [ctypes.POINTER(vp), i32, i32, ctypes.POINTER(vp),
                                     ctypes.c_int, ctypes.POINTER(ctypes.c_int32), p64,
                                     ctypes.POINTER(ctypes.c_int32), p64, p64, pd, dbl, dbl,
@@ -371,6 +374,29 @@ def reconstruct(h: Handle, out=None, dtype=None):
                                  F64 if out.dtype == torch.float64 else F32)
     if rc != OK:
         raise RTCURError(rc, f"rtcur_reconstruct: {strerror(rc)}: {h.last_error()}")
+    return out
+
+
+def reconstruct_noalloc(h: Handle, out):
+    """rtcur_reconstruct_noalloc: the full L into the caller's `out` with the
+    library's static device scratch (no device allocation in the library);
+    queued on the handle's stream, which torch's current stream is then made
+    to wait for."""
+    torch = _torch()
+    if not isinstance(out, torch.Tensor) or not out.is_cuda or not out.is_contiguous():
+        raise TypeError("out must be a C-contiguous device tensor")
+    if out.dtype not in (torch.float32, torch.float64):
+        raise TypeError("out must be float32 or float64")
+    if list(out.shape) != list(h.dims):
+        raise ValueError(f"out has shape {tuple(out.shape)}, the solve had {tuple(h.dims)}")
+    _order(h)
+    rc = lib().rtcur_reconstruct_noalloc(h.ptr, ctypes.c_void_p(out.data_ptr()),
+                                         F64 if out.dtype == torch.float64 else F32)
+    if rc != OK:
+        raise RTCURError(rc, f"rtcur_reconstruct_noalloc: {strerror(rc)}: {h.last_error()}")
+    cur = torch.cuda.current_stream(h.device)
+    if h.stream is not None and h.stream.cuda_stream != cur.cuda_stream:
+        cur.wait_stream(h.stream)
     return out
 
 

@@ -93,6 +93,8 @@ int rtcur_create(rtcur_t* out, int device, void* hip_stream, int variant, int co
     if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return RTCUR_E_HIP;
     if (device < 0 || device >= count) return RTCUR_E_INVAL;
     if (hipSetDevice(device) != hipSuccess) return RTCUR_E_HIP;
+    // the device's static scratch (rtcur_reconstruct_noalloc), looked up once
+    if (rtcur::static_scratch_init(device) != RTCUR_OK) return RTCUR_E_HIP;
     rtcur_t h = new (std::nothrow) rtcur_s();
     if (!h) return RTCUR_E_NOMEM;
     h->device = device;
@@ -139,6 +141,18 @@ int rtcur_reconstruct(rtcur_t h, void* L_out, int out_dtype) {
     if (out_dtype != RTCUR_F64 && out_dtype != RTCUR_F32)
         return fail(h, RTCUR_E_INVAL, "out_dtype must be RTCUR_F64 or RTCUR_F32");
     return rtcur::reconstruct(h, L_out, out_dtype);
+}
+
+int rtcur_reconstruct_noalloc(rtcur_t h, void* L_out, int out_dtype) {
+    if (!h) return RTCUR_E_INVAL;
+    if (!L_out) return fail(h, RTCUR_E_INVAL, "L_out is null");
+    if (out_dtype != RTCUR_F64 && out_dtype != RTCUR_F32)
+        return fail(h, RTCUR_E_INVAL, "out_dtype must be RTCUR_F64 or RTCUR_F32");
+    try {
+        return rtcur::reconstruct_noalloc(h, L_out, out_dtype);
+    } catch (...) {
+        return fail(h, RTCUR_E_STATE, "internal error");
+    }
 }
 
 int rtcur_outliers(rtcur_t h, const void* X, int x_dtype, double zeta, void* S_out,

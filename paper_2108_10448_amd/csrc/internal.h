@@ -151,6 +151,11 @@ int get_block(rtcur_s* h, int block, int what, double* out, int64_t cap,
               int64_t* len);
 int get_tucker(rtcur_s* h, double* core, double* const* B);
 void release(rtcur_s* h);
+// bytes of the per-device static scratch of the allocation-free entry point
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+// looks up (once per device, `device` current) the static scratch's address
+int static_scratch_init(int device);
+int reconstruct_noalloc(rtcur_s* h, void* out, int out_dtype);
 constexpr int kProfKinds = 10;
 extern const char* const kProfNames[kProfKinds];
 }  // namespace rtcur

@@ -2545,6 +2545,23 @@ __global__ void k_unpack_mask(const uint64_t* __restrict__ mask, int64_t moff, i
     out[e] = ((wd >> (c & 63)) & 1ull) ? 1.0 : 0.0;
 }
 
+// out[0..N) = 0 (a fill kernel rather than a memset: safe inside a captured
+// graph)
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_fill_zero(T* __restrict__ out, int64_t N) {
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < N; e += stride)
+        out[e] = T(0);
+}
+
+// The work list of an H expansion over the full mode-0 unfolding: tile q
+// covers columns [256 q, 256 q + 256) (block id -1: dense).
+__global__ __launch_bounds__(kThreads) void k_dense_tiles(int2* __restrict__ tiles,
+                                                          int64_t ntile) {
+    const int64_t q = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (q < ntile) tiles[q] = make_int2(-1, (int)q);
+}
+
 template <typename T>
 __global__ void k_to_double(const T* __restrict__ in, int64_t N, double* __restrict__ out) {
     const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;

@@ -24,6 +24,8 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <string>
+#include <mutex>
 #include <vector>
 
 #include "internal.h"
@@ -68,6 +70,35 @@ const char* const kProfNames[kProfKinds] = {"absmax", "gather", "ht",   "gram", 
 struct ProfRec {
     int kind, iter, a, b;  // a, b: indices into the event pool
 };
+
+// Device scratch of the allocation-free entry point (rtcur_reconstruct_noalloc):
+// one static array in the code object, of which every GPU that loads the
+// library holds its own copy, at its own address, until the process ends.
+// In host code `scratch` names a host-side stand-in, not device memory:
+// kernels and copies only ever get the address that hipGetSymbolAddress
+// returned for the current device (scratch_dev below).
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+void* scratch_dev[kMaxDevices] = {};
+}  // namespace
+
+int static_scratch_init(int device) {
+    if (device < 0 || device >= kMaxDevices) return RTCUR_E_INVAL;
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    if (scratch_dev[device]) return RTCUR_OK;
+    void* p = nullptr;
+    // the caller made `device` current
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+        (void)hipGetLastError();
+        return RTCUR_E_HIP;
+    }
+    scratch_dev[device] = p;
+    return RTCUR_OK;
+}
 
 // Solver-private state kept in the handle between calls.
 struct Impl {
@@ -1233,6 +1264,80 @@ int reconstruct(rtcur_s* h, void* out, int out_dtype) {
     HIPCHK(hipSetDevice(h->device));
     if (h->dtype == RTCUR_F64) return recon_rp<double>(h, *im, out, out_dtype);
     return recon_rp<float>(h, *im, out, out_dtype);
+}
+
+// The allocation-free reconstruction: the dense H and its tile list in the
+// device's static scratch (no hipMalloc, no host-to-device copy, no memset:
+// every step is a kernel launch on the handle's stream), queued without
+// waiting for the device.
+template <typename T, typename TO, int RP>
+static int recon_static_t(rtcur_s* h, Impl& im, void* out, char* base) {
+    const Prob& P = im.P;
+    int64_t ncols = 1;
+    for (int j = 1; j < P.n; ++j) ncols *= P.d[j];
+    const int64_t total = ncols * P.d[0];
+    if (im.final_iter == 0) {
+        const unsigned nwg = (unsigned)std::min<int64_t>(4096, (total + kThreads - 1) / kThreads);
+        hipLaunchKernelGGL((k_fill_zero<TO>), dim3(std::max(1u, nwg)), dim3(kThreads), 0,
+                           h->stream, (TO*)out, total);
+        HIPCHK(hipGetLastError());
+        return 0;
+    }
+    const int64_t ntile = (ncols + kThreads - 1) / kThreads;
+    const size_t hbytes = align_up(sizeof(T) * RP * (size_t)ncols, 256);
+    const size_t need = hbytes + sizeof(int2) * (size_t)ntile;
+    if (need > kStaticScratchBytes) {
+        h->last_error = "reconstruction needs " + std::to_string(need) +
+                        " bytes of scratch; the static scratch holds " +
+                        std::to_string(kStaticScratchBytes);
+        return RTCUR_E_INVAL;
+    }
+    T* Hf = reinterpret_cast<T*>(base);
+    int2* tiles = reinterpret_cast<int2*>(base + hbytes);
+    hipLaunchKernelGGL(k_dense_tiles, dim3((unsigned)((ntile + kThreads - 1) / kThreads)),
+                       dim3(kThreads), 0, h->stream, tiles, ntile);
+    HIPCHK(hipGetLastError());
+    launch_hexp<T, RP>(P, true, (unsigned)ntile, h->stream, tiles, (const T*)im.Bf, im.Gd, Hf,
+                       (const DevState*)nullptr, 0, ncols);
+    HIPCHK(hipGetLastError());
+    dim3 grid((unsigned)ntile, (unsigned)((P.d[0] + kTileRows - 1) / kTileRows));
+    hipLaunchKernelGGL((k_recon<T, TO, RP>), grid, dim3(kThreads), 0, h->stream, P.d[0],
+                       ncols, (const T*)im.Bf + P.boff[0], (const T*)Hf, (TO*)out);
+    HIPCHK(hipGetLastError());
+    return 0;
+}
+
+template <typename T>
+static int recon_static_rp(rtcur_s* h, Impl& im, void* out, int odt, char* base) {
+    switch (im.P.rp) {
+        case 4: return odt == RTCUR_F64 ? recon_static_t<T, double, 4>(h, im, out, base)
+                                        : recon_static_t<T, float, 4>(h, im, out, base);
+        case 8: return odt == RTCUR_F64 ? recon_static_t<T, double, 8>(h, im, out, base)
+                                        : recon_static_t<T, float, 8>(h, im, out, base);
+        default: return odt == RTCUR_F64 ? recon_static_t<T, double, 16>(h, im, out, base)
+                                         : recon_static_t<T, float, 16>(h, im, out, base);
+    }
+}
+
+int reconstruct_noalloc(rtcur_s* h, void* out, int out_dtype) {
+    Impl* im = static_cast<Impl*>(h->impl);
+    if (!h->have_result || !im) {
+        h->last_error = "no successful solve to reconstruct";
+        return RTCUR_E_STATE;
+    }
+    void* base = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(scratch_mu);
+        if (h->device >= 0 && h->device < kMaxDevices) base = scratch_dev[h->device];
+    }
+    if (!base) {
+        h->last_error = "static scratch address of this device unknown";
+        return RTCUR_E_STATE;
+    }
+    HIPCHK(hipSetDevice(h->device));
+    char* b = static_cast<char*>(base);
+    if (h->dtype == RTCUR_F64) return recon_static_rp<double>(h, *im, out, out_dtype, b);
+    return recon_static_rp<float>(h, *im, out, out_dtype, b);
 }
 
 template <typename T, int RP>
