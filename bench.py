@@ -9,15 +9,21 @@ Algorithm 1 until the stopping rule holds) with X already resident in HBM.
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-cpu]
 
-Prints one JSON line.  The primary row is RTCUR-F with float32 blocks and
-factors (float64 Gram, eigensolver and norms); RTCUR-F in float64 and
-RTCUR-R are reported alongside.  Inside the timed region the library records
-a pair of HIP events on its own stream around every kernel launch; the
-per-kernel averages give `kernels` and the `roofline` of the kernel with the
-largest share of the solve.  `cpu_baseline` times the float64 oracle on the
-same instance on the host cores.  `--copy-calib` adds a plain device copy of
-known size after the timed region (the reference dispatch for the HBM
-traffic counters).
+Prints one JSON line.  The primary row (`value`, `ms_per_step`) is RTCUR-F
+with float32 blocks and factors (float64 Gram, eigensolver and norms), timed
+with no per-kernel events.  The float64 and bfloat16-then-float32 arms run
+the same number of timed solves; each arm then runs a second timed region
+with a pair of HIP events, recorded by the library on its own stream, around
+every launch of its dominant kernel only (chosen from a short pass with every
+kernel bracketed): that kernel's average launch time gives the arm's
+`roofline`.  `kernels_rocprof` is the per-kernel table of the committed
+rocprofv3 summary when it was taken on the current kernel sources.  Side
+rows: the 100^3 float64 workload, RTCUR-R, the video-shaped 4-mode workload,
+full-grid outliers and the 64-instance batch.  `cpu_baseline` times the
+float64 oracle on the same 300^3 instance on the host: complete solves with
+the BLAS on every core, and a bounded run on one thread.  `--copy-calib` adds
+a plain device copy of known size after the timed region (the reference
+dispatch for the HBM traffic counters).
 """
 
 from __future__ import annotations
@@ -217,6 +223,57 @@ def summarize_counters(fetch_dir, write_dir, cmds):
     return "\n".join(lines) + "\n"
 
 
+def read_rocprof_table(digest):
+    """{kernel: {calls, avg_us, share}} from the committed rocprofv3 kernel
+    trace summary of this workload, when it was taken on the current kernel
+    sources; else None."""
+    path = os.path.join(ROOT, "profiles", "kernels_cube300_f32.txt")
+    try:
+        lines = open(path).read().splitlines()
+    except OSError:
+        return None
+    meta = {l.split(":", 1)[0].strip("# ").strip(): l.split(":", 1)[1].strip()
+            for l in lines if l.startswith("#") and ":" in l}
+    if meta.get("source_digest") != digest:
+        return None
+    out = {}
+    for l in lines:
+        if l.startswith("#") or not l.strip():
+            continue
+        parts = l.split()
+        if len(parts) >= 5 and parts[-1].endswith("%"):
+            try:
+                calls, avg = int(parts[-4]), float(parts[-2])
+            except ValueError:
+                continue
+            out[" ".join(parts[:-4])] = {"calls": calls, "avg_us": avg,
+                                         "share": float(parts[-1].rstrip("%")) / 100.0}
+    return out or None
+
+
+def cpu_info():
+    """Host description for the CPU baseline: core count, CPU model and the
+    BLAS libraries numpy uses with their thread counts."""
+    import numpy  # noqa: F401  (loads the BLAS that threadpoolctl reports)
+    info = {"nproc": os.cpu_count()}
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    info["cpu_model"] = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        from threadpoolctl import threadpool_info
+        info["blas"] = [{"api": p.get("internal_api"), "threads": p.get("num_threads"),
+                         "lib": os.path.basename(p.get("filepath", ""))}
+                        for p in threadpool_info()]
+    except Exception:
+        info["blas"] = []
+    return info
+
+
 def main():
     if len(sys.argv) > 1 and sys.argv[1] in ("--summarize-trace", "--summarize-counters"):
         # host-side: turn rocprofv3 output into the text summaries under profiles/
@@ -237,9 +294,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
-                    help="minimum host time spent on the oracle baseline")
+                    help="minimum host time spent on the all-core oracle baseline")
     ap.add_argument("--side-steps", type=int, default=5,
-                    help="timed solves for the float64 and RTCUR-R rows (0: skip them)")
+                    help="timed solves for the side rows (0: skip them)")
+    ap.add_argument("--no-arms", action="store_true",
+                    help="skip the float64 and bfloat16 arms")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 64-instance batch side row")
     ap.add_argument("--no-video", action="store_true",
@@ -270,37 +329,75 @@ def main():
     ranks = list(inst.ranks)
     I, _ = synth.sample_sizes(inst.dims, ranks, cfg["upsilon"])
     X = torch.from_numpy(inst.X).to("cuda:0")          # float32, resident in HBM
-    torch.cuda.synchronize()
-
-    # ---- primary: RTCUR-F, float32 compute
-    h = rt.create(0, variant="F", dtype=torch.float32)
-    for _ in range(args.warmup):
-        rt.solve(h, X, ranks, I, tol=1e-5, gamma=0.7, max_iter=100, seed=0)
-    # every kernel timed (events around each launch) over a few solves: the
-    # per-kernel breakdown, and which kernel takes the largest share
-    nprof = 3
-    rt.set_profiling(h, True)
-    pinfos, _ = time_solves(rt, torch, h, X, ranks, I, nprof, 0)
-    prof_all = rt.get_profile(h)
-    rt.set_profiling(h, False)
-    dom = max((k for k in prof_all if prof_all[k][1]), key=lambda k: prof_all[k][0])
-    # timed region: events around the dominant kernel's launches only
-    rt.set_profiling(h, True, kinds=[dom])
-    log(f"timing RTCUR-F f32: {args.steps} solves (events around {dom})")
-    infos, times = time_solves(rt, torch, h, X, ranks, I, args.steps, 0)
-    prof_dom = rt.get_profile(h)[dom]
-    rt.set_profiling(h, False)
-    iters = [i.iters for i in infos]
-    total_t = sum(times)
-    value = sum(iters) / total_t
-    K = iters[-1]
-    Lrec = rt.reconstruct(h, dtype=torch.float32)
     Ls = torch.from_numpy(inst.L_star).to("cuda:0")
-    true_err = float(torch.linalg.norm(Lrec.double() - Ls) / torch.linalg.norm(Ls))
-    del Lrec, Ls
+    torch.cuda.synchronize()
+    digest = source_digest()
+
+    def roofline_of(h, dtype, name, steps):
+        """Dominant kernel (every kernel bracketed over 3 solves), then a
+        timed region of `steps` solves with events around its launches only."""
+        nprof = 3
+        rt.set_profiling(h, True)
+        pinfos, _ = time_solves(rt, torch, h, X, ranks, I, nprof, 0)
+        prof_all = rt.get_profile(h)
+        rt.set_profiling(h, False)
+        dom = max((k for k in prof_all if prof_all[k][1]), key=lambda k: prof_all[k][0])
+        rt.set_profiling(h, True, kinds=[dom])
+        log(f"{name}: {steps} solves with events around {dom}")
+        infos, times = time_solves(rt, torch, h, X, ranks, I, steps, 0)
+        ms, cnt = rt.get_profile(h)[dom]
+        rt.set_profiling(h, False)
+        K = infos[-1].iters
+        eig_steps = sum(i.eig_steps for i in infos) / len(infos)
+        b = 8 if dtype == torch.float64 else (4 if dtype == torch.float32 else 2)
+        work = work_per_solve(list(inst.dims), I, ranks, b, K, eig_steps)
+        launches = cnt / len(infos)
+        t = 1e-3 * ms / cnt
+        out = {"kernel": dom, "avg_launch_us": 1e6 * t, "launches_per_solve": launches,
+               "timed_ms_per_step": 1e3 * sum(times) / len(times), "source_digest": digest}
+        if dom in work:
+            bound, w = work[dom]
+            wl = w / launches
+            if bound == "hbm":
+                ach, unit, peak = wl / t / 1e9, "GB/s", HBM_PEAK_GBS
+            else:
+                ach, unit, peak = wl / t / 1e12, "TFLOP/s", FP64_PEAK_TFLOPS
+            out.update(bound=bound, achieved=ach, peak=peak, unit=unit, frac=ach / peak,
+                       work_per_launch=wl)
+            if b == 2 and bound == "hbm":
+                out["bytes_per_element_assumed"] = 2   # bfloat16 phase: a lower bound
+        out["traffic"] = read_traffic(dom, digest) if dtype == torch.float32 else None
+        return out
+
+    def arm(dtype, name, steps, warmup, with_roofline=True):
+        h = rt.create(0, variant="F", dtype=dtype)
+        for _ in range(warmup):
+            rt.solve(h, X, ranks, I, tol=1e-5, gamma=0.7, max_iter=100, seed=0)
+        log(f"timing RTCUR-F {name}: {steps} solves, no events")
+        infos, times = time_solves(rt, torch, h, X, ranks, I, steps, 0)
+        Lr = rt.reconstruct(h)
+        terr = float(torch.linalg.norm(Lr.double() - Ls) / torch.linalg.norm(Ls))
+        del Lr
+        row = {"iters_per_s": sum(i.iters for i in infos) / sum(times),
+               "ms_per_step": 1e3 * sum(times) / len(times),
+               "time_to_tol_ms": {"p50": 1e3 * percentile(times, 0.5),
+                                  "p10": 1e3 * percentile(times, 0.1),
+                                  "p90": 1e3 * percentile(times, 0.9)},
+               "iters": infos[-1].iters, "err": infos[-1].err, "true_rel_err": terr,
+               "eig_steps_per_solve": sum(i.eig_steps for i in infos) / len(infos),
+               "eig_unconverged": max(i.eig_unconverged for i in infos),
+               "converged": all(i.converged for i in infos)}
+        if with_roofline:
+            row["roofline"] = roofline_of(h, dtype, name, steps)
+        return h, row
+
+    # ---- primary: RTCUR-F, float32 blocks (float64 Gram, eigensolver, norms)
+    h, prim = arm(torch.float32, "f32", args.steps, args.warmup)
+    assert prim["eig_unconverged"] == 0 and prim["converged"], prim
+    log(f"f32: {prim}")
 
     # full-grid outliers fused with the reconstruction (one read of X, one
-    # write of S): time a few calls after the solve
+    # write of S): a few calls after the solve
     rt.outliers(h, X)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -316,30 +413,47 @@ def main():
                    "support_recall": float((found & planted).sum() / planted.sum()),
                    "support_precision": float((found & planted).sum() / max(1, int(found.sum())))}
     del S, planted, found
+    rt.destroy(h)
     log(f"outliers: {outlier_row}")
+
+    # ---- the other precisions of the metric: float64, bfloat16 + float32 sweep
+    arms = {}
+    if not args.no_arms:
+        for dt, name in ((torch.float64, "f64"), (torch.bfloat16, "bf16_then_f32")):
+            hh, row = arm(dt, name, args.steps, 1)
+            rt.destroy(hh)
+            arms[name] = row
+            log(f"{name}: {row}")
 
     rows = {}
 
-    def side(variant, dtype, name):
+    def side(variant, dtype, name, Xs=None, inst_=None, I_=None):
+        Xs = X if Xs is None else Xs
+        inst_ = inst if inst_ is None else inst_
+        I_ = I if I_ is None else I_
         hh = rt.create(0, variant=variant, dtype=dtype)
-        inf, ts = time_solves(rt, torch, hh, X, ranks, I, args.side_steps, 1)
+        inf, ts = time_solves(rt, torch, hh, Xs, list(inst_.ranks), I_, args.side_steps, 1)
         Lr = rt.reconstruct(hh)
-        Ls_ = torch.from_numpy(inst.L_star).to("cuda:0")
+        Ls_ = torch.from_numpy(inst_.L_star).to("cuda:0")
         terr = float(torch.linalg.norm(Lr.double() - Ls_) / torch.linalg.norm(Ls_))
         del Lr, Ls_
         rows[name] = {"time_to_tol_ms_p50": 1e3 * percentile(ts, 0.5),
                       "iters": inf[-1].iters, "err": inf[-1].err,
                       "iters_per_s": sum(i.iters for i in inf) / sum(ts),
-                      "true_rel_err": terr}
+                      "true_rel_err": terr, "eig_unconverged": inf[-1].eig_unconverged}
         rt.destroy(hh)
         log(f"{name}: {rows[name]}")
 
     if args.side_steps > 0:
-        side("F", torch.float32, "F_f32_no_events")
-        side("F", torch.bfloat16, "F_bf16_then_f32")
-        side("F", torch.float64, "F_f64")
         side("R", torch.float32, "R_f32")
         side("R", torch.float64, "R_f64")
+        # the 100^3 float64 workload (rank 3, alpha 0.2, |I_i| = 42)
+        c0 = synth.config_instance("cube100_r3")
+        I0, _ = synth.sample_sizes(c0.dims, c0.ranks, synth.CONFIGS["cube100_r3"]["upsilon"])
+        X0 = torch.from_numpy(c0.X).to("cuda:0")
+        side("F", torch.float64, "cube100_F_f64", X0, c0, I0)
+        side("R", torch.float64, "cube100_R_f64", X0, c0, I0)
+        del X0
 
     # ---- the video-shaped 4-mode workload (height x width x colour x frame)
     video = None
@@ -425,38 +539,6 @@ def main():
         torch.cuda.empty_cache()
         log(f"batch: {batch}")
 
-    # ---- per-kernel figures
-    def figures(name, ms, cnt, nsolve, eig_steps):
-        work = work_per_solve(list(inst.dims), I, ranks, 4, K, eig_steps)
-        per = {"total_ms_per_solve": ms / nsolve, "launches_per_solve": cnt / nsolve,
-               "avg_us": 1e3 * ms / cnt}
-        if name in work:
-            bound, w = work[name]
-            w_launch = w / (cnt / nsolve)
-            t = 1e-3 * ms / cnt
-            if bound == "hbm":
-                ach, unit, peak = w_launch / t / 1e9, "GB/s", HBM_PEAK_GBS
-            else:
-                ach, unit, peak = w_launch / t / 1e12, "TFLOP/s", FP64_PEAK_TFLOPS
-            per.update(bound=bound, work_per_launch=w_launch, achieved=ach, unit=unit,
-                       peak=peak, frac=ach / peak)
-        return per
-
-    kernels = {}
-    pe_steps = sum(i.eig_steps for i in pinfos) / nprof
-    for name, (ms, cnt) in prof_all.items():
-        if cnt:
-            kernels[name] = figures(name, ms, cnt, nprof, pe_steps)
-    eig_steps = sum(i.eig_steps for i in infos) / len(infos)
-    kk = figures(dom, prof_dom[0], prof_dom[1], len(infos), eig_steps)
-    digest = source_digest()
-    roofline = {"kernel": dom, "bound": kk.get("bound"), "achieved": kk.get("achieved"),
-                "peak": kk.get("peak"), "unit": kk.get("unit"), "frac": kk.get("frac"),
-                "traffic": read_traffic(dom, digest),
-                "work_per_launch": kk.get("work_per_launch"), "avg_launch_us": kk["avg_us"],
-                "launches_per_solve": kk["launches_per_solve"], "source_digest": digest}
-    log(f"kernels: {json.dumps(kernels)}")
-
     if args.copy_calib:
         n = COPY_CALIB_BYTES // 4
         a = torch.ones(n, dtype=torch.float32, device="cuda:0")
@@ -471,11 +553,8 @@ def main():
     cpu = None
     if not args.no_cpu:
         from oracle import rtcur as oracle_rtcur
-        try:
-            from threadpoolctl import threadpool_info
-            threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
-        except Exception:
-            threads = os.cpu_count() or 1
+        hw = cpu_info()
+        threads = max([b.get("threads") or 1 for b in hw.get("blas", [])] or [1])
         Xh = inst.X
         runs, t_all, it_all = 0, 0.0, 0
         while t_all < args.cpu_seconds and runs < 3:
@@ -485,19 +564,33 @@ def main():
             it_all += res.iters
             runs += 1
             log(f"oracle solve {runs}: {res.iters} iterations, {t_all:.1f} s so far")
+        one = None
+        try:
+            from threadpoolctl import threadpool_limits
+            k1 = 4
+            with threadpool_limits(limits=1):
+                t0 = time.perf_counter()
+                oracle_rtcur(Xh, ranks, I, None, None, 0.7, 0.0, k1, 0, "F")
+                t1 = time.perf_counter() - t0
+            one = {"value": k1 / t1, "unit": "iters/s", "threads": 1,
+                   "sample": f"{k1} iterations of the same solve (tol 0), {t1:.1f} s"}
+            log(f"oracle on one thread: {one}")
+        except Exception as e:  # threadpoolctl missing: report without it
+            log(f"one-thread oracle run skipped: {e}")
         cpu = {"value": it_all / t_all, "unit": "iters/s", "cores": threads, "kind": "oracle",
                "sample": (f"{runs} complete float64 oracle RTCUR-F solves of the same "
                           f"300^3 instance to tol 1e-5 ({res.iters} iterations each), "
-                          f"{t_all:.1f} s in total; time to tol {1e3 * t_all / runs:.0f} ms")}
+                          f"{t_all:.1f} s in total; time to tol {1e3 * t_all / runs:.0f} ms"),
+               "host": hw, "one_thread": one}
 
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": prim["iters_per_s"],
         "unit": "iters/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * total_t / len(times),
+        "ms_per_step": prim["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -509,20 +602,19 @@ def main():
                    "dims": list(inst.dims), "ranks": ranks, "alpha": cfg["alpha"],
                    "I_sizes": I, "variant": "F", "compute": "f32 blocks and factors; "
                    "f64 Gram, eigensolver, stopping-rule norms"},
-        "time_to_tol_ms": {"p50": 1e3 * percentile(times, 0.5),
-                           "p10": 1e3 * percentile(times, 0.1),
-                           "p90": 1e3 * percentile(times, 0.9)},
-        "iters": K,
-        "err": infos[-1].err,
-        "true_rel_err": true_err,
-        "eig_steps_per_solve": eig_steps,
+        "time_to_tol_ms": prim["time_to_tol_ms"],
+        "iters": prim["iters"],
+        "err": prim["err"],
+        "true_rel_err": prim["true_rel_err"],
+        "eig_steps_per_solve": prim["eig_steps_per_solve"],
+        "roofline": prim["roofline"],
+        "arms": arms,
         "variants": rows,
         "outliers_full_grid": outlier_row,
         "video": video,
         "batch": batch,
-        "roofline": roofline,
         "cpu_baseline": cpu,
-        "kernels": kernels,
+        "kernels_rocprof": read_rocprof_table(digest),
     }
     print(json.dumps(out), flush=True)
 

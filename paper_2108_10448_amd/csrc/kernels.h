@@ -614,6 +614,7 @@ struct EigShared {
     double red[4];
     int jp[RP], ord[RP];                   // rotation partners; decreasing order
     int gsteps;                            // steps of the guarded iteration
+    int stopf;                             // the stop flag at entry
     int ok;
     int cok;                               // RP = 16: the factor's pivots were positive
     double part[4][256];                   // per-wave 16 x 16 MFMA partials
@@ -1190,8 +1191,11 @@ __device__ __forceinline__ void eig_gq_tm(const double* G, int sp, int s, EigSha
 }
 
 // W_i = Q and Y_i = Q T^-1 with T = R^T R (Cholesky of the symmetrised T,
-// in sh.mm), the rank test on T, and the step counts; RP <= 8: R and R^-1 in
-// the registers of every thread.
+// in sh.mm), the rank test on T, and the step counts; RP <= 8: R in the
+// registers of every thread, y = (q R^-1) R^-T by two triangular solves.
+// The rank test's ||T^-1||_F is formed by wave 0: lane t < RP solves for
+// column t of R^-1 (into sh.vv), then lane (p, t) forms entry (p, t) of
+// T^-1 = R^-1 R^-T.
 template <int RP>
 __device__ __forceinline__ void eig_finish_regs(const Prob& P, int i, int s, int r, int a, bool act,
                                                 const double (&q)[RP], bool conv, int steps,
@@ -1199,49 +1203,45 @@ __device__ __forceinline__ void eig_finish_regs(const Prob& P, int i, int s, int
                                                 DevState* st, EigShared<RP>& sh) {
     double R[RP][RP], di[RP];
     const bool tok = eig_chol<RP>(sh.mm, r, R, di);
-    // Rinv = R^-1 (upper triangular)
-    double Ri[RP][RP];
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        if (lane < RP) {
+            double x[RP];
 #pragma unroll
-    for (int j = 0; j < RP; ++j) {
+            for (int j = RP - 1; j >= 0; --j) {
+                double v = j == lane ? 1.0 : 0.0;
 #pragma unroll
-        for (int q = 0; q < RP; ++q) Ri[j][q] = 0.0;
-    }
+                for (int k = j + 1; k < RP; ++k) v -= R[j][k] * x[k];
+                x[j] = v * di[j];
+            }
 #pragma unroll
-    for (int j = RP - 1; j >= 0; --j) {
-        Ri[j][j] = di[j];
-#pragma unroll
-        for (int q = j + 1; q < RP; ++q) {
-            double v = 0.0;
-#pragma unroll
-            for (int k = j + 1; k <= q; ++k) v += R[j][k] * Ri[k][q];
-            Ri[j][q] = -v * di[j];
+            for (int j = 0; j < RP; ++j) sh.vv[j * RP + lane] = x[j];  // R^-1[j][lane]
         }
-    }
-    {
+        wave_sync();
         // rank test on ||T||_F >= lambda_1 and 1/||T^-1||_F <= lambda_r
         // (flag when lambda_r / lambda_1 may be <= 64 s 2^-52); the padded
         // rows and columns of T and R^-1 are masked out
         double tf = 0.0, tif = 0.0;
+        if (lane < RP * RP) {
+            const int p = lane / RP, t = lane % RP;
+            const bool in = p < r && t < r;
+            const double tv = in ? sh.mm[p * RP + t] : 0.0;
+            double v = 0.0;  // (R^-1 R^-T)[p][t]
 #pragma unroll
-        for (int p = 0; p < RP; ++p) {
-#pragma unroll
-            for (int t = 0; t < RP; ++t) {
-                const bool in = p < r && t < r;
-                const double tv = in ? sh.mm[p * RP + t] : 0.0;
-                double v = 0.0;  // (R^-1 R^-T)[p][t]
-#pragma unroll
-                for (int k = (p > t ? p : t); k < RP; ++k) v += Ri[p][k] * Ri[t][k];
-                tf += tv * tv;
-                tif += in ? v * v : 0.0;
-            }
+            for (int k = 0; k < RP; ++k)
+                v += (k >= p && k >= t) ? sh.vv[p * RP + k] * sh.vv[t * RP + k] : 0.0;
+            tf = tv * tv;
+            tif = in ? v * v : 0.0;
         }
+        tf = wave_sum(tf);
+        tif = wave_sum(tif);
         if (threadIdx.x == 0) {
             atomicAdd(&st->eig_steps, steps);
             if (!conv) atomicAdd(&st->eig_unconverged, 1);
             // 1 / (||T||_F ||T^-1||_F) <= lambda_r / lambda_1: the next call's
             // stopping scale
-            const double q = tf * tif;
-            st->eigest[i] = (q > 0.0 && isfinite(q)) ? 1.0 / sqrt(q) : 0.0;
+            const double qq = tf * tif;
+            st->eigest[i] = (qq > 0.0 && isfinite(qq)) ? 1.0 / sqrt(qq) : 0.0;
             if (!isfinite(tf) || !isfinite(tif)) {
                 st->stop = 1;
                 st->status = RTCUR_E_NONFINITE;
@@ -1252,23 +1252,21 @@ __device__ __forceinline__ void eig_finish_regs(const Prob& P, int i, int s, int
         }
     }
     if (act) {
-        // y = q T^-1 = (q R^-1) R^-T
-        double u[RP];
+        // y = q T^-1: u = q R^-1, then y R^T = u
+        double u[RP], y[RP];
+        eig_trsm<RP>(q, R, di, u);
 #pragma unroll
-        for (int p = 0; p < RP; ++p) {
-            double v = 0.0;
+        for (int p = RP - 1; p >= 0; --p) {
+            double v = u[p];
 #pragma unroll
-            for (int k = 0; k <= p; ++k) v += q[k] * Ri[k][p];
-            u[p] = v;
+            for (int k = p + 1; k < RP; ++k) v -= R[p][k] * y[k];
+            y[p] = v * di[p];
         }
         double* Yi = Y + P.woff[i];
 #pragma unroll
         for (int p = 0; p < RP; ++p) {
-            double v = 0.0;
-#pragma unroll
-            for (int k = p; k < RP; ++k) v += u[k] * Ri[p][k];
             Wi[a * RP + p] = p < r ? q[p] : 0.0;
-            Yi[a * RP + p] = p < r ? v : 0.0;
+            Yi[a * RP + p] = p < r ? y[p] : 0.0;
         }
     }
 }
@@ -1401,12 +1399,6 @@ __global__ __launch_bounds__(kThreads) void k_eig(Prob P, const double* __restri
     // takes the same branch: a sibling mode's workgroup of this launch may
     // raise the flag meanwhile
     const int sf0 = threadIdx.x == 0 ? stop_flag(st) : 0;
-    // Q and Z rows s..sp-1 stay zero for the padded products
-    for (int e = s * RP + threadIdx.x; e < sp * RP; e += kThreads) {
-        sh.qs[e] = 0.0;
-        sh.zs[e] = 0.0;
-    }
-    __syncthreads();
     {
         // the Gram from k_gram's per-chunk 16 x 16 tiles, chunks added in
         // order; every load of a thread is issued before the first use
@@ -1422,16 +1414,22 @@ __global__ __launch_bounds__(kThreads) void k_eig(Prob P, const double* __restri
         else
             gram_assemble<4, 16, true>(src0, total, nkc, G);
     }
-    if (threadIdx.x == 0) sh.ok = sf0;
+    // Q and Z rows s..sp-1 stay zero for the padded products (written after
+    // the assembly's loads were issued; the barrier below orders both)
+    for (int e = s * RP + threadIdx.x; e < sp * RP; e += kThreads) {
+        sh.qs[e] = 0.0;
+        sh.zs[e] = 0.0;
+    }
+    if (threadIdx.x == 0) {
+        sh.stopf = sf0;
+        sh.ok = 1;
+    }
     __syncthreads();
-    if (sh.ok) return;  // uniform: one value for the whole workgroup
-    __syncthreads();    // every thread has read sh.ok before it is reset
-    if (threadIdx.x == 0) sh.ok = 1;
+    if (sh.stopf) return;  // uniform: one value for the whole workgroup
     double q[RP], z[RP];
     if (warm == 1) {
 #pragma unroll
         for (int p = 0; p < RP; ++p) q[p] = (act && p < r) ? qw[p] : 0.0;
-        __syncthreads();
     } else {
         // start block G * Omega, then Cholesky-QR twice.  Omega: with
         // warm == 2 (a new sample under RTCUR-R) the previous mode-i factor's
