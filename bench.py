@@ -274,6 +274,80 @@ def cpu_info():
     return info
 
 
+def learned_schedule_row(rt, torch, np, synth, steps, ntrain, nsolve):
+    """Learn the 15 threshold multipliers c_k = zeta_k / zeta_0 of RTCUR-F
+    by gradient descent through the library's differentiable unrolled pass
+    (K = 15 iterations, gate temperature 0.05), on seeded instances of the
+    200^3 rank-5 alpha-0.3 recipe; the loss is the relative error of L^15
+    against the planted low-rank part on the sampled blocks.  Then solve
+    held-out instances to tol 1e-5 with the learned multipliers (the decay
+    by gamma = 0.7 continues after them) and with the geometric schedule,
+    and time both."""
+    from paper_2108_10448_amd.unrolled import UnrolledRTCUR
+    K, tau, gamma = 15, 0.05, 0.7
+    dims, ranks, alpha = (200, 200, 200), (5, 5, 5), 0.3
+    I, _ = synth.sample_sizes(dims, ranks, 3.0)
+    log(f"learned schedule: {ntrain} training instances, {steps} steps")
+    plan = rt.unroll_plan(dims, ranks, I, K=K, seed=0)
+    idx = plan.block_index()
+    data = []
+    for j in range(ntrain):
+        inst = synth.tucker_plus_sparse(dims, ranks, alpha, seed=1000 + j, storage=np.float32)
+        data.append((torch.from_numpy(inst.X), torch.from_numpy(inst.L_star.reshape(-1)[idx])))
+    theta = torch.tensor([(k + 1) * math.log(gamma) for k in range(K)], dtype=torch.float64,
+                         requires_grad=True)
+    opt = torch.optim.Adam([theta], lr=0.05)
+    losses = []
+    t0 = time.perf_counter()
+    for step in range(steps):
+        Xh, Lh = data[step % ntrain]
+        X = Xh.to("cuda:0")
+        Ls = Lh.to("cuda:0")
+        zeta0 = float(X.abs().max())
+        L = UnrolledRTCUR.apply(X, zeta0 * torch.exp(theta), plan, tau)
+        loss = ((L - Ls) ** 2).sum() / (Ls ** 2).sum()
+        opt.zero_grad()
+        loss.backward()
+        opt.step()
+        losses.append(float(loss.detach()))
+    t_train = time.perf_counter() - t0
+    plan.close()
+    mult = torch.exp(theta).detach().numpy()
+    geo = np.array([gamma ** (k + 1) for k in range(K)])
+    # held-out comparison on the real solver
+    rows = []
+    for j in range(2):
+        inst = synth.tucker_plus_sparse(dims, ranks, alpha, seed=5000 + j, storage=np.float32)
+        X = torch.from_numpy(inst.X).to("cuda:0")
+        Ls = torch.from_numpy(inst.L_star).to("cuda:0")
+        row = {}
+        for name, c in (("geometric", None), ("learned", mult)):
+            h = rt.create(0, variant="F", dtype=torch.float32)
+            rt.set_schedule(h, c)
+            inf, ts = time_solves(rt, torch, h, X, list(ranks), I, nsolve, 1)
+            Lr = rt.reconstruct(h)
+            row[name] = {"time_to_tol_ms_p50": 1e3 * percentile(ts, 0.5),
+                         "iters": inf[-1].iters, "converged": bool(inf[-1].converged),
+                         "true_rel_err": float(torch.linalg.norm(Lr.double() - Ls) /
+                                               torch.linalg.norm(Ls))}
+            rt.destroy(h)
+            del Lr
+        rows.append(row)
+        del X, Ls
+    out = {"workload": "200^3 float32 storage, rank (5,5,5), alpha 0.3, RTCUR-F, chidori "
+                       f"|I_i|={I[0]}, K=15 unrolled, gate tau={tau}; loss ||L^15 - L*||^2 / "
+                       "||L*||^2 on the sampled blocks",
+           "train_instances": ntrain, "steps": steps, "train_s": t_train,
+           "ms_per_step": 1e3 * t_train / max(1, steps),
+           "loss_first": losses[0] if losses else None,
+           "loss_last5_mean": float(np.mean(losses[-5:])) if losses else None,
+           "multipliers_learned": [float(v) for v in mult],
+           "multipliers_geometric": [float(v) for v in geo],
+           "held_out": rows}
+    log(f"learned schedule: {out}")
+    return out
+
+
 def main():
     if len(sys.argv) > 1 and sys.argv[1] in ("--summarize-trace", "--summarize-counters"):
         # host-side: turn rocprofv3 output into the text summaries under profiles/
@@ -305,6 +379,10 @@ def main():
                     help="skip the video-shaped 4-mode side rows")
     ap.add_argument("--copy-calib", action="store_true",
                     help="run a plain 1 GiB device copy after the timed region")
+    ap.add_argument("--learn-steps", type=int, default=60,
+                    help="Adam steps of the learned threshold schedule (0: skip the row)")
+    ap.add_argument("--learn-instances", type=int, default=16,
+                    help="seeded 200^3 training instances of the learned schedule")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: RTCUR's hot loop is measured on a "
@@ -539,6 +617,11 @@ def main():
         torch.cuda.empty_cache()
         log(f"batch: {batch}")
 
+    learned = None
+    if args.learn_steps > 0:
+        learned = learned_schedule_row(rt, torch, np, synth, args.learn_steps,
+                                       args.learn_instances, args.side_steps or 3)
+
     if args.copy_calib:
         n = COPY_CALIB_BYTES // 4
         a = torch.ones(n, dtype=torch.float32, device="cuda:0")
@@ -613,6 +696,7 @@ def main():
         "outliers_full_grid": outlier_row,
         "video": video,
         "batch": batch,
+        "learned_schedule": learned,
         "cpu_baseline": cpu,
         "kernels_rocprof": read_rocprof_table(digest),
     }

@@ -186,6 +186,16 @@ int rtcur_solve_batch(rtcur_t* hs, int32_t nh, int32_t count, const void* const*
                       const uint64_t* seeds, void* const* L_out, int out_dtype,
                       rtcur_info* infos, int32_t* status);
 
+/* Threshold schedule of the following solves on this handle (a learned
+ * alternative to equation 12's decay, Section 3.2): iteration k <= n
+ * thresholds with zeta_k = multipliers[k-1] * zeta_0, later iterations
+ * continue the decay from the last one, zeta_k = gamma zeta_(k-1) (repeated
+ * float64 multiplication).  n = 0 restores the geometric schedule
+ * zeta_k = gamma^k zeta_0 throughout.  The multipliers (host, n positive
+ * finite values) are copied; entries beyond a solve's max_iter are unused.
+ * RTCUR_E_INVAL for a negative n or a non-positive multiplier. */
+int rtcur_set_schedule(rtcur_t h, const double* multipliers, int32_t n);
+
 /* Release the handle and its device workspace.  NULL-safe. */
 int rtcur_destroy(rtcur_t h);
 
@@ -241,6 +251,48 @@ int rtcur_get_profile(rtcur_t h, int32_t kind, char* name, int32_t name_cap,
 
 const char* rtcur_strerror(int status);
 const char* rtcur_last_error(rtcur_t h);
+
+/* ---- differentiable unrolled RTCUR-F (float64, three modes) ----
+ *
+ * K iterations of Algorithm 1 on one fixed chidori sample (resample counter
+ * 0) with the thresholds zeta_1..zeta_K as inputs instead of the decay of
+ * equation 12, and the adjoint of those K iterations with respect to the
+ * thresholds and to X, for learning the threshold schedule (Section 3.2's
+ * zeta_k).  The threshold of equation 10 is the strict hard threshold when
+ * tau = 0 and the gate S = D sigmoid((|D| / zeta - 1) / tau) when tau > 0
+ * (the hard threshold has zero derivative in zeta almost everywhere; with
+ * tau > 0 the forward pass is the function whose derivative the backward
+ * pass returns).  The L-update is equation 8's literal form: A_i = C_i U_i^+
+ * with U_i^+ the pseudo-inverse of the rank-r_i truncation (from the
+ * eigendecomposition of U_i U_i^T), L = R x_i A_i on the sampled blocks.
+ * All arithmetic is float64.  Block buffers hold R (s_0 x s_1 x s_2, C
+ * order) then C_0, C_1, C_2 (d_i x m_i row-major), m_i = prod_{j!=i} s_j. */
+typedef struct rtcur_unroll_s* rtcur_unroll_t;
+
+/* Plan an unrolled pass: n = 3, r_i <= s_i <= min(d_i, 96), 1 <= K <= 1000;
+ * draws the sample from seed.  Allocates the device workspace, including K
+ * checkpoints of the factor form of L^k (R^k, A_i^k and the Grams'
+ * eigenpairs: O(K (s^3 + sum_i d_i s_i)) doubles, never K block buffers). */
+int rtcur_unroll_create(rtcur_unroll_t* out, int device, void* hip_stream, int32_t n,
+                        const int64_t* dims, const int32_t* ranks, const int64_t* I_sizes,
+                        int32_t K, uint64_t seed);
+/* Number of block entries (*n_blk) and, when idx_out is not NULL (cap >=
+ * n_blk), the offset in X of every block entry, in block-buffer order. */
+int rtcur_unroll_blocks(rtcur_unroll_t u, int64_t* n_blk, int64_t* idx_out, int64_t cap);
+/* Forward pass on the device tensor X (x_dtype RTCUR_F64 or RTCUR_F32, the
+ * planned dims): zetas (host, K positive values), tau >= 0; writes L^K on
+ * the blocks into L_out (device, n_blk doubles).  Blocks until done.
+ * RTCUR_E_RANK when some U_i met has sigma_r <= max(s_i, m_i) 2^-52 sigma_1. */
+int rtcur_unroll_forward(rtcur_unroll_t u, const void* X, int x_dtype, const double* zetas,
+                         double tau, double* L_out);
+/* Backward pass of the last forward: given L_bar = dloss / dL^K on the
+ * blocks (device, n_blk doubles), writes dloss / dzeta_k into zeta_bar (host,
+ * K) and dloss / dX into X_bar (device, prod(dims) doubles; zero off the
+ * sampled blocks).  RTCUR_E_STATE without a successful forward pass. */
+int rtcur_unroll_backward(rtcur_unroll_t u, const double* L_bar, double* zeta_bar,
+                          double* X_bar);
+int rtcur_unroll_destroy(rtcur_unroll_t u);  /* NULL-safe */
+const char* rtcur_unroll_last_error(rtcur_unroll_t u);
 
 #ifdef __cplusplus
 }

@@ -184,7 +184,8 @@ BF16_SWITCH = 1e-2
 def rtcur(X: np.ndarray, ranks: Sequence[int], I_sizes: Sequence[int],
           J_sizes: Optional[Sequence[int]] = None, zeta0: Optional[float] = None,
           gamma: float = 0.7, tol: float = 1e-5, max_iter: int = 100,
-          seed: int = 0, variant: str = "F", storage: str = "f64") -> Result:
+          seed: int = 0, variant: str = "F", storage: str = "f64",
+          schedule: Optional[Sequence[float]] = None) -> Result:
     """Robust Tensor CUR (Algorithm 1).  variant "F" keeps the first sample,
     "R" resamples before every iteration after the first (Section 3.4).
 
@@ -197,8 +198,16 @@ def rtcur(X: np.ndarray, ranks: Sequence[int], I_sizes: Sequence[int],
     the unrounded X, its denominator and unrounded C.  All arithmetic stays
     float64; the returned XB is the unrounded X.
 
+    schedule (multipliers c_1..c_n of zeta_0) replaces equation 12's decay
+    for the first n thresholds: zeta_k = zeta_0 c_k for k <= n, then
+    zeta_k = gamma zeta_(k-1) (repeated multiplication) beyond; None is the
+    geometric schedule zeta_k = gamma zeta_(k-1) throughout.
+
     Raises OracleError(E_INVAL / E_RANK / E_NONFINITE) on the error paths.
     """
+    if schedule is not None and (len(schedule) < 1 or
+                                 not all(math.isfinite(c) and c > 0 for c in schedule)):
+        raise OracleError(E_INVAL, "schedule multipliers must be positive and finite")
     if storage not in ("f64", "bf16") or (storage == "bf16" and variant != "F"):
         raise OracleError(E_INVAL, "storage must be f64, or bf16 with variant F")
     X = np.asarray(X, dtype=np.float64)
@@ -240,7 +249,10 @@ def rtcur(X: np.ndarray, ranks: Sequence[int], I_sizes: Sequence[int],
             XB = XB_exact = _checked_gather(X, samp)
             den = sum(fro(b) for b in XB)
             LB = evaluate(f, samp)
-        zeta = gamma * zeta
+        if schedule is not None and k < len(schedule):
+            zeta = float(zeta0) * float(schedule[k])
+        else:
+            zeta = gamma * zeta
         # Step (I): partial S-update on the blocks (equations 11 and 13)
         DB = [XB[b] - LB[b] for b in range(n + 1)]
         SB = [hard_threshold(DB[b], zeta) for b in range(n + 1)]

@@ -14,6 +14,8 @@ mirror the C ABI in include/rtcur.h:
     destroy(handle)
     get_indices / get_history / get_block / get_tucker / sample
     set_profiling / get_profile
+    unroll_plan(dims, ranks, I_sizes, K, seed) -> UnrollPlan (see unrolled.py:
+        the differentiable K-iteration RTCUR-F behind torch.autograd)
 
 The library must have been built (``python -m paper_2108_10448_amd.build``);
 importing the binding never falls back to anything else.
@@ -44,7 +46,9 @@ SYMBOLS = ["rtcur_create", "rtcur_solve", "rtcur_reconstruct", "rtcur_outliers",
            "rtcur_get_indices", "rtcur_get_history", "rtcur_get_block",
            "rtcur_get_tucker", "rtcur_sample", "rtcur_set_profiling",
            "rtcur_get_profile", "rtcur_strerror", "rtcur_last_error", "rtcur_solve_batch",
-           "rtcur_reconstruct_noalloc"]
+           "rtcur_reconstruct_noalloc", "rtcur_set_schedule", "rtcur_unroll_create", "rtcur_unroll_blocks",
+           "rtcur_unroll_forward", "rtcur_unroll_backward", "rtcur_unroll_destroy",
+           "rtcur_unroll_last_error"]
 
 
 class RtcurInfo(ctypes.Structure):
@@ -86,6 +90,7 @@ def lib() -> ctypes.CDLL:
                               dbl, i32, u64, ctypes.POINTER(RtcurInfo)]
     L.rtcur_reconstruct.argtypes = [vp, vp, ctypes.c_int]
     L.rtcur_reconstruct_noalloc.argtypes = [vp, vp, ctypes.c_int]
+    L.rtcur_set_schedule.argtypes = [vp, pd, i32]
     L.rtcur_solve_batch.argtypes = [ctypes.POINTER(vp), i32, i32, ctypes.POINTER(vp),
                                     ctypes.c_int, ctypes.POINTER(ctypes.c_int32), p64,
                                     ctypes.POINTER(ctypes.c_int32), p64, p64, pd, dbl, dbl,
@@ -102,12 +107,20 @@ def lib() -> ctypes.CDLL:
     L.rtcur_set_profiling.argtypes = [vp, i32]
     L.rtcur_get_profile.argtypes = [vp, i32, ctypes.c_char_p, i32, pd,
                                     ctypes.POINTER(ctypes.c_int64)]
+    L.rtcur_unroll_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, vp, i32, p64,
+                                      ctypes.POINTER(ctypes.c_int32), p64, i32, u64]
+    L.rtcur_unroll_blocks.argtypes = [vp, p64, p64, i64]
+    L.rtcur_unroll_forward.argtypes = [vp, vp, ctypes.c_int, pd, dbl, vp]
+    L.rtcur_unroll_backward.argtypes = [vp, vp, pd, vp]
+    L.rtcur_unroll_destroy.argtypes = [vp]
+    L.rtcur_unroll_last_error.argtypes = [vp]
+    L.rtcur_unroll_last_error.restype = ctypes.c_char_p
     L.rtcur_strerror.argtypes = [ctypes.c_int]
     L.rtcur_strerror.restype = ctypes.c_char_p
     L.rtcur_last_error.argtypes = [vp]
     L.rtcur_last_error.restype = ctypes.c_char_p
     for name in SYMBOLS:
-        if name not in ("rtcur_strerror", "rtcur_last_error"):
+        if name not in ("rtcur_strerror", "rtcur_last_error", "rtcur_unroll_last_error"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -269,6 +282,18 @@ def solve(h: Handle, X, ranks: Sequence[int], I_sizes: Optional[Sequence[int]] =
         warnings.warn(f"RTCUR did not reach tol in {max_iter} iterations (e={info.err:.3e})")
     return Info(rc, info.iters, bool(info.converged), info.err, info.zeta, info.zeta0,
                 info.eig_steps, info.eig_unconverged)
+
+
+def set_schedule(h: Handle, multipliers=None) -> None:
+    """rtcur_set_schedule: thresholds zeta_k = multipliers[k-1] zeta_0 for
+    the first len(multipliers) iterations of the following solves, then the
+    decay by gamma; None (or empty) restores the geometric schedule."""
+    c = np.ascontiguousarray(np.asarray([] if multipliers is None else multipliers,
+                                        dtype=np.float64).reshape(-1))
+    rc = lib().rtcur_set_schedule(h.ptr, c.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+                                  if c.size else None, int(c.size))
+    if rc != OK:
+        raise RTCURError(rc, f"rtcur_set_schedule: {strerror(rc)}: {h.last_error()}")
 
 
 def batch_schedule(shapes, nh: int):
@@ -519,3 +544,114 @@ def get_profile(h: Handle) -> dict:
         out[name.value.decode()] = (ms.value, cnt.value)
         kind += 1
     return out
+
+
+class UnrollPlan:
+    """An rtcur_unroll_t: the sample, workspace and checkpoints of one
+    differentiable unrolled RTCUR-F pass (float64, three modes)."""
+
+    def __init__(self, ptr, device, dims, ranks, I_sizes, K, seed, stream):
+        self.ptr = ptr
+        self.device = device
+        self.dims = list(dims)
+        self.ranks = list(ranks)
+        self.I_sizes = list(I_sizes)
+        self.K = K
+        self.seed = seed
+        self.stream = stream
+        self.generation = 0     # forward passes run so far (backward checks it)
+        n = ctypes.c_int64(0)
+        rc = lib().rtcur_unroll_blocks(ptr, ctypes.byref(n), None, 0)
+        if rc != OK:
+            raise RTCURError(rc, "rtcur_unroll_blocks")
+        self.n_blk = n.value
+
+    def last_error(self) -> str:
+        return lib().rtcur_unroll_last_error(self.ptr).decode() if self.ptr else ""
+
+    def block_index(self) -> np.ndarray:
+        """Offset in X of every block entry, in block-buffer order."""
+        out = np.zeros(self.n_blk, dtype=np.int64)
+        rc = lib().rtcur_unroll_blocks(self.ptr, None,
+                                       out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                       self.n_blk)
+        if rc != OK:
+            raise RTCURError(rc, self.last_error())
+        return out
+
+    def close(self):
+        if self.ptr:
+            lib().rtcur_unroll_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def unroll_plan(dims, ranks, I_sizes=None, K=15, seed=0, device=0, stream=None,
+                upsilon=3.0) -> UnrollPlan:
+    """rtcur_unroll_create on `device` (stream: torch's current by default)."""
+    torch = _torch()
+    if I_sizes is None:
+        I_sizes, _ = default_sizes(dims, ranks, upsilon)
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    out = ctypes.c_void_p()
+    r32 = (ctypes.c_int32 * len(ranks))(*[int(r) for r in ranks])
+    rc = lib().rtcur_unroll_create(ctypes.byref(out), device, ctypes.c_void_p(stream.cuda_stream),
+                                   len(dims), _i64(dims), r32, _i64(I_sizes), int(K),
+                                   int(seed) & ((1 << 64) - 1))
+    if rc != OK:
+        raise RTCURError(rc, f"rtcur_unroll_create: {strerror(rc)}")
+    return UnrollPlan(out, device, dims, ranks, I_sizes, K, seed, stream)
+
+
+def unroll_forward(plan: UnrollPlan, X, zetas, tau: float, L_out=None):
+    """rtcur_unroll_forward: L^K on the blocks (float64 device tensor of
+    plan.n_blk entries); zetas: K thresholds (any sequence / tensor)."""
+    torch = _torch()
+    if not (isinstance(X, torch.Tensor) and X.is_cuda and X.is_contiguous()):
+        raise TypeError("X must be a C-contiguous device tensor")
+    if X.dtype not in (torch.float32, torch.float64) or list(X.shape) != plan.dims:
+        raise TypeError("X must be float32/float64 with the planned dims")
+    z = np.ascontiguousarray(np.asarray(
+        zetas.detach().cpu().numpy() if isinstance(zetas, torch.Tensor) else zetas,
+        dtype=np.float64).reshape(-1))
+    if z.size != plan.K:
+        raise ValueError(f"need {plan.K} thresholds, got {z.size}")
+    if L_out is None:
+        L_out = torch.empty(plan.n_blk, dtype=torch.float64, device=X.device)
+    cur = torch.cuda.current_stream(plan.device)
+    if plan.stream.cuda_stream != cur.cuda_stream:
+        plan.stream.wait_stream(cur)
+    rc = lib().rtcur_unroll_forward(plan.ptr, ctypes.c_void_p(X.data_ptr()),
+                                    F64 if X.dtype == torch.float64 else F32,
+                                    z.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                    float(tau), ctypes.c_void_p(L_out.data_ptr()))
+    if rc != OK:
+        raise RTCURError(rc, f"rtcur_unroll_forward: {strerror(rc)}: {plan.last_error()}")
+    plan.generation += 1
+    return L_out
+
+
+def unroll_backward(plan: UnrollPlan, L_bar):
+    """rtcur_unroll_backward of the plan's last forward: (zeta_bar as a
+    float64 numpy array of K, X_bar as a float64 device tensor)."""
+    torch = _torch()
+    L_bar = L_bar.detach().to(dtype=torch.float64).contiguous()
+    if L_bar.numel() != plan.n_blk or not L_bar.is_cuda:
+        raise ValueError("L_bar must be a device tensor of n_blk entries")
+    zb = np.zeros(plan.K)
+    Xb = torch.empty(plan.dims, dtype=torch.float64, device=L_bar.device)
+    cur = torch.cuda.current_stream(plan.device)
+    if plan.stream.cuda_stream != cur.cuda_stream:
+        plan.stream.wait_stream(cur)
+    rc = lib().rtcur_unroll_backward(plan.ptr, ctypes.c_void_p(L_bar.data_ptr()),
+                                     zb.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                     ctypes.c_void_p(Xb.data_ptr()))
+    if rc != OK:
+        raise RTCURError(rc, f"rtcur_unroll_backward: {strerror(rc)}: {plan.last_error()}")
+    return zb, Xb

@@ -19,7 +19,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librtcur.so")
-SOURCES = ["abi.cpp", "sampler.cpp", "solver.hip"]
+SOURCES = ["abi.cpp", "sampler.cpp", "solver.hip", "unroll.hip"]
 ARCH = os.environ.get("RTCUR_OFFLOAD_ARCH", "gfx950")
 
 

@@ -259,6 +259,20 @@ int rtcur_solve_batch(rtcur_t* hs, int32_t nh, int32_t count, const void* const*
     return rc;
 }
 
+int rtcur_set_schedule(rtcur_t h, const double* multipliers, int32_t n) {
+    if (!h) return RTCUR_E_INVAL;
+    if (n < 0 || (n > 0 && !multipliers)) return fail(h, RTCUR_E_INVAL, "bad schedule");
+    for (int32_t k = 0; k < n; ++k)
+        if (!(multipliers[k] > 0.0) || !std::isfinite(multipliers[k]))
+            return fail(h, RTCUR_E_INVAL, "schedule multipliers must be positive and finite");
+    try {
+        h->sched.assign(multipliers, multipliers + n);
+    } catch (...) {
+        return fail(h, RTCUR_E_NOMEM, "host allocation failed");
+    }
+    return RTCUR_OK;
+}
+
 int rtcur_destroy(rtcur_t h) {
     if (!h) return RTCUR_OK;
     rtcur::release(h);

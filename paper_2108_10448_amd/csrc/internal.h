@@ -88,6 +88,8 @@ struct Prob {
     int bnkc[kMaxModes];      // B-factor column chunks per row block of mode i
     int bsub[kMaxModes];      // staged Z sub-chunks per B-factor column chunk
     const int32_t* I[kMaxModes];   // sampled rows of each mode (device)
+    const double* zsched;     // threshold multipliers c_1..c_nsched of zeta_0 (device)
+    int nsched;               // 0: the geometric decay of equation 12 throughout
     BlockDev blk[kMaxBlocks];
 };
 
@@ -130,6 +132,7 @@ struct rtcur_s {
     rtcur::Shape shape;
     rtcur::SampleHost sample;
     std::vector<double> err_hist, zeta_hist;
+    std::vector<double> sched;  // rtcur_set_schedule: multipliers of zeta_0
     rtcur_info info{};
     // device workspace (owned; grown on demand, freed by destroy)
     std::vector<rtcur::DevBuf> bufs;

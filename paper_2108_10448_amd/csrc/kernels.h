@@ -116,10 +116,14 @@ __device__ __forceinline__ bool stopped(const DevState* st) {
 }
 
 // The same flag for kernels that issue their first loads before testing it:
-// the flag's load bypasses the caches, so testing it at once would stall
-// every workgroup on that round trip.
+// a relaxed device-scope atomic load, which (unlike a volatile one) lets the
+// compiler place its wait at the first use, so that the flag's round trip
+// overlaps the kernel's first data loads instead of stalling every wave at
+// entry.  Only an earlier launch raises the flag where a kernel tests it
+// per thread; where a sibling workgroup of the same launch can raise it,
+// the kernel shares one thread's value through LDS.
 __device__ __forceinline__ int stop_flag(const DevState* st) {
-    return *(volatile const int*)&st->stop;
+    return __hip_atomic_load(&st->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // --------------------------------------------------------------- set-up
@@ -349,7 +353,9 @@ __global__ __launch_bounds__(kThreads) void k_den(Prob P, const double* part, in
 //   L^k = sum_p B[x][p] H[p][c]              (formed on the fly, never stored)
 //   E   = C^k - L^k  -> per-tile sums of E^2 (numerator of e^(k))
 //   D   = X - L^k;  S = D if |D| > zeta_{k+1} else 0;  C^{k+1} = X - S
-// zeta_{k+1} = gamma^(k+1) zeta_0 by repeated multiplication (equation 12).
+// zeta_{k+1} = gamma^(k+1) zeta_0 by repeated multiplication (equation 12),
+// or, with a schedule of multipliers c_j of zeta_0, zeta_j = c_j zeta_0 for
+// j <= nsched and the decay by gamma from the last of them beyond.
 // T: factor and arithmetic type; TB: block storage type (T, or bfloat16
 // with T = float).
 template <typename T, int RP, typename TB = T>
@@ -371,7 +377,16 @@ __global__ __launch_bounds__(kThreads) void k_ht(
     const int cc = valid ? c : bd.ncols - 1;
     const int rows = min(kTileRows, bd.nrows - tl.y);
     double zeta = st->zeta0;
-    for (int j = 0; j <= kcur; ++j) zeta *= gamma;
+    if (kcur < P.nsched) {
+        zeta *= P.zsched[kcur];
+    } else {
+        int j = 0;
+        if (P.nsched > 0) {
+            zeta *= P.zsched[P.nsched - 1];
+            j = P.nsched;
+        }
+        for (; j <= kcur; ++j) zeta *= gamma;
+    }
 
     // all loads first
     TB xb[kTileRows], cb[kTileRows];

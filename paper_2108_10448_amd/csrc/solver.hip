@@ -134,6 +134,7 @@ struct Impl {
     // device regions (inside the arena)
     void *XO = nullptr, *C[2] = {nullptr, nullptr}, *Bf = nullptr, *H = nullptr;
     uint64_t* mask[2] = {nullptr, nullptr};
+    double* zsched = nullptr;       // threshold schedule (max_iter doubles)
     double *W = nullptr, *Y = nullptr, *Z = nullptr, *gram = nullptr,
            *gpart = nullptr, *bpart = nullptr, *Bd = nullptr, *Gd = nullptr, *Tc = nullptr,
            *part = nullptr, *hpart = nullptr, *err_hist = nullptr;
@@ -250,7 +251,7 @@ static void pack_indices(const Shape& sh, const SampleHost& smp, const IdxPack& 
 // Region offsets of one solve's arena.
 struct Regions {
     size_t XO, C0, C1, m0, m1, Bf, H, W, Y, Z, gram, gpart, bpart, Bd, Gd, Tc, part,
-        hpart, hist, st, tiles, idx;
+        hpart, hist, st, tiles, idx, zs;
 };
 
 // Block descriptors, offsets and work lists for this shape; sizes the arena.
@@ -417,6 +418,7 @@ static void plan(Impl& im, const Shape& sh, int esize, size_t idx_bytes, int max
                                       im.bfac_items.size()) +
                       sizeof(int2) * (im.z_tiles.size() + im.h_tiles.size()));
     rg.idx = ar.add(idx_bytes);
+    rg.zs = ar.add(sizeof(double) * (size_t)max_iter);  // threshold schedule
 }
 
 // ------------------------------------------------------------ the solver
@@ -734,6 +736,14 @@ struct Runner {
         int rc;
         im.recs.clear();
         im.ev_used = 0;
+        // the threshold schedule (multipliers of zeta_0), at most max_iter of
+        // them; a pageable copy, finished before the call returns
+        const int ns = (int)std::min<size_t>(h->sched.size(), im.hist_len - 2);
+        im.P.zsched = im.zsched;
+        im.P.nsched = ns;
+        if (ns > 0)
+            HIPCHK(hipMemcpyAsync(im.zsched, h->sched.data(), sizeof(double) * ns,
+                                  hipMemcpyHostToDevice, s));
         draw_sample(seed, 0, sh, sh.chidori, h->sample, false);
         if ((rc = upload_sample(h->sample, sh))) return rc;
         hipLaunchKernelGGL(k_init_state, dim3(16), dim3(kThreads), 0, s, im.st,
@@ -803,9 +813,16 @@ struct Runner {
             for (int j = 1; j <= K; ++j) h->err_hist[j - 1] = eh[j];
         }
         h->zeta_hist.assign(K, 0.0);
+        // the thresholds the kernels used: the schedule's multipliers of
+        // zeta_0, then the decay by gamma from the last of them
+        const int ns = im.P.nsched;
         double z = ds.zeta0;
         for (int j = 0; j < K; ++j) {
-            z *= gamma;
+            if (j < ns) {
+                z = ds.zeta0 * h->sched[(size_t)j];
+            } else {
+                z *= gamma;
+            }
             h->zeta_hist[j] = z;
         }
         rtcur_info& info = h->info;
@@ -1012,6 +1029,7 @@ static int prepare(rtcur_s* h, Impl& im, const Shape& sh, int max_iter) {
     im.d_h_tiles = reinterpret_cast<int2*>(t);
     im.d_idx = a + rg.idx;
     im.idx_bytes = pk.bytes;
+    im.zsched = dp(rg.zs);
     // work lists (one upload)
     std::vector<char> tb(sizeof(int4) * (im.ht_tiles.size() + im.gram_items.size() +
                                          im.bfac_items.size()) +

@@ -178,3 +178,28 @@ def test_resample_counter_of_final_iterate(cube100):
         assert all(np.array_equal(a, b) for a, b in zip(res.sample.I, want.I))
         blocks = gather_blocks(inst.X.astype(np.float64), want)
         assert all(np.array_equal(a, b) for a, b in zip(res.XB, blocks))
+
+
+def test_threshold_schedule_multipliers():
+    # a schedule of multipliers c_k of zeta_0 replaces the first thresholds;
+    # c_k = gamma^k reproduces equation 12 (up to the rounding of gamma^k),
+    # and beyond the schedule the decay continues from its last value
+    import math
+
+    import synth
+    from oracle import rtcur
+    inst = synth.tucker_plus_sparse((20, 18, 16), (2, 2, 2), alpha=0.1, seed=2)
+    I, _ = synth.sample_sizes(inst.dims, inst.ranks, 3.0)
+    base = rtcur(inst.X, inst.ranks, I, tol=0.0, max_iter=6)
+    geo = rtcur(inst.X, inst.ranks, I, tol=0.0, max_iter=6,
+                schedule=[0.7 ** (k + 1) for k in range(3)])
+    for a, b in zip(base.zeta_hist, geo.zeta_hist):
+        assert math.isclose(a, b, rel_tol=1e-14)
+    c = [0.5, 0.3, 0.2]
+    res = rtcur(inst.X, inst.ranks, I, tol=0.0, max_iter=6, schedule=c)
+    z0 = res.zeta0
+    assert res.zeta_hist[:3] == [z0 * 0.5, z0 * 0.3, z0 * 0.2]
+    z = z0 * 0.2
+    for k in range(3, 6):
+        z *= 0.7
+        assert res.zeta_hist[k] == z
