@@ -611,6 +611,14 @@ def main():
                  "one_by_one_tensors_per_s": len(Xb) / sum(single),
                  "single_solve_ms_p50": 1e3 * percentile(single, 0.5),
                  "single_solve_ms_p99": 1e3 * percentile(single, 0.99),
+                 # each instance's solve inside the batch (host wall clock of
+                 # its rtcur_solve on its handle, concurrent with the others)
+                 "in_batch_solve_ms": {
+                     "p50": percentile([i.solve_ms for i in binfos], 0.5),
+                     "p99": percentile([i.solve_ms for i in binfos], 0.99),
+                     "max": max(i.solve_ms for i in binfos)},
+                 "instances_per_handle": [sum(1 for i in binfos if i.batch_slot == t)
+                                          for t in range(nh)],
                  "converged": sum(1 for i in binfos if i.converged),
                  "iters_total": sum(i.iters for i in binfos)}
         del Xb

@@ -72,6 +72,12 @@ typedef struct {
     int32_t eig_unconverged; /* eigensolver calls that stopped at their step
                                 limit before the residual test passed (a
                                 near-degenerate gap sigma_r ~ sigma_{r+1})   */
+    double solve_ms;     /* host wall-clock time of the solve, from the call's
+                            entry to its return (device work included)        */
+    int32_t batch_slot;  /* rtcur_solve_batch: index in hs of the handle that
+                            solved the instance; -1 for rtcur_solve           */
+    int32_t batch_seq;   /* rtcur_solve_batch: the instance's position in that
+                            handle's sequence of solves (0 first); else -1    */
 } rtcur_info;
 
 /* Create a solver bound to HIP device `device` and stream `hip_stream`
@@ -155,15 +161,17 @@ int rtcur_outliers(rtcur_t h, const void* X, int x_dtype, double zeta, void* S_o
 /* Many independent instances (a batch of tensors of uneven shapes and
  * ranks), solved concurrently: each of the nh handles is driven by its own
  * host thread, so handles bound to distinct streams overlap their kernels on
- * the device.  Schedule (fixed before any solve starts): the instances are
- * taken in decreasing number of entries (ties: lower j first), each given to
- * the handle with the fewest entries assigned so far (ties: lower handle
- * index); a handle solves its instances in the order they were given to it.
- * Each instance is Algorithm 1 exactly as rtcur_solve runs it (same results
- * bit for bit, whichever handle runs it).
+ * the device.  Schedule: one work queue holds the instances in decreasing
+ * number of entries (ties: lower j first); each handle's thread takes the
+ * next instance whenever its previous solve has returned, so that slow
+ * instances (many iterations or eigensolver steps) do not hold back the
+ * others.  Which handle solves which instance depends on timing; infos[j]
+ * records it (batch_slot, batch_seq).  Each instance is Algorithm 1 exactly
+ * as rtcur_solve runs it (same results bit for bit, whichever handle runs
+ * it).
  *   hs, nh     nh >= 1 distinct handles (their variant and compute dtype
  *              apply); after the call each holds the state of the last
- *              instance the schedule gave it
+ *              instance it solved (the largest batch_seq among its own)
  *   count      number of instances (>= 0)
  *   X[j]       device tensor of instance j, x_dtype, C-contiguous, read-only
  *   n[j]       its number of modes; dims, ranks, I_sizes (and J_sizes when
@@ -174,8 +182,9 @@ int rtcur_outliers(rtcur_t h, const void* X, int x_dtype, double zeta, void* S_o
  *   seeds[j]   sampler seed of instance j
  *   L_out      NULL, or count device pointers (NULL entries skipped) that
  *              receive instance j's full L (prod dims elements, out_dtype)
- *   infos      NULL or count summaries; status[j] = rtcur_solve's result for
- *              instance j (or rtcur_reconstruct's error)
+ *   infos      NULL or count summaries (with solve_ms, batch_slot and
+ *              batch_seq); status[j] = rtcur_solve's result for instance j
+ *              (or rtcur_reconstruct's error)
  * Returns the first error status by j, else RTCUR_NOT_CONVERGED if any
  * instance did not converge, else RTCUR_OK; RTCUR_E_INVAL for bad arguments
  * (NULL arrays, repeated handles) before any work. */

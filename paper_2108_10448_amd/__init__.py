@@ -55,7 +55,9 @@ class RtcurInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32),
                 ("err", ctypes.c_double), ("zeta", ctypes.c_double),
                 ("zeta0", ctypes.c_double), ("eig_steps", ctypes.c_int32),
-                ("status", ctypes.c_int32), ("eig_unconverged", ctypes.c_int32)]
+                ("status", ctypes.c_int32), ("eig_unconverged", ctypes.c_int32),
+                ("solve_ms", ctypes.c_double), ("batch_slot", ctypes.c_int32),
+                ("batch_seq", ctypes.c_int32)]
 
 
 class RTCURError(RuntimeError):
@@ -181,6 +183,14 @@ class Info:
     zeta0: float
     eig_steps: int
     eig_unconverged: int = 0
+    solve_ms: float = 0.0      # host wall-clock time of the solve
+    batch_slot: int = -1       # batch: index of the handle that solved it
+    batch_seq: int = -1        # batch: position in that handle's sequence
+
+
+def _info(rc, c) -> "Info":
+    return Info(rc, c.iters, bool(c.converged), c.err, c.zeta, c.zeta0, c.eig_steps,
+                c.eig_unconverged, c.solve_ms, c.batch_slot, c.batch_seq)
 
 
 class Handle:
@@ -280,8 +290,7 @@ def solve(h: Handle, X, ranks: Sequence[int], I_sizes: Optional[Sequence[int]] =
         raise RTCURError(rc, f"rtcur_solve: {strerror(rc)}: {h.last_error()}")
     if rc == NOT_CONVERGED and check:
         warnings.warn(f"RTCUR did not reach tol in {max_iter} iterations (e={info.err:.3e})")
-    return Info(rc, info.iters, bool(info.converged), info.err, info.zeta, info.zeta0,
-                info.eig_steps, info.eig_unconverged)
+    return _info(rc, info)
 
 
 def set_schedule(h: Handle, multipliers=None) -> None:
@@ -296,28 +305,14 @@ def set_schedule(h: Handle, multipliers=None) -> None:
         raise RTCURError(rc, f"rtcur_set_schedule: {strerror(rc)}: {h.last_error()}")
 
 
-def batch_schedule(shapes, nh: int):
-    """The instance lists rtcur_solve_batch gives to each of nh handles:
-    instances in decreasing number of entries (ties: lower index first), each
-    to the handle with the fewest entries so far (ties: lower handle)."""
-    ent = [float(math.prod(int(d) for d in sh)) for sh in shapes]
-    order = sorted(range(len(shapes)), key=lambda j: -ent[j])
-    nt = min(nh, len(shapes))
-    lists, load = [[] for _ in range(nt)], [0.0] * nt
-    for j in order:
-        t = min(range(nt), key=lambda u: (load[u], u))
-        lists[t].append(j)
-        load[t] += ent[j]
-    return lists
-
-
 def solve_batch(handles: Sequence[Handle], Xs, ranks, I_sizes=None, J_sizes=None, *,
                 upsilon: float = 3.0, zeta0=None, gamma: float = 0.7, tol: float = 1e-5,
                 max_iter: int = 100, seeds=None, with_L: bool = False, L_dtype=None,
                 check: bool = True):
     """rtcur_solve_batch: instance j is device tensor Xs[j] with ranks[j],
     I_sizes[j] (default upsilon sizes) and J_sizes[j] (or chidori); one host
-    thread per handle, instances spread over the handles by batch_schedule.
+    thread per handle, each taking the next instance (largest first) from one
+    work queue; Info.batch_slot / batch_seq say which handle solved it, when.
     All Xs share one dtype.  Returns (infos, Ls) with Ls the full
     reconstructions when with_L, else None."""
     torch = _torch()
@@ -370,14 +365,16 @@ def solve_batch(handles: Sequence[Handle], Xs, ranks, I_sizes=None, J_sizes=None
                                  F64 if dt == torch.float64 else F32, nn, dims, rk, Is, Js,
                                  z0, float(gamma), float(tol), int(max_iter), sd, lo,
                                  F64 if odt == torch.float64 else F32, infos, st)
-    for t, js in enumerate(batch_schedule([X.shape for X in Xs], len(handles))):
-        if js:
-            handles[t].dims, handles[t].ranks = list(Xs[js[-1]].shape), list(ranks[js[-1]])
+    last = {}
+    for j in range(count):
+        t = infos[j].batch_slot
+        if 0 <= t < len(handles) and infos[j].batch_seq >= last.get(t, (-1, -1))[0]:
+            last[t] = (infos[j].batch_seq, j)
+    for t, (_, j) in last.items():
+        handles[t].dims, handles[t].ranks = list(Xs[j].shape), list(ranks[j])
     if rc < 0 and check:
         raise RTCURError(rc, f"rtcur_solve_batch: {strerror(rc)}")
-    out = [Info(st[j], infos[j].iters, bool(infos[j].converged), infos[j].err,
-                infos[j].zeta, infos[j].zeta0, infos[j].eig_steps, infos[j].eig_unconverged)
-           for j in range(count)]
+    out = [_info(st[j], infos[j]) for j in range(count)]
     return out, Ls
 
 

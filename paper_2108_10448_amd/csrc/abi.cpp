@@ -6,6 +6,8 @@
 #include <cstring>
 #include <new>
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <thread>
 #include <vector>
 
@@ -120,6 +122,7 @@ int rtcur_solve(rtcur_t h, const void* X, int x_dtype, int32_t n, const int64_t*
         if (info) *info = h->info;
         return rc;
     }
+    const auto t0 = std::chrono::steady_clock::now();
     try {
         rc = rtcur::solve(h, X, x_dtype, sh, zeta0, gamma, tol, max_iter, seed);
     } catch (const std::bad_alloc&) {
@@ -131,6 +134,10 @@ int rtcur_solve(rtcur_t h, const void* X, int x_dtype, int32_t n, const int64_t*
         std::memset(&h->info, 0, sizeof(h->info));
         h->info.status = rc;
     }
+    h->info.solve_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    h->info.batch_slot = -1;
+    h->info.batch_seq = -1;
     if (info) *info = h->info;
     return rc;
 }
@@ -183,19 +190,15 @@ int rtcur_solve_batch(rtcur_t* hs, int32_t nh, int32_t count, const void* const*
             if (hs[u] == hs[t]) return RTCUR_E_INVAL;  // one thread per handle
     }
     const int32_t nt = count < nh ? count : nh;
-    // static longest-first schedule: instances in decreasing number of
-    // entries (ties by index), each given to the handle with the fewest
-    // entries assigned so far (ties: lowest handle); every handle then solves
-    // its list in that order
+    // one work queue, longest first: instances in decreasing number of
+    // entries (ties by index); each handle's thread takes the next one when
+    // its previous solve has returned
     std::vector<int32_t> order;
-    std::vector<std::vector<int32_t>> list;
-    std::vector<double> load;
     std::vector<std::thread> pool;
     std::vector<char> inline_list;
+    std::atomic<int32_t> next{0};
     try {
         order.resize(count);
-        list.resize(nt > 0 ? nt : 0);
-        load.assign(nt > 0 ? nt : 0, 0.0);
         inline_list.assign(nt > 0 ? nt : 0, 0);
         pool.reserve(nt > 1 ? nt - 1 : 0);
     } catch (...) {
@@ -211,18 +214,14 @@ int rtcur_solve_batch(rtcur_t* hs, int32_t nh, int32_t count, const void* const*
     try {
         std::stable_sort(order.begin(), order.end(),
                          [&](int32_t x, int32_t y) { return entries(x) > entries(y); });
-        for (int32_t j : order) {
-            int32_t t = 0;
-            for (int32_t u = 1; u < nt; ++u)
-                if (load[u] < load[t]) t = u;
-            list[t].push_back(j);
-            load[t] += entries(j);
-        }
     } catch (...) {
         return RTCUR_E_NOMEM;  // before any solve started
     }
     auto work = [&](int32_t t) {
-        for (int32_t j : list[t]) {
+        for (int32_t seq = 0;; ++seq) {
+            const int32_t q = next.fetch_add(1);
+            if (q >= count) break;
+            const int32_t j = order[q];
             const int64_t* Js = J_sizes ? J_sizes + (int64_t)j * rtcur::kMaxModes : nullptr;
             rtcur_info inf;
             std::memset(&inf, 0, sizeof(inf));
@@ -235,6 +234,8 @@ int rtcur_solve_batch(rtcur_t* hs, int32_t nh, int32_t count, const void* const*
                 if (rr != RTCUR_OK) rc = rr;
             }
             status[j] = rc;
+            inf.batch_slot = t;
+            inf.batch_seq = seq;
             if (infos) infos[j] = inf;
         }
     };

@@ -105,6 +105,9 @@ struct DevState {
     int eig_steps;
     int eig_unconverged;
     double e_prev, e_last;  // the last two e^(k) decided (host chunk planning)
+    int iter;            // k of the next threshold pass when its launch passes
+                         // k = -1 (replayed iteration graphs): advanced by the
+                         // Gram launch's decision workgroup
     unsigned counter[4]; // last-workgroup counters (gather, ht, spare)
     double eigest[kMaxModes];  // per mode: lower bound of lambda_r / lambda_1 of
                                // the Gram at the last eigensolver call (0: none)

@@ -25,6 +25,7 @@ namespace rtcur {
 constexpr int kThreads = 256;      // 4 waves of 64
 constexpr int kTileRows = 16;      // rows per gather / threshold tile
 constexpr int kTileCols = 256;     // one column per thread
+constexpr bool kIterGraphs = true;  // RTCUR-F: steady-state iteration pairs as replayed graphs
 constexpr int kGramMinChunk = 2048; // Gram: columns per work item (at least)
 constexpr int kGramMaxKC = 64;     // Gram: column chunks per output tile (at most)
 constexpr int kGramKCGroup = 4;    // chunks summed per load round in the eigensolver
@@ -130,6 +131,17 @@ __device__ __forceinline__ int stop_flag(const DevState* st) {
 
 // Loop state of a new solve, and zeroed factors (so that a k = 0 result
 // reconstructs to L = 0) and error history, in one launch.
+// The iteration index k of a launch: its argument, or with k = -1 the
+// device's own count (set by k_set_iter before a replayed iteration graph,
+// advanced once per iteration by the Gram launch).
+__device__ __forceinline__ int iter_of(int kcur, const DevState* st) {
+    return kcur >= 0 ? kcur : st->iter;
+}
+
+__global__ void k_set_iter(DevState* st, int k) {
+    if (threadIdx.x == 0) st->iter = k;
+}
+
 __global__ __launch_bounds__(kThreads) void k_init_state(DevState* st, double zeta0,
                                                          uint32_t* bf, int64_t bf_words,
                                                          double* bd, int64_t nbd, double* gd,
@@ -145,6 +157,7 @@ __global__ __launch_bounds__(kThreads) void k_init_state(DevState* st, double ze
         st->eig_unconverged = 0;
         st->e_prev = -1.0;
         st->e_last = -1.0;
+        st->iter = 0;
         for (int j = 0; j < 4; ++j) st->counter[j] = 0u;
         for (int j = 0; j < kMaxModes; ++j) st->eigest[j] = 0.0;
     }
@@ -376,6 +389,7 @@ __global__ __launch_bounds__(kThreads) void k_ht(
     const bool valid = c < bd.ncols;
     const int cc = valid ? c : bd.ncols - 1;
     const int rows = min(kTileRows, bd.nrows - tl.y);
+    kcur = iter_of(kcur, st);
     double zeta = st->zeta0;
     if (kcur < P.nsched) {
         zeta *= P.zsched[kcur];
@@ -417,25 +431,27 @@ __global__ __launch_bounds__(kThreads) void k_ht(
     double e2 = 0.0;
 #pragma unroll
     for (int x = 0; x < kTileRows; ++x) {
-        if (x >= rows) break;  // uniform
+        // (a predicate, not a break: the loop unrolls completely, so that
+        // the row arrays stay in registers)
+        const bool rowok = x < rows;  // uniform
         T L = T(0);
         if (haveL) {
 #pragma unroll
             for (int p = 0; p < RP; ++p) L = fma(brow[x][p], h[p], L);
         }
         const int64_t e = bd.off + (int64_t)(tl.y + x) * bd.ncols + c;
-        if (doE && valid) {
+        if (doE && valid && rowok) {
             const double dv = (double)(T)cb[x] - (double)L;
             e2 += dv * dv;
         }
         if (doHT) {
             const T xv = (T)xb[x];
             const T D = xv - L;
-            const bool keep = valid && fabs((double)D) > zeta;
+            const bool keep = valid && rowok && fabs((double)D) > zeta;
             const T S = keep ? D : T(0);
-            if (valid) Cnew[e] = (TB)(xv - S);
+            if (valid && rowok) Cnew[e] = (TB)(xv - S);
             const uint64_t bal = __ballot(keep);
-            if (lane == 0 && tl.z + wv * 64 < bd.ncols)
+            if (lane == 0 && rowok && tl.z + wv * 64 < bd.ncols)
                 mask[bd.moff + (int64_t)(tl.y + x) * bd.words + (tl.z >> 6) + wv] = bal;
         }
     }
@@ -507,7 +523,12 @@ __global__ __launch_bounds__(kThreads) void k_gram(
     __shared__ T pan[32 * LD];
     __shared__ double sacc[4][256];
     if ((int)blockIdx.x == nitems) {
-        if (decide && !sf) decide_block(P, hpart, kcur, tol, err_hist, st, &sacc[0][0]);
+        if (decide && !sf) {
+            const int kc = iter_of(kcur, st);
+            decide_block(P, hpart, kc, tol, err_hist, st, &sacc[0][0]);
+            // (every thread read the count before decide_block's barriers)
+            if (kcur < 0 && threadIdx.x == 0) st->iter = kc + 1;
+        }
         return;
     }
     const int4 it = items[blockIdx.x];
@@ -680,49 +701,62 @@ __device__ void eig_tm(int sp, bool wantT, EigShared<RP>& sh) {
 // Cholesky of M's r x r block (M in LDS, row stride RP) into upper R in
 // registers, in every thread, with Rinv_jj = 1 / R_jj from one reciprocal
 // square root (no divisions); identity beyond r.  Returns false if a pivot
-// is not positive.
+// is not positive.  M's upper triangle is read up front (every LDS read in
+// flight at once); the columns j >= r, whose entries are fixed, cost a
+// uniform branch each instead of a chain of dependent operations (r is the
+// same in every thread).
 template <int RP>
 __device__ __forceinline__ bool eig_chol(const double* M, int r, double (&R)[RP][RP],
                                          double (&dinv)[RP]) {
-    // straight-line code (selects, no branches on r) so that the LDS reads
-    // of M are not serialised
+    double m[RP][RP];
+#pragma unroll
+    for (int j = 0; j < RP; ++j)
+#pragma unroll
+        for (int q = 0; q < RP; ++q) {
+            m[j][q] = q >= j ? M[j * RP + q] : 0.0;
+            R[j][q] = 0.0;
+        }
     bool ok = true;
 #pragma unroll
     for (int j = 0; j < RP; ++j) {
+        if (j < r) {
+            double d = m[j][j];
 #pragma unroll
-        for (int q = 0; q < RP; ++q) R[j][q] = 0.0;
-    }
+            for (int k = 0; k < j; ++k) d -= R[k][j] * R[k][j];
+            ok = ok && d > 0.0;
+            const double ri = rsqrt(d > 0.0 ? d : 1.0);
+            dinv[j] = ri;
+            R[j][j] = d * ri;
 #pragma unroll
-    for (int j = 0; j < RP; ++j) {
-        const bool jin = j < r;
-        double d = M[j * RP + j];
+            for (int q = j + 1; q < RP; ++q) {
+                double v = m[j][q];
 #pragma unroll
-        for (int k = 0; k < j; ++k) d -= R[k][j] * R[k][j];
-        ok = ok && (!jin || d > 0.0);
-        const double ri = rsqrt((jin && d > 0.0) ? d : 1.0);
-        dinv[j] = ri;
-        R[j][j] = jin ? d * ri : 1.0;
-#pragma unroll
-        for (int q = j + 1; q < RP; ++q) {
-            double v = M[j * RP + q];
-#pragma unroll
-            for (int k = 0; k < j; ++k) v -= R[k][j] * R[k][q];
-            R[j][q] = (jin && q < r) ? v * ri : 0.0;
+                for (int k = 0; k < j; ++k) v -= R[k][j] * R[k][q];
+                R[j][q] = q < r ? v * ri : 0.0;
+            }
+        } else {
+            dinv[j] = 1.0;
+            R[j][j] = 1.0;
         }
     }
     return ok;
 }
 
-// q = z R^-1 for this thread's row.
+// q = z R^-1 for this thread's row (columns r.. of z are zero, and so are
+// those of q).
 template <int RP>
 __device__ __forceinline__ void eig_trsm(const double (&z)[RP], const double (&R)[RP][RP],
-                                         const double (&dinv)[RP], double (&q)[RP]) {
+                                         const double (&dinv)[RP], double (&q)[RP], int r) {
 #pragma unroll
     for (int p = 0; p < RP; ++p) {
-        double v = z[p];
+        if (p < r) {
+            double v = z[p];
 #pragma unroll
-        for (int k = 0; k < p; ++k) v -= q[k] * R[k][p];
-        q[p] = v * dinv[p];
+            for (int k = 0; k < p; ++k) v -= q[k] * R[k][p];
+            q[p] = v * dinv[p];
+        } else {
+            q[p] = 0.0;
+        }
     }
 }
 
@@ -743,14 +777,16 @@ __device__ __forceinline__ void wave_sync() {
 template <int RP, bool kLds = (RP > 8)>
 struct EigChol {
     double R[RP][RP], di[RP];
+    int rk;  // the factored order
     __device__ __forceinline__ bool factor(double* M, int r, EigShared<RP>& sh) {
         (void)sh;
+        rk = r;
         return eig_chol<RP>(M, r, R, di);  // same value in every thread
     }
     __device__ __forceinline__ void solve(const double (&z)[RP], double (&q)[RP],
                                           const EigShared<RP>& sh) const {
         (void)sh;
-        eig_trsm<RP>(z, R, di, q);
+        eig_trsm<RP>(z, R, di, q, rk);
     }
 };
 
@@ -1225,9 +1261,12 @@ __device__ __forceinline__ void eig_finish_regs(const Prob& P, int i, int s, int
 #pragma unroll
             for (int j = RP - 1; j >= 0; --j) {
                 double v = j == lane ? 1.0 : 0.0;
+                if (j < r) {  // (the identity beyond r)
 #pragma unroll
-                for (int k = j + 1; k < RP; ++k) v -= R[j][k] * x[k];
-                x[j] = v * di[j];
+                    for (int k = j + 1; k < RP; ++k) v -= R[j][k] * x[k];
+                    v *= di[j];
+                }
+                x[j] = v;
             }
 #pragma unroll
             for (int j = 0; j < RP; ++j) sh.vv[j * RP + lane] = x[j];  // R^-1[j][lane]
@@ -1269,13 +1308,17 @@ __device__ __forceinline__ void eig_finish_regs(const Prob& P, int i, int s, int
     if (act) {
         // y = q T^-1: u = q R^-1, then y R^T = u
         double u[RP], y[RP];
-        eig_trsm<RP>(q, R, di, u);
+        eig_trsm<RP>(q, R, di, u, r);
 #pragma unroll
         for (int p = RP - 1; p >= 0; --p) {
-            double v = u[p];
+            if (p < r) {
+                double v = u[p];
 #pragma unroll
-            for (int k = p + 1; k < RP; ++k) v -= R[p][k] * y[k];
-            y[p] = v * di[p];
+                for (int k = p + 1; k < RP; ++k) v -= R[p][k] * y[k];
+                y[p] = v * di[p];
+            } else {
+                y[p] = 0.0;
+            }
         }
         double* Yi = Y + P.woff[i];
 #pragma unroll
@@ -2518,14 +2561,15 @@ __global__ __launch_bounds__(kThreads) void k_outliers(int d0, int64_t ncols,
     for (int p = 0; p < RP; ++p) h[p] = Hf[(int64_t)p * ncols + c];
 #pragma unroll
     for (int x = 0; x < kTileRows; ++x) {
-        if (x >= rows) break;  // uniform
-        T L = T(0);
+        if (x < rows) {  // uniform (a predicate, not a break: full unrolling)
+            T L = T(0);
 #pragma unroll
-        for (int p = 0; p < RP; ++p) L = fma(bs[x][p], h[p], L);
-        const T D = (T)xv[x] - L;
-        const int64_t e = (int64_t)(x0 + x) * ncols + c;
-        S_out[e] = (TO)(fabs((double)D) > zeta ? D : T(0));
-        if (L_out) L_out[e] = (TO)L;
+            for (int p = 0; p < RP; ++p) L = fma(bs[x][p], h[p], L);
+            const T D = (T)xv[x] - L;
+            const int64_t e = (int64_t)(x0 + x) * ncols + c;
+            S_out[e] = (TO)(fabs((double)D) > zeta ? D : T(0));
+            if (L_out) L_out[e] = (TO)L;
+        }
     }
 }
 

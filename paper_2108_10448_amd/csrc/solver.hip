@@ -145,6 +145,16 @@ struct Impl {
     size_t idx_bytes = 0;
     size_t hist_len = 0;
 
+    // replayed iteration pair (RTCUR-F steady state), captured on cstream
+    // (two entries: the bfloat16 runner and its FP32 refinement sweep)
+    hipStream_t cstream = nullptr;
+    struct PairGraph {
+        std::vector<char> key;      // what the captured launches depend on
+        hipGraphExec_t exec = nullptr;
+    };
+    std::vector<PairGraph> graphs;  // most recently captured last
+    bool graph_off = false;         // capture failed once: direct launches only
+
     // result bookkeeping
     int final_iter = 0;
     int cur = 0;                    // which C / mask buffer holds C^k
@@ -168,6 +178,8 @@ void release(rtcur_s* h) {
     if (im->h_idx) (void)hipHostFree(im->h_idx);
     if (im->idx_ev) (void)hipEventDestroy(im->idx_ev);
     for (hipEvent_t e : im->events) (void)hipEventDestroy(e);
+    for (auto& g : im->graphs) (void)hipGraphExecDestroy(g.exec);
+    if (im->cstream) (void)hipStreamDestroy(im->cstream);
     delete im;
     h->impl = nullptr;
 }
@@ -866,6 +878,72 @@ struct Runner {
     // C^j lives in C[j % 2]; C^0 is X_Omega itself.
     TB* cbuf(int j) { return j == 0 ? (TB*)im.XO : (TB*)im.C[j % 2]; }
 
+    // The steady-state iteration pair as one executable graph: iterations j
+    // (odd, C^{j-1} in C[0]) and j + 1, every error and decision formed, k
+    // taken from the device's count (launch argument -1).  Captured on the
+    // handle's own capture stream (the caller's stream may be the null
+    // stream, which cannot be captured) and kept while the launches would be
+    // the same: runner type, gamma, tol, the arena and the whole layout.
+    // Sets *out to null when capturing is not possible (then the iterations
+    // are launched one by one).
+    int pair_graph(double gamma, double tol, hipGraphExec_t* out) {
+        *out = nullptr;
+        if (im.graph_off) return 0;
+        std::vector<char> key(sizeof(int) * 3 + sizeof(double) * 2 + sizeof(void*) + sizeof(Prob));
+        {
+            char* q = key.data();
+            const int tp[3] = {(int)sizeof(T), RP, (int)sizeof(TB)};
+            const void* ar = im.arena;
+            std::memcpy(q, tp, sizeof(tp));
+            q += sizeof(tp);
+            std::memcpy(q, &gamma, sizeof(double));
+            q += sizeof(double);
+            std::memcpy(q, &tol, sizeof(double));
+            q += sizeof(double);
+            std::memcpy(q, &ar, sizeof(void*));
+            q += sizeof(void*);
+            std::memcpy(q, &im.P, sizeof(Prob));
+        }
+        for (auto& g : im.graphs)
+            if (g.key == key) {
+                *out = g.exec;
+                return 0;
+            }
+        if (im.graphs.size() >= 2) {
+            HIPCHK(hipStreamSynchronize(s));  // no replay of it still queued
+            HIPCHK(hipGraphExecDestroy(im.graphs.front().exec));
+            im.graphs.erase(im.graphs.begin());
+        }
+        if (!im.cstream) HIPCHK(hipStreamCreateWithFlags(&im.cstream, hipStreamNonBlocking));
+        const hipStream_t s0 = s;
+        if (hipStreamBeginCapture(im.cstream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            (void)hipGetLastError();
+            im.graph_off = true;
+            return 0;
+        }
+        s = im.cstream;
+        const int flags = kDoHT | kHaveL | kDoE | kDecide;
+        int rc = ht(-1, flags, (TB*)im.C[0], (TB*)im.C[1], im.mask[1], gamma);
+        if (!rc) rc = lupdate((TB*)im.C[1], 1, 1, -1, tol);
+        if (!rc) rc = ht(-1, flags, (TB*)im.C[1], (TB*)im.C[0], im.mask[0], gamma);
+        if (!rc) rc = lupdate((TB*)im.C[0], 1, 1, -1, tol);
+        s = s0;
+        hipGraph_t g = nullptr;
+        const hipError_t ec = hipStreamEndCapture(im.cstream, &g);
+        hipError_t ei = hipErrorUnknown;
+        hipGraphExec_t ex = nullptr;
+        if (!rc && ec == hipSuccess && g) ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        if (g) (void)hipGraphDestroy(g);
+        if (rc || ec != hipSuccess || ei != hipSuccess) {
+            (void)hipGetLastError();
+            im.graph_off = true;
+            return rc;
+        }
+        im.graphs.push_back(Impl::PairGraph{std::move(key), ex});
+        *out = ex;
+        return 0;
+    }
+
     // Iterations j0 + 1 .. (stop or max_iter).  The first of them has no
     // e^(j0) to form when j0 > 0 (it was formed before the loop was resumed).
     // Iterations are queued in chunks (4 first, then as many as the observed
@@ -884,14 +962,31 @@ struct Runner {
                 if (std::isfinite(need)) chunk = (int)std::min(12.0, std::max(1.0, std::ceil(need)));
             }
             chunk = std::min(chunk, max_iter - done);
-            for (int q = 0; q < chunk; ++q) {
+            for (int q = 0; q < chunk;) {
                 const int j = done + 1 + q;  // iteration j computes S^j, L^j
                 tag = j;
+                // steady state from an odd j >= 3 on (C^{j-1} in C[0], every
+                // error formed): the rest of the chunk as replayed pairs, with
+                // the device's iteration count set to j - 1 first
+                if (kIterGraphs && h->prof_mask == 0 && j % 2 == 1 && j >= 3 && j >= j0 + 2 &&
+                    chunk - q >= 2) {
+                    hipGraphExec_t gx = nullptr;
+                    if ((rc = pair_graph(gamma, tol, &gx))) return rc;
+                    if (gx) {
+                        hipLaunchKernelGGL(k_set_iter, dim3(1), dim3(64), 0, s, im.st, j - 1);
+                        HIPCHK(hipGetLastError());
+                        const int np = (chunk - q) / 2;
+                        for (int p = 0; p < np; ++p) HIPCHK(hipGraphLaunch(gx, s));
+                        q += 2 * np;
+                        continue;
+                    }
+                }
                 const bool err = j > 1 && j > j0 + 1;  // e^(j-1) formed here
                 const int flags = kDoHT | (j > 1 ? kHaveL : 0) | (err ? (kDoE | kDecide) : 0);
                 if ((rc = ht(j - 1, flags, cbuf(j - 1), cbuf(j), im.mask[j % 2], gamma)))
                     return rc;
                 if ((rc = lupdate(cbuf(j), j > 1 ? 1 : 0, err ? 1 : 0, j - 1, tol))) return rc;
+                ++q;
             }
             done += chunk;
             if ((rc = read_state(ds))) return rc;

@@ -106,16 +106,24 @@ def test_library_sampler_matches_oracle(L, seed):
                 assert np.array_equal(rt.sample(seed, t, dims, I, J, i, 1), o.J_cols[i])
 
 
-def test_batch_schedule_longest_first():
-    # the schedule rtcur_solve_batch documents, worked by hand: entries
-    # 8, 27, 8, 64, 1 over two handles -> 64 to handle 0, then 27, 8, 8, 1
-    # all to handle 1 (its load stays below 64)
+def test_info_layout_matches_header(tmp_path):
+    # the binding's rtcur_info mirror has the C header's size and offsets
+    # (a C program built from include/rtcur.h prints them)
+    import shutil
+    import subprocess
     import paper_2108_10448_amd as rt
-    shapes = [(2, 2, 2), (3, 3, 3), (2, 4), (4, 4, 4), (1, 1)]
-    assert rt.batch_schedule(shapes, 2) == [[3], [1, 0, 2, 4]]
-    assert rt.batch_schedule(shapes, 8) == [[3], [1], [0], [2], [4]]
-    assert rt.batch_schedule([], 3) == []
-    # entries 35, 15, 45, 45, 5, 20, 30 over three handles
-    lists = rt.batch_schedule([(d, 5) for d in (7, 3, 9, 9, 1, 4, 6)], 3)
-    assert sorted(j for js in lists for j in js) == list(range(7))
-    assert lists == [[2, 5], [3, 1, 4], [0, 6]]
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    names = [f[0] for f in rt.RtcurInfo._fields_]
+    src = tmp_path / "layout.c"
+    body = "".join(f'printf("%zu ", offsetof(rtcur_info, {n}));' for n in names)
+    src.write_text("#include <stddef.h>\n#include <stdio.h>\n#include \"rtcur.h\"\n"
+                   "int main(void) {" + body + 'printf("%zu\\n", sizeof(rtcur_info)); return 0; }\n')
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run([cc, "-I", inc, str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True,
+                                          text=True).stdout.split()]
+    want = [getattr(rt.RtcurInfo, n).offset for n in names] + [ctypes.sizeof(rt.RtcurInfo)]
+    assert got == want

@@ -141,11 +141,21 @@ def test_solve_batch_uneven_instances():
         torch.cuda.synchronize()
         assert torch.equal(L1, Ls[j])
         rt.destroy(h1)
-    # each handle keeps the state of the last instance its schedule gave it
-    for t, js in enumerate(rt.batch_schedule([X.shape for X in Xs], len(hs))):
-        Lt = rt.reconstruct(hs[t])
-        torch.cuda.synchronize()
-        assert js and torch.equal(Lt, Ls[js[-1]])
+    # the work queue: every instance solved once, each handle's solves
+    # numbered 0, 1, .. and taken largest first; each handle keeps the state
+    # of the last instance it solved
+    ent = [int(np.prod(X.shape)) for X in Xs]
+    for t in range(len(hs)):
+        mine = sorted((infos[j].batch_seq, j) for j in range(len(Xs))
+                      if infos[j].batch_slot == t)
+        assert [q for q, _ in mine] == list(range(len(mine)))
+        assert all(ent[a] >= ent[b] for (_, a), (_, b) in zip(mine, mine[1:]))
+        if mine:
+            Lt = rt.reconstruct(hs[t])
+            torch.cuda.synchronize()
+            assert torch.equal(Lt, Ls[mine[-1][1]])
+    assert all(0 <= infos[j].batch_slot < len(hs) for j in range(len(Xs)))
+    assert all(infos[j].solve_ms > 0 for j in range(len(Xs)))
     for h in hs:
         rt.destroy(h)
 
