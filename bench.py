@@ -586,12 +586,30 @@ def main():
         nh = 4
         streams = [torch.cuda.Stream() for _ in range(nh)]
         hs = [rt.create(0, stream=st, dtype=torch.float32) for st in streams]
-        rt.solve_batch(hs, Xb, rb, Ib, seeds=sb, check=False)   # warm-up pass
-        torch.cuda.synchronize()
+
+        def timed_batch():
+            rt.solve_batch(hs, Xb, rb, Ib, seeds=sb, check=False)   # warm-up pass
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            infos, _ = rt.solve_batch(hs, Xb, rb, Ib, seeds=sb, check=False)
+            torch.cuda.synchronize()
+            return infos, time.perf_counter() - t0
+
+        # built-in tile rule, then every instance's sizes autotuned (tiles of
+        # the threshold pass, Gram and B-factor work items), then again
+        rt.autotune_clear()
+        _, t_untuned = timed_batch()
+        htune = rt.create(0, dtype=torch.float32)
         t0 = time.perf_counter()
-        binfos, _ = rt.solve_batch(hs, Xb, rb, Ib, seeds=sb, check=False)
-        torch.cuda.synchronize()
-        t_batch = time.perf_counter() - t0
+        tiles = {}
+        for j in range(len(Xb)):
+            got = rt.autotune(htune, Xb[j], rb[j], Ib[j], iters=4, reps=2, seed=sb[j])
+            key = (got["ht_rows"], got["gram_chunk"], got["bfac_sub"])
+            tiles[key] = tiles.get(key, 0) + 1
+        t_tune = time.perf_counter() - t0
+        rt.destroy(htune)
+        binfos, t_batch = timed_batch()
+        rt.autotune_clear()
         for hh in hs:
             rt.destroy(hh)
         h1 = rt.create(0, dtype=torch.float32)
@@ -607,6 +625,13 @@ def main():
                              "r_i ~ U{2..8}, alpha ~ U[0.1, 0.4], RTCUR-F, upsilon 3, tol 1e-5",
                  "handles": nh, "batch_ms": 1e3 * t_batch,
                  "tensors_per_s": len(Xb) / t_batch,
+                 "tiles": "autotuned per instance sizes (rtcur_autotune, 4 iterations x 2 "
+                          "reps per candidate)",
+                 "autotune_s": t_tune,
+                 "tiles_chosen": {f"rows{a}_gram{b}_bsub{c}": v
+                                  for (a, b, c), v in sorted(tiles.items())},
+                 "untuned_batch_ms": 1e3 * t_untuned,
+                 "untuned_tensors_per_s": len(Xb) / t_untuned,
                  "one_by_one_ms": 1e3 * sum(single),
                  "one_by_one_tensors_per_s": len(Xb) / sum(single),
                  "single_solve_ms_p50": 1e3 * percentile(single, 0.5),

@@ -195,6 +195,55 @@ int rtcur_solve_batch(rtcur_t* hs, int32_t nh, int32_t count, const void* const*
                       const uint64_t* seeds, void* const* L_out, int out_dtype,
                       rtcur_info* infos, int32_t* status);
 
+/* Tile autotuner for the per-iteration kernels (the threshold pass of
+ * equations 10-11 over the sampled blocks, the Gram of the truncated SVD of
+ * equation 9 and the B-factor mode products of equation 8 in core form):
+ * times candidate tile shapes on this problem and records the fastest in a
+ * process-wide table keyed by the problem sizes (dims, ranks, I_sizes,
+ * J_sizes, sampling kind, block element size), which every later layout of
+ * those sizes -- on any handle, in rtcur_solve and rtcur_solve_batch --
+ * uses.  Candidates, by coordinate descent from the built-in rule: rows per
+ * threshold tile (8, 16, 32; 32 not for float64 blocks), columns per Gram
+ * work item (512 .. 8192), Z sub-chunks per B-factor work item (1 .. 8);
+ * each timed as the best of `reps` solves of `iters` iterations (tol 0,
+ * gamma 0.7, zeta_0 = max|X|, seed) after one warm-up, host wall clock.
+ * Tile shapes change only the order of floating-point sums (the Gram over
+ * column chunks, B over sub-chunks), so results agree to rounding with the
+ * built-in rule; a solve is bit-for-bit reproducible for a fixed table.
+ *   X, x_dtype, n, dims, ranks, I_sizes, J_sizes   as in rtcur_solve
+ *   iters (1..1000), reps (1..100), seed
+ *   tile       out, 3 values: rows per tile, Gram chunk columns (0: built-in
+ *              rule), B sub-chunks (0: built-in rule)
+ *   tuned_ms, default_ms   out (nullable): best candidate's time and the
+ *              built-in rule's
+ * The handle is left holding the last candidate's solve.  Errors as
+ * rtcur_solve; the table is unchanged on error. */
+int rtcur_autotune(rtcur_t h, const void* X, int x_dtype, int32_t n, const int64_t* dims,
+                   const int32_t* ranks, const int64_t* I_sizes, const int64_t* J_sizes,
+                   int32_t iters, int32_t reps, uint64_t seed, int32_t* tile,
+                   double* tuned_ms, double* default_ms);
+/* Tile shapes of this handle's following solves, overriding the tuned table:
+ * tile[0] rows per threshold tile (8, 16 or 32; float64 blocks use 16 for
+ * 32), tile[1] columns per Gram work item (0: built-in rule, else a multiple
+ * of 256), tile[2] Z sub-chunks per B-factor work item (0: built-in, at most
+ * 64; raised to the minimum the partial-row limit needs).  NULL: back to the
+ * table.  RTCUR_E_INVAL for other values. */
+int rtcur_set_tiles(rtcur_t h, const int32_t* tile);
+/* Replayed iteration graphs for this handle's RTCUR-F solves (enable != 0):
+ * from the third iteration on, each pair of iterations (the threshold pass
+ * and the L-update of equations 8-14, twice) is one executable HIP graph,
+ * captured once per layout on a private stream and replayed with
+ * hipGraphLaunch; the iteration index lives on the device.  Results are
+ * bit for bit those of kernel-by-kernel launches.  Off by default: on the
+ * measured stack a replayed pair takes a few microseconds longer than its
+ * launches one by one, and a capture costs about half a millisecond per new
+ * layout; it pays only where the host cannot keep the launch queue full.
+ * Ignored while profiling is on. */
+int rtcur_set_graphs(rtcur_t h, int32_t enable);
+/* Empties the autotuner's table: every solve afterwards uses the built-in
+ * rule.  Thread-safe; not to be called while solves run. */
+int rtcur_autotune_clear(void);
+
 /* Threshold schedule of the following solves on this handle (a learned
  * alternative to equation 12's decay, Section 3.2): iteration k <= n
  * thresholds with zeta_k = multipliers[k-1] * zeta_0, later iterations

@@ -48,7 +48,8 @@ SYMBOLS = ["rtcur_create", "rtcur_solve", "rtcur_reconstruct", "rtcur_outliers",
            "rtcur_get_profile", "rtcur_strerror", "rtcur_last_error", "rtcur_solve_batch",
            "rtcur_reconstruct_noalloc", "rtcur_set_schedule", "rtcur_unroll_create", "rtcur_unroll_blocks",
            "rtcur_unroll_forward", "rtcur_unroll_backward", "rtcur_unroll_destroy",
-           "rtcur_unroll_last_error"]
+           "rtcur_unroll_last_error", "rtcur_autotune", "rtcur_autotune_clear",
+           "rtcur_set_tiles", "rtcur_set_graphs"]
 
 
 class RtcurInfo(ctypes.Structure):
@@ -93,6 +94,11 @@ def lib() -> ctypes.CDLL:
     L.rtcur_reconstruct.argtypes = [vp, vp, ctypes.c_int]
     L.rtcur_reconstruct_noalloc.argtypes = [vp, vp, ctypes.c_int]
     L.rtcur_set_schedule.argtypes = [vp, pd, i32]
+    L.rtcur_autotune.argtypes = [vp, vp, ctypes.c_int, i32, p64, ctypes.POINTER(ctypes.c_int32),
+                                 p64, p64, i32, i32, u64, ctypes.POINTER(ctypes.c_int32), pd, pd]
+    L.rtcur_autotune_clear.argtypes = []
+    L.rtcur_set_tiles.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+    L.rtcur_set_graphs.argtypes = [vp, i32]
     L.rtcur_solve_batch.argtypes = [ctypes.POINTER(vp), i32, i32, ctypes.POINTER(vp),
                                     ctypes.c_int, ctypes.POINTER(ctypes.c_int32), p64,
                                     ctypes.POINTER(ctypes.c_int32), p64, p64, pd, dbl, dbl,
@@ -303,6 +309,62 @@ def set_schedule(h: Handle, multipliers=None) -> None:
                                   if c.size else None, int(c.size))
     if rc != OK:
         raise RTCURError(rc, f"rtcur_set_schedule: {strerror(rc)}: {h.last_error()}")
+
+
+def autotune(h: Handle, X, ranks: Sequence[int], I_sizes: Optional[Sequence[int]] = None,
+             J_sizes: Optional[Sequence[int]] = None, *, upsilon: float = 3.0, iters: int = 4,
+             reps: int = 2, seed: int = 0) -> dict:
+    """rtcur_autotune: times tile shapes on this problem and records the
+    fastest in the library's process-wide table for its sizes.  Returns
+    {"ht_rows", "gram_chunk", "bfac_sub", "tuned_ms", "default_ms"}."""
+    torch = _torch()
+    if not isinstance(X, torch.Tensor) or not X.is_cuda or not X.is_contiguous():
+        raise TypeError("X must be a C-contiguous device torch.Tensor")
+    if X.dtype not in (torch.float32, torch.float64):
+        raise TypeError("X must be float32 or float64")
+    dims = list(X.shape)
+    if I_sizes is None:
+        I_sizes, _ = default_sizes(dims, ranks, upsilon)
+    r32 = (ctypes.c_int32 * len(ranks))(*[int(r) for r in ranks])
+    tile = (ctypes.c_int32 * 3)()
+    tms, dms = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    _order(h)
+    rc = lib().rtcur_autotune(h.ptr, ctypes.c_void_p(X.data_ptr()),
+                              F64 if X.dtype == torch.float64 else F32, len(dims), _i64(dims),
+                              r32, _i64(I_sizes),
+                              _i64(J_sizes) if J_sizes is not None else None, int(iters),
+                              int(reps), int(seed) & ((1 << 64) - 1), tile, ctypes.byref(tms),
+                              ctypes.byref(dms))
+    h.dims, h.ranks = dims, list(ranks)
+    if rc != OK:
+        raise RTCURError(rc, f"rtcur_autotune: {strerror(rc)}: {h.last_error()}")
+    return {"ht_rows": tile[0], "gram_chunk": tile[1], "bfac_sub": tile[2],
+            "tuned_ms": tms.value, "default_ms": dms.value}
+
+
+def set_tiles(h: Handle, tile=None) -> None:
+    """rtcur_set_tiles: (rows per threshold tile, Gram chunk columns, B
+    sub-chunks) for this handle's solves; None: back to the tuned table."""
+    if tile is None:
+        rc = lib().rtcur_set_tiles(h.ptr, None)
+    else:
+        t = (ctypes.c_int32 * 3)(*[int(v) for v in tile])
+        rc = lib().rtcur_set_tiles(h.ptr, t)
+    if rc != OK:
+        raise RTCURError(rc, f"rtcur_set_tiles: {strerror(rc)}: {h.last_error()}")
+
+
+def set_graphs(h: Handle, enable: bool) -> None:
+    """rtcur_set_graphs: RTCUR-F steady-state iteration pairs as replayed
+    HIP graphs (bit-for-bit the same results; off by default)."""
+    rc = lib().rtcur_set_graphs(h.ptr, 1 if enable else 0)
+    if rc != OK:
+        raise RTCURError(rc, f"rtcur_set_graphs: {strerror(rc)}")
+
+
+def autotune_clear() -> None:
+    """rtcur_autotune_clear: every later solve uses the built-in tile rule."""
+    lib().rtcur_autotune_clear()
 
 
 def solve_batch(handles: Sequence[Handle], Xs, ranks, I_sizes=None, J_sizes=None, *,

@@ -260,6 +260,65 @@ int rtcur_solve_batch(rtcur_t* hs, int32_t nh, int32_t count, const void* const*
     return rc;
 }
 
+int rtcur_autotune(rtcur_t h, const void* X, int x_dtype, int32_t n, const int64_t* dims,
+                   const int32_t* ranks, const int64_t* I_sizes, const int64_t* J_sizes,
+                   int32_t iters, int32_t reps, uint64_t seed, int32_t* tile,
+                   double* tuned_ms, double* default_ms) {
+    if (!h) return RTCUR_E_INVAL;
+    if (!X || !tile) return fail(h, RTCUR_E_INVAL, "X and tile must not be null");
+    if (iters < 1 || iters > 1000 || reps < 1 || reps > 100)
+        return fail(h, RTCUR_E_INVAL, "iters must be in [1, 1000] and reps in [1, 100]");
+    rtcur::Shape sh;
+    int rc = validate(h, n, dims, ranks, I_sizes, J_sizes, 0.7, 0.0, iters, x_dtype, sh);
+    if (rc != RTCUR_OK) return rc;
+    rtcur::Tune best;
+    double bm = 0.0, dm = 0.0;
+    try {
+        rc = rtcur::autotune(h, X, x_dtype, sh, iters, reps, seed, &best, &bm, &dm);
+    } catch (const std::bad_alloc&) {
+        rc = fail(h, RTCUR_E_NOMEM, "host allocation failed");
+    } catch (...) {
+        rc = fail(h, RTCUR_E_STATE, "internal error");
+    }
+    h->tune_forced = false;
+    if (rc < 0) return rc;
+    tile[0] = best.ht_rows;
+    tile[1] = best.gram_chunk;
+    tile[2] = best.bfac_sub;
+    if (tuned_ms) *tuned_ms = bm;
+    if (default_ms) *default_ms = dm;
+    return RTCUR_OK;
+}
+
+int rtcur_set_tiles(rtcur_t h, const int32_t* tile) {
+    if (!h) return RTCUR_E_INVAL;
+    if (!tile) {
+        h->tune_user_set = false;
+        return RTCUR_OK;
+    }
+    if ((tile[0] != 8 && tile[0] != 16 && tile[0] != 32) || tile[1] < 0 ||
+        (tile[1] > 0 && (tile[1] < 256 || tile[1] % 256 != 0)) || tile[2] < 0 || tile[2] > 64)
+        return fail(h, RTCUR_E_INVAL,
+                    "tile: rows 8, 16 or 32; Gram chunk 0 or a multiple of 256; B sub-chunks "
+                    "0..64");
+    h->tune_user.ht_rows = tile[0];
+    h->tune_user.gram_chunk = tile[1];
+    h->tune_user.bfac_sub = tile[2];
+    h->tune_user_set = true;
+    return RTCUR_OK;
+}
+
+int rtcur_set_graphs(rtcur_t h, int32_t enable) {
+    if (!h) return RTCUR_E_INVAL;
+    h->graphs = enable != 0;
+    return RTCUR_OK;
+}
+
+int rtcur_autotune_clear(void) {
+    rtcur::autotune_clear();
+    return RTCUR_OK;
+}
+
 int rtcur_set_schedule(rtcur_t h, const double* multipliers, int32_t n) {
     if (!h) return RTCUR_E_INVAL;
     if (n < 0 || (n > 0 && !multipliers)) return fail(h, RTCUR_E_INVAL, "bad schedule");

@@ -122,6 +122,18 @@ struct DevBuf {
 
 struct rtcur_handle_impl;  // fwd
 
+// Tile shapes of a layout (0: the built-in rule): rows per gather /
+// threshold tile (8, 16 or 32), columns per Gram work item (sets the number
+// of column chunks per Gram tile), Z sub-chunks per B-factor work item.
+struct Tune {
+    int ht_rows = 0;
+    int gram_chunk = 0;
+    int bfac_sub = 0;
+    bool operator==(const Tune& o) const {
+        return ht_rows == o.ht_rows && gram_chunk == o.gram_chunk && bfac_sub == o.bfac_sub;
+    }
+};
+
 }  // namespace rtcur
 
 struct rtcur_s {
@@ -144,6 +156,14 @@ struct rtcur_s {
     uint32_t prof_mask = 0;   // bit k: time kernel kind k
     double prof_ms[16] = {};
     int64_t prof_count[16] = {};
+    // tile shapes: the autotuner's candidate under test, else the caller's
+    // (rtcur_set_tiles), else the tuned table's entry, else the built-in rule
+    bool tune_forced = false;
+    rtcur::Tune tune_force;
+    bool tune_user_set = false;
+    rtcur::Tune tune_user;
+    // rtcur_set_graphs: RTCUR-F's steady-state iterations as replayed graphs
+    bool graphs = false;
 };
 
 namespace rtcur {
@@ -162,6 +182,13 @@ constexpr size_t kStaticScratchBytes = size_t(64) << 20;
 // looks up (once per device, `device` current) the static scratch's address
 int static_scratch_init(int device);
 int reconstruct_noalloc(rtcur_s* h, void* out, int out_dtype);
+// Times candidate tile shapes for this problem (coordinate descent over
+// ht_rows, gram_chunk, bfac_sub; each candidate the best of `reps` solves of
+// `iters` iterations after one warm-up) and records the fastest for its
+// sizes in the process-wide table that later layouts of those sizes use.
+int autotune(rtcur_s* h, const void* X, int x_dtype, const Shape& sh, int iters, int reps,
+             uint64_t seed, Tune* best, double* best_ms, double* default_ms);
+void autotune_clear();
 constexpr int kProfKinds = 10;
 extern const char* const kProfNames[kProfKinds];
 }  // namespace rtcur

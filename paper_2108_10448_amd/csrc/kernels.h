@@ -25,7 +25,6 @@ namespace rtcur {
 constexpr int kThreads = 256;      // 4 waves of 64
 constexpr int kTileRows = 16;      // rows per gather / threshold tile
 constexpr int kTileCols = 256;     // one column per thread
-constexpr bool kIterGraphs = true;  // RTCUR-F: steady-state iteration pairs as replayed graphs
 constexpr int kGramMinChunk = 2048; // Gram: columns per work item (at least)
 constexpr int kGramMaxKC = 64;     // Gram: column chunks per output tile (at most)
 constexpr int kGramKCGroup = 4;    // chunks summed per load round in the eigensolver
@@ -289,7 +288,7 @@ __global__ __launch_bounds__(kThreads) void k_absmax_fin(const double* part, int
 // ------------------------------------------------------------------ gather
 // X_Omega: R = X(I_1..I_n), C_i = X_(i)(:, J_i) (Algorithm 1, equation 9),
 // with per-tile squared sums for the denominator of e^(k) (equation 14).
-template <typename TX, typename T>
+template <typename TX, typename T, int TR = kTileRows>
 __global__ __launch_bounds__(kThreads) void k_gather(
     const TX* __restrict__ X, Prob P, const int4* __restrict__ tiles,
     T* __restrict__ XO, double* part, const DevState* st, int flags) {
@@ -298,21 +297,21 @@ __global__ __launch_bounds__(kThreads) void k_gather(
     const int4 tl = tiles[blockIdx.x];
     const BlockDev& bd = P.blk[tl.x];
     const int c = tl.z + threadIdx.x;
-    const int rows = min(kTileRows, bd.nrows - tl.y);
+    const int rows = min(TR, bd.nrows - tl.y);
     const bool valid = c < bd.ncols;
     const int cc = valid ? c : bd.ncols - 1;
     const int64_t cx = bd.colx[cc];
     const int64_t rs = P.xstride[bd.mode];
-    TX v[kTileRows];
+    TX v[TR];
 #pragma unroll
-    for (int x = 0; x < kTileRows; ++x) {
+    for (int x = 0; x < TR; ++x) {
         const int xr = tl.y + (x < rows ? x : rows - 1);
         const int64_t xi = bd.rowidx ? bd.rowidx[xr] : xr;
         v[x] = X[xi * rs + cx];
     }
     double acc = 0.0, bad = 0.0;
 #pragma unroll
-    for (int x = 0; x < kTileRows; ++x) {
+    for (int x = 0; x < TR; ++x) {
         if (valid && x < rows) {
             const T t = (T)v[x];
             XO[bd.off + (int64_t)(tl.y + x) * bd.ncols + c] = t;
@@ -371,7 +370,7 @@ __global__ __launch_bounds__(kThreads) void k_den(Prob P, const double* part, in
 // j <= nsched and the decay by gamma from the last of them beyond.
 // T: factor and arithmetic type; TB: block storage type (T, or bfloat16
 // with T = float).
-template <typename T, int RP, typename TB = T>
+template <typename T, int RP, typename TB = T, int TR = kTileRows>
 __global__ __launch_bounds__(kThreads) void k_ht(
     Prob P, const int4* __restrict__ tiles, const TB* __restrict__ XO,
     const TB* __restrict__ Cold, TB* __restrict__ Cnew,
@@ -379,7 +378,7 @@ __global__ __launch_bounds__(kThreads) void k_ht(
     const T* __restrict__ H, double gamma, int kcur, int flags,
     double* __restrict__ part, const DevState* st) {
     const int sf = stop_flag(st);
-    __shared__ T brow[kTileRows][RP];
+    __shared__ T brow[TR][RP];
     __shared__ double red[4];
     const bool haveL = flags & kHaveL, doE = flags & kDoE, doHT = flags & kDoHT;
     const int4 tl = tiles[blockIdx.x];
@@ -388,7 +387,7 @@ __global__ __launch_bounds__(kThreads) void k_ht(
     const int c = tl.z + tid;
     const bool valid = c < bd.ncols;
     const int cc = valid ? c : bd.ncols - 1;
-    const int rows = min(kTileRows, bd.nrows - tl.y);
+    const int rows = min(TR, bd.nrows - tl.y);
     kcur = iter_of(kcur, st);
     double zeta = st->zeta0;
     if (kcur < P.nsched) {
@@ -403,10 +402,10 @@ __global__ __launch_bounds__(kThreads) void k_ht(
     }
 
     // all loads first
-    TB xb[kTileRows], cb[kTileRows];
+    TB xb[TR], cb[TR];
     const int64_t base = bd.off + (int64_t)tl.y * bd.ncols + cc;
 #pragma unroll
-    for (int x = 0; x < kTileRows; ++x) {
+    for (int x = 0; x < TR; ++x) {
         const int64_t e = base + (int64_t)(x < rows ? x : rows - 1) * bd.ncols;
         xb[x] = doHT ? XO[e] : TB(0.0f);
         cb[x] = doE ? Cold[e] : TB(0.0f);
@@ -420,8 +419,9 @@ __global__ __launch_bounds__(kThreads) void k_ht(
     }
     if (sf) return;
     if (haveL) {
-        if (tid < kTileRows * RP) {
-            const int x = tid / RP, p = tid % RP;
+        for (int q = tid; q < (TR * RP <= kThreads ? kThreads : TR * RP); q += kThreads) {
+            if (TR * RP <= kThreads && q >= TR * RP) break;
+            const int x = q / RP, p = q % RP;
             const int xr = tl.y + (x < rows ? x : rows - 1);
             const int64_t xi = bd.rowidx ? bd.rowidx[xr] : xr;
             brow[x][p] = Bf[P.boff[bd.mode] + xi * RP + p];
@@ -430,28 +430,26 @@ __global__ __launch_bounds__(kThreads) void k_ht(
     }
     double e2 = 0.0;
 #pragma unroll
-    for (int x = 0; x < kTileRows; ++x) {
-        // (a predicate, not a break: the loop unrolls completely, so that
-        // the row arrays stay in registers)
-        const bool rowok = x < rows;  // uniform
+    for (int x = 0; x < TR; ++x) {
+        if (x >= rows) break;  // uniform
         T L = T(0);
         if (haveL) {
 #pragma unroll
             for (int p = 0; p < RP; ++p) L = fma(brow[x][p], h[p], L);
         }
         const int64_t e = bd.off + (int64_t)(tl.y + x) * bd.ncols + c;
-        if (doE && valid && rowok) {
+        if (doE && valid) {
             const double dv = (double)(T)cb[x] - (double)L;
             e2 += dv * dv;
         }
         if (doHT) {
             const T xv = (T)xb[x];
             const T D = xv - L;
-            const bool keep = valid && rowok && fabs((double)D) > zeta;
+            const bool keep = valid && fabs((double)D) > zeta;
             const T S = keep ? D : T(0);
-            if (valid && rowok) Cnew[e] = (TB)(xv - S);
+            if (valid) Cnew[e] = (TB)(xv - S);
             const uint64_t bal = __ballot(keep);
-            if (lane == 0 && rowok && tl.z + wv * 64 < bd.ncols)
+            if (lane == 0 && tl.z + wv * 64 < bd.ncols)
                 mask[bd.moff + (int64_t)(tl.y + x) * bd.words + (tl.z >> 6) + wv] = bal;
         }
     }
@@ -701,62 +699,49 @@ __device__ void eig_tm(int sp, bool wantT, EigShared<RP>& sh) {
 // Cholesky of M's r x r block (M in LDS, row stride RP) into upper R in
 // registers, in every thread, with Rinv_jj = 1 / R_jj from one reciprocal
 // square root (no divisions); identity beyond r.  Returns false if a pivot
-// is not positive.  M's upper triangle is read up front (every LDS read in
-// flight at once); the columns j >= r, whose entries are fixed, cost a
-// uniform branch each instead of a chain of dependent operations (r is the
-// same in every thread).
+// is not positive.
 template <int RP>
 __device__ __forceinline__ bool eig_chol(const double* M, int r, double (&R)[RP][RP],
                                          double (&dinv)[RP]) {
-    double m[RP][RP];
-#pragma unroll
-    for (int j = 0; j < RP; ++j)
-#pragma unroll
-        for (int q = 0; q < RP; ++q) {
-            m[j][q] = q >= j ? M[j * RP + q] : 0.0;
-            R[j][q] = 0.0;
-        }
+    // straight-line code (selects, no branches on r) so that the LDS reads
+    // of M are not serialised
     bool ok = true;
 #pragma unroll
     for (int j = 0; j < RP; ++j) {
-        if (j < r) {
-            double d = m[j][j];
 #pragma unroll
-            for (int k = 0; k < j; ++k) d -= R[k][j] * R[k][j];
-            ok = ok && d > 0.0;
-            const double ri = rsqrt(d > 0.0 ? d : 1.0);
-            dinv[j] = ri;
-            R[j][j] = d * ri;
+        for (int q = 0; q < RP; ++q) R[j][q] = 0.0;
+    }
 #pragma unroll
-            for (int q = j + 1; q < RP; ++q) {
-                double v = m[j][q];
+    for (int j = 0; j < RP; ++j) {
+        const bool jin = j < r;
+        double d = M[j * RP + j];
 #pragma unroll
-                for (int k = 0; k < j; ++k) v -= R[k][j] * R[k][q];
-                R[j][q] = q < r ? v * ri : 0.0;
-            }
-        } else {
-            dinv[j] = 1.0;
-            R[j][j] = 1.0;
+        for (int k = 0; k < j; ++k) d -= R[k][j] * R[k][j];
+        ok = ok && (!jin || d > 0.0);
+        const double ri = rsqrt((jin && d > 0.0) ? d : 1.0);
+        dinv[j] = ri;
+        R[j][j] = jin ? d * ri : 1.0;
+#pragma unroll
+        for (int q = j + 1; q < RP; ++q) {
+            double v = M[j * RP + q];
+#pragma unroll
+            for (int k = 0; k < j; ++k) v -= R[k][j] * R[k][q];
+            R[j][q] = (jin && q < r) ? v * ri : 0.0;
         }
     }
     return ok;
 }
 
-// q = z R^-1 for this thread's row (columns r.. of z are zero, and so are
-// those of q).
+// q = z R^-1 for this thread's row.
 template <int RP>
 __device__ __forceinline__ void eig_trsm(const double (&z)[RP], const double (&R)[RP][RP],
-                                         const double (&dinv)[RP], double (&q)[RP], int r) {
+                                         const double (&dinv)[RP], double (&q)[RP]) {
 #pragma unroll
     for (int p = 0; p < RP; ++p) {
-        if (p < r) {
-            double v = z[p];
+        double v = z[p];
 #pragma unroll
-            for (int k = 0; k < p; ++k) v -= q[k] * R[k][p];
-            q[p] = v * dinv[p];
-        } else {
-            q[p] = 0.0;
-        }
+        for (int k = 0; k < p; ++k) v -= q[k] * R[k][p];
+        q[p] = v * dinv[p];
     }
 }
 
@@ -777,16 +762,14 @@ __device__ __forceinline__ void wave_sync() {
 template <int RP, bool kLds = (RP > 8)>
 struct EigChol {
     double R[RP][RP], di[RP];
-    int rk;  // the factored order
     __device__ __forceinline__ bool factor(double* M, int r, EigShared<RP>& sh) {
         (void)sh;
-        rk = r;
         return eig_chol<RP>(M, r, R, di);  // same value in every thread
     }
     __device__ __forceinline__ void solve(const double (&z)[RP], double (&q)[RP],
                                           const EigShared<RP>& sh) const {
         (void)sh;
-        eig_trsm<RP>(z, R, di, q, rk);
+        eig_trsm<RP>(z, R, di, q);
     }
 };
 
@@ -1261,12 +1244,9 @@ __device__ __forceinline__ void eig_finish_regs(const Prob& P, int i, int s, int
 #pragma unroll
             for (int j = RP - 1; j >= 0; --j) {
                 double v = j == lane ? 1.0 : 0.0;
-                if (j < r) {  // (the identity beyond r)
 #pragma unroll
-                    for (int k = j + 1; k < RP; ++k) v -= R[j][k] * x[k];
-                    v *= di[j];
-                }
-                x[j] = v;
+                for (int k = j + 1; k < RP; ++k) v -= R[j][k] * x[k];
+                x[j] = v * di[j];
             }
 #pragma unroll
             for (int j = 0; j < RP; ++j) sh.vv[j * RP + lane] = x[j];  // R^-1[j][lane]
@@ -1308,17 +1288,13 @@ __device__ __forceinline__ void eig_finish_regs(const Prob& P, int i, int s, int
     if (act) {
         // y = q T^-1: u = q R^-1, then y R^T = u
         double u[RP], y[RP];
-        eig_trsm<RP>(q, R, di, u, r);
+        eig_trsm<RP>(q, R, di, u);
 #pragma unroll
         for (int p = RP - 1; p >= 0; --p) {
-            if (p < r) {
-                double v = u[p];
+            double v = u[p];
 #pragma unroll
-                for (int k = p + 1; k < RP; ++k) v -= R[p][k] * y[k];
-                y[p] = v * di[p];
-            } else {
-                y[p] = 0.0;
-            }
+            for (int k = p + 1; k < RP; ++k) v -= R[p][k] * y[k];
+            y[p] = v * di[p];
         }
         double* Yi = Y + P.woff[i];
 #pragma unroll
@@ -2561,15 +2537,14 @@ __global__ __launch_bounds__(kThreads) void k_outliers(int d0, int64_t ncols,
     for (int p = 0; p < RP; ++p) h[p] = Hf[(int64_t)p * ncols + c];
 #pragma unroll
     for (int x = 0; x < kTileRows; ++x) {
-        if (x < rows) {  // uniform (a predicate, not a break: full unrolling)
-            T L = T(0);
+        if (x >= rows) break;  // uniform
+        T L = T(0);
 #pragma unroll
-            for (int p = 0; p < RP; ++p) L = fma(bs[x][p], h[p], L);
-            const T D = (T)xv[x] - L;
-            const int64_t e = (int64_t)(x0 + x) * ncols + c;
-            S_out[e] = (TO)(fabs((double)D) > zeta ? D : T(0));
-            if (L_out) L_out[e] = (TO)L;
-        }
+        for (int p = 0; p < RP; ++p) L = fma(bs[x][p], h[p], L);
+        const T D = (T)xv[x] - L;
+        const int64_t e = (int64_t)(x0 + x) * ncols + c;
+        S_out[e] = (TO)(fabs((double)D) > zeta ? D : T(0));
+        if (L_out) L_out[e] = (TO)L;
     }
 }
 

@@ -25,6 +25,8 @@
 #include <cstring>
 #include <memory>
 #include <string>
+#include <chrono>
+#include <map>
 #include <mutex>
 #include <vector>
 
@@ -124,6 +126,7 @@ struct Impl {
 
     // layout of the current solve
     Prob P{};
+    int ht_rows = kTileRows;        // rows per gather / threshold tile
     int64_t nblk_elems = 0;
     int64_t h_elems = 0, mask_words = 0, bf_elems = 0, w_elems = 0, z_elems = 0,
             g_elems = 0, t_elems = 0;
@@ -268,7 +271,7 @@ struct Regions {
 
 // Block descriptors, offsets and work lists for this shape; sizes the arena.
 static void plan(Impl& im, const Shape& sh, int esize, size_t idx_bytes, int max_iter,
-                 Arena& ar, Regions& rg) {
+                 const Tune& tune, Arena& ar, Regions& rg) {
     const int n = sh.n;
     Prob& P = im.P;
     std::memset(&P, 0, sizeof(P));
@@ -290,6 +293,8 @@ static void plan(Impl& im, const Shape& sh, int esize, size_t idx_bytes, int max
     for (int j = n - 2; j >= 0; --j) P.xstride[j] = P.xstride[j + 1] * sh.d[j + 1];
     int64_t off = 0, hoff = 0, moff = 0;
     im.ht_tiles.clear();
+    im.ht_rows = tune.ht_rows == 8 || tune.ht_rows == 32 ? tune.ht_rows : kTileRows;
+    if (esize == 8 && im.ht_rows == 32) im.ht_rows = kTileRows;  // (registers)
     for (int b = 0; b <= n; ++b) {
         BlockDev& bd = P.blk[b];
         if (b == 0) {
@@ -318,7 +323,7 @@ static void plan(Impl& im, const Shape& sh, int esize, size_t idx_bytes, int max
         hoff += (int64_t)RP * bd.ncols;
         moff += (int64_t)bd.nrows * bd.words;
         bd.tile0 = (int)im.ht_tiles.size();
-        for (int r0 = 0; r0 < bd.nrows; r0 += kTileRows)
+        for (int r0 = 0; r0 < bd.nrows; r0 += im.ht_rows)
             for (int c0 = 0; c0 < bd.ncols; c0 += kTileCols)
                 im.ht_tiles.push_back(make_int4(b, r0, c0, 0));
         bd.tile1 = (int)im.ht_tiles.size();
@@ -352,8 +357,15 @@ static void plan(Impl& im, const Shape& sh, int esize, size_t idx_bytes, int max
         // at least kGramMinChunk columns per chunk; at most kGramMaxKC chunks,
         // and about 1024 tiles per mode for the eigensolver to add up
         const int npi = nt * (nt + 1) / 2;
-        int nkc = (int)std::min<int64_t>(kGramMaxKC, (sh.m[i] + kGramMinChunk - 1) / kGramMinChunk);
-        nkc = std::max(1, std::min(nkc, std::max(kGramKCGroup, 1024 / npi)));
+        int nkc;
+        if (tune.gram_chunk > 0) {
+            nkc = (int)std::min<int64_t>(kGramMaxKC, (sh.m[i] + tune.gram_chunk - 1) /
+                                                         tune.gram_chunk);
+            nkc = std::max(1, nkc);
+        } else {
+            nkc = (int)std::min<int64_t>(kGramMaxKC, (sh.m[i] + kGramMinChunk - 1) / kGramMinChunk);
+            nkc = std::max(1, std::min(nkc, std::max(kGramKCGroup, 1024 / npi)));
+        }
         const int chunk = (int)align_up((size_t)((sh.m[i] + nkc - 1) / nkc), 256);
         P.gitem0[i] = (int)im.gram_items.size();
         P.gnkc[i] = nkc;
@@ -375,7 +387,8 @@ static void plan(Impl& im, const Shape& sh, int esize, size_t idx_bytes, int max
         // at most kBfacMaxKC partial rows per entry for k_bred: long modes
         // stage several Z sub-chunks per work item
         const int nsc = (int)((sh.m[i] + bkc - 1) / bkc);
-        const int nsub = (nsc + kBfacMaxKC - 1) / kBfacMaxKC;
+        const int nsub = std::min(nsc, std::max((nsc + kBfacMaxKC - 1) / kBfacMaxKC,
+                                                tune.bfac_sub));
         const int nkc = (nsc + nsub - 1) / nsub;
         P.bitem0[i] = (int)im.bfac_items.size();
         P.bnkc[i] = nkc;
@@ -520,17 +533,24 @@ struct Runner {
         return 0;
     }
 
-    int gather(const void* X, int xdt, int flags) {
-        const int nt = (int)im.ht_tiles.size();
-        HIPCHK(pb(PK_GATHER));
+    template <int TR>
+    void gather_tr(const void* X, int xdt, int flags, int nt) {
         if (xdt == RTCUR_F64)
-            hipLaunchKernelGGL((k_gather<double, TB>), dim3(nt), dim3(kThreads), 0, s,
+            hipLaunchKernelGGL((k_gather<double, TB, TR>), dim3(nt), dim3(kThreads), 0, s,
                                (const double*)X, im.P, im.d_ht_tiles, (TB*)im.XO, im.part,
                                (const DevState*)im.st, flags);
         else
-            hipLaunchKernelGGL((k_gather<float, TB>), dim3(nt), dim3(kThreads), 0, s,
+            hipLaunchKernelGGL((k_gather<float, TB, TR>), dim3(nt), dim3(kThreads), 0, s,
                                (const float*)X, im.P, im.d_ht_tiles, (TB*)im.XO, im.part,
                                (const DevState*)im.st, flags);
+    }
+
+    int gather(const void* X, int xdt, int flags) {
+        const int nt = (int)im.ht_tiles.size();
+        HIPCHK(pb(PK_GATHER));
+        if (im.ht_rows == 8) gather_tr<8>(X, xdt, flags, nt);
+        else if (im.ht_rows == 32 && sizeof(TB) <= 4) gather_tr<32>(X, xdt, flags, nt);
+        else gather_tr<kTileRows>(X, xdt, flags, nt);
         HIPCHK(hipGetLastError());
         hipLaunchKernelGGL(k_den, dim3(1), dim3(kThreads), 0, s, im.P, (const double*)im.part,
                            flags, im.st);
@@ -542,10 +562,16 @@ struct Runner {
     int ht(int kcur, int flags, const TB* Cold, TB* Cnew, uint64_t* mask, double gamma) {
         const int nt = (int)im.ht_tiles.size();
         HIPCHK(pb(PK_HT));
-        hipLaunchKernelGGL((k_ht<T, RP, TB>), dim3(nt), dim3(kThreads), 0, s, im.P,
-                           im.d_ht_tiles, (const TB*)im.XO, Cold, Cnew, mask,
-                           (const T*)im.Bf, (const T*)im.H, gamma, kcur, flags, im.hpart,
-                           im.st);
+        auto go = [&](auto tr) {
+            constexpr int TR = decltype(tr)::value;
+            hipLaunchKernelGGL((k_ht<T, RP, TB, TR>), dim3(nt), dim3(kThreads), 0, s, im.P,
+                               im.d_ht_tiles, (const TB*)im.XO, Cold, Cnew, mask,
+                               (const T*)im.Bf, (const T*)im.H, gamma, kcur, flags, im.hpart,
+                               im.st);
+        };
+        if (im.ht_rows == 8) go(std::integral_constant<int, 8>{});
+        else if (im.ht_rows == 32 && sizeof(TB) <= 4) go(std::integral_constant<int, 32>{});
+        else go(std::integral_constant<int, kTileRows>{});
         HIPCHK(hipGetLastError());
         HIPCHK(pe());
         return 0;
@@ -968,7 +994,7 @@ struct Runner {
                 // steady state from an odd j >= 3 on (C^{j-1} in C[0], every
                 // error formed): the rest of the chunk as replayed pairs, with
                 // the device's iteration count set to j - 1 first
-                if (kIterGraphs && h->prof_mask == 0 && j % 2 == 1 && j >= 3 && j >= j0 + 2 &&
+                if (h->graphs && h->prof_mask == 0 && j % 2 == 1 && j >= 3 && j >= j0 + 2 &&
                     chunk - q >= 2) {
                     hipGraphExec_t gx = nullptr;
                     if ((rc = pair_graph(gamma, tol, &gx))) return rc;
@@ -1058,25 +1084,57 @@ struct Runner {
 };
 
 // Lay out the arena for this problem and point every region into it.
-template <typename T>
-static int prepare(rtcur_s* h, Impl& im, const Shape& sh, int max_iter) {
-    IdxPack pk;
-    index_layout(sh, pk);
-    // the layout and work lists depend on the sizes only: a solve of the
-    // same sizes as the previous one on this handle reuses them
-    std::vector<int64_t> key = {sh.n, sh.chidori ? 1 : 0, (int64_t)sizeof(T), max_iter,
-                                (int64_t)pk.bytes};
+// ---------------------------------------------------------- tile autotuner
+// Process-wide table: problem sizes (and block element size) -> the tile
+// shapes the autotuner found fastest for them.
+static std::mutex g_tune_mu;
+static std::map<std::vector<int64_t>, Tune> g_tune;
+
+static std::vector<int64_t> tune_key(const Shape& sh, int esize) {
+    std::vector<int64_t> key = {sh.n, sh.chidori ? 1 : 0, esize};
     for (int i = 0; i < sh.n; ++i) {
         key.push_back(sh.d[i]);
         key.push_back(sh.r[i]);
         key.push_back(sh.s[i]);
         key.push_back(sh.m[i]);
     }
+    return key;
+}
+
+static Tune tuned_for(const Shape& sh, int esize) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(tune_key(sh, esize));
+    return it == g_tune.end() ? Tune{} : it->second;
+}
+
+void autotune_clear() {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.clear();
+}
+
+template <typename T>
+static int prepare(rtcur_s* h, Impl& im, const Shape& sh, int max_iter) {
+    IdxPack pk;
+    index_layout(sh, pk);
+    // the layout and work lists depend on the sizes and the tile shapes only:
+    // a solve of the same sizes as the previous one on this handle reuses
+    // them.  Tile shapes: the autotuner's candidate while it runs, else the
+    // caller's (rtcur_set_tiles), else the table's entry for these sizes,
+    // else the built-in rule.
+    const Tune tune = h->tune_forced     ? h->tune_force
+                      : h->tune_user_set ? h->tune_user
+                                         : tuned_for(sh, (int)sizeof(T));
+    std::vector<int64_t> key = tune_key(sh, (int)sizeof(T));
+    key.push_back(max_iter);
+    key.push_back((int64_t)pk.bytes);
+    key.push_back(tune.ht_rows);
+    key.push_back(tune.gram_chunk);
+    key.push_back(tune.bfac_sub);
     if (im.arena && key == im.plan_key) return 0;
     im.plan_key.clear();
     Arena ar;
     Regions rg;
-    plan(im, sh, sizeof(T), pk.bytes, max_iter, ar, rg);
+    plan(im, sh, sizeof(T), pk.bytes, max_iter, tune, ar, rg);
     if (ar.total > im.arena_bytes) {
         if (im.arena) HIPCHK(hipFree(im.arena));
         im.arena = nullptr;
@@ -1232,6 +1290,115 @@ int solve(rtcur_s* h, const void* X, int x_dtype, const Shape& sh, double zeta0,
     if (h->dtype == RTCUR_F64)
         return run_t<double>(h, im, X, x_dtype, sh, zeta0, gamma, tol, max_iter, seed);
     return run_t<float>(h, im, X, x_dtype, sh, zeta0, gamma, tol, max_iter, seed);
+}
+
+// Coordinate descent over the tile shapes, one at a time from the built-in
+// rule: rows per gather / threshold tile, then the Gram's column chunk, then
+// the B-factor sub-chunks; a candidate whose work lists equal one already
+// timed is skipped.  Each candidate: one warm-up solve (layout, graph
+// capture), then the best of `reps` timed solves of `iters` iterations
+// (tol 0, so every candidate does the same iterations), host wall clock.
+int autotune(rtcur_s* h, const void* X, int x_dtype, const Shape& sh, int iters, int reps,
+             uint64_t seed, Tune* best, double* best_ms, double* default_ms) {
+    const int esize = h->dtype == RTCUR_F64 ? 8 : 4;
+    int rc = 0;
+    auto time_of = [&](const Tune& t, double* ms) -> int {
+        h->tune_forced = true;
+        h->tune_force = t;
+        int r = solve(h, X, x_dtype, sh, 0.0, 0.7, 0.0, iters, seed);
+        double bt = 1e300;
+        for (int q = 0; q < reps && r >= 0; ++q) {
+            const auto t0 = std::chrono::steady_clock::now();
+            r = solve(h, X, x_dtype, sh, 0.0, 0.7, 0.0, iters, seed);
+            const double dt = std::chrono::duration<double, std::milli>(
+                                  std::chrono::steady_clock::now() - t0).count();
+            bt = std::min(bt, dt);
+        }
+        h->tune_forced = false;
+        *ms = bt;
+        return r < 0 ? r : 0;
+    };
+    // the work split a tune gives (to skip candidates equal to one timed)
+    auto gram_split = [&](const Tune& t) {
+        std::vector<int> v;
+        for (int i = 0; i < sh.n; ++i) {
+            const int nt = (int)((sh.s[i] + 15) / 16), npi = nt * (nt + 1) / 2;
+            int nkc;
+            if (t.gram_chunk > 0) {
+                nkc = std::max(1, (int)std::min<int64_t>(kGramMaxKC, (sh.m[i] + t.gram_chunk - 1) /
+                                                                         t.gram_chunk));
+            } else {
+                nkc = (int)std::min<int64_t>(kGramMaxKC, (sh.m[i] + kGramMinChunk - 1) /
+                                                             kGramMinChunk);
+                nkc = std::max(1, std::min(nkc, std::max(kGramKCGroup, 1024 / npi)));
+            }
+            v.push_back(nkc);
+        }
+        return v;
+    };
+    int rmax = 1;
+    for (int i = 0; i < sh.n; ++i) rmax = std::max(rmax, sh.r[i]);
+    const int bkc = pad_rank(rmax) <= 8 ? kBfacKC : kBfacKC / 2;
+    auto bfac_split = [&](const Tune& t) {
+        std::vector<int> v;
+        for (int i = 0; i < sh.n; ++i) {
+            const int nsc = (int)((sh.m[i] + bkc - 1) / bkc);
+            v.push_back(std::min(nsc, std::max((nsc + kBfacMaxKC - 1) / kBfacMaxKC, t.bfac_sub)));
+        }
+        return v;
+    };
+    Tune cur;
+    cur.ht_rows = kTileRows;
+    double cur_ms = 0.0;
+    if ((rc = time_of(cur, &cur_ms))) return rc;
+    *default_ms = cur_ms;
+    auto consider = [&](const Tune& t) -> int {
+        double ms = 0.0;
+        const int r = time_of(t, &ms);
+        if (r) return r;
+        if (ms < cur_ms) {
+            cur = t;
+            cur_ms = ms;
+        }
+        return 0;
+    };
+    for (int tr : {8, 32}) {
+        if (esize == 8 && tr == 32) continue;
+        Tune t = cur;
+        t.ht_rows = tr;
+        if ((rc = consider(t))) return rc;
+    }
+    {
+        std::vector<std::vector<int>> seen = {gram_split(cur)};
+        const Tune base = cur;
+        for (int c : {512, 1024, 2048, 4096, 8192}) {
+            Tune t = base;
+            t.gram_chunk = c;
+            const std::vector<int> v = gram_split(t);
+            if (std::find(seen.begin(), seen.end(), v) != seen.end()) continue;
+            seen.push_back(v);
+            if ((rc = consider(t))) return rc;
+        }
+    }
+    {
+        std::vector<std::vector<int>> seen = {bfac_split(cur)};
+        const Tune base = cur;
+        for (int b : {2, 4, 8}) {
+            Tune t = base;
+            t.bfac_sub = b;
+            const std::vector<int> v = bfac_split(t);
+            if (std::find(seen.begin(), seen.end(), v) != seen.end()) continue;
+            seen.push_back(v);
+            if ((rc = consider(t))) return rc;
+        }
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[tune_key(sh, esize)] = cur;
+    }
+    *best = cur;
+    *best_ms = cur_ms;
+    return 0;
 }
 
 // ------------------------------------------------------------ outputs

@@ -42,7 +42,9 @@ def test_graph_replays_equal_direct_launches(dtype):
              synth.tucker_plus_sparse((48, 40, 44), (4, 2, 3), alpha=0.15, seed=42)]
     hg = rt.create(0, variant="F", dtype=dtype)
     hd = rt.create(0, variant="F", dtype=dtype)
-    rt.set_profiling(hd, True)
+    rt.set_graphs(hg, True)
+    rt.set_graphs(hd, True)
+    rt.set_profiling(hd, True)   # (which turns the graphs off)
     # the first case twice (the graph replayed from the cache), then with a
     # schedule, then the second case (new sizes)
     runs = [(0, None), (0, None), (0, [0.8, 0.6, 0.5, 0.3]), (1, None)]
