@@ -11,15 +11,21 @@ Algorithm 1 until the stopping rule holds) with X already resident in HBM.
 
 Prints one JSON line.  The primary row (`value`, `ms_per_step`) is RTCUR-F
 with float32 blocks and factors (float64 Gram, eigensolver and norms), timed
-with no per-kernel events.  The float64 and bfloat16-then-float32 arms run
+with no per-kernel events, on the tile shapes the library's autotuner picks
+for this problem before the timed region (`tiles_autotuned`, with the time
+the tuning took; `--no-autotune` keeps the built-in tiles).  The float64 and
+bfloat16-then-float32 arms run
 the same number of timed solves; each arm then runs a second timed region
 with a pair of HIP events, recorded by the library on its own stream, around
 every launch of its dominant kernel only (chosen from a short pass with every
 kernel bracketed): that kernel's average launch time gives the arm's
 `roofline`.  `kernels_rocprof` is the per-kernel table of the committed
 rocprofv3 summary when it was taken on the current kernel sources.  Side
-rows: the 100^3 float64 workload, RTCUR-R, the video-shaped 4-mode workload,
-full-grid outliers and the 64-instance batch.  `cpu_baseline` times the
+rows: the primary configuration with replayed iteration graphs, the 100^3
+float64 workload, RTCUR-R, the video-shaped 4-mode workload, full-grid
+outliers, the 64-instance batch (built-in and autotuned tiles, per-instance
+solve times inside the batch) and the learned threshold schedule.
+`cpu_baseline` times the
 float64 oracle on the same 300^3 instance on the host: complete solves with
 the BLAS on every core, and a bounded run on one thread.  `--copy-calib` adds
 a plain device copy of known size after the timed region (the reference
@@ -223,6 +229,53 @@ def summarize_counters(fetch_dir, write_dir, cmds):
     return "\n".join(lines) + "\n"
 
 
+MFMA_COUNTERS = ("SQ_INSTS_VALU_MFMA_MOPS_F64", "SQ_INSTS_VALU_MFMA_MOPS_F32",
+                 "SQ_VALU_MFMA_BUSY_CYCLES", "SQ_INSTS_VALU", "SQ_INSTS_MFMA", "GRBM_GUI_ACTIVE")
+
+
+def summarize_mfma(d, cmd):
+    """Per-kernel matrix-core use from one rocprofv3 --pmc run of
+    MFMA_COUNTERS: MFMA flops per launch (MOPS x 512, padding included), all
+    VALU and MFMA instructions, the raw matrix-core busy and GPU-active
+    cycle counts; with the kernel trace summary's average launch time, the
+    achieved float64 matrix-core rate."""
+    import csv
+    import glob
+    path = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if not path:
+        raise SystemExit(f"no counter_collection.csv under {d}")
+    per = {}
+    for r in csv.DictReader(open(path[0])):
+        name = r["Kernel_Name"]
+        if "rtcur::" not in name or r["Counter_Name"] not in MFMA_COUNTERS:
+            continue
+        k = short_name(name)
+        per.setdefault(k, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    avg_us = {}
+    table = read_rocprof_table(source_digest()) or {}
+    for k, v in table.items():
+        avg_us[k] = v["avg_us"]
+    lines = ["# rocprofv3 --pmc " + " ".join(MFMA_COUNTERS) + " (per dispatch),",
+             "# RTCUR-F on the 300^3 float32 rank-5 instance",
+             f"# command: {cmd}",
+             f"source_digest: {source_digest()}",
+             "# kernel: dispatches, f64 MFMA flops/launch, f32 MFMA flops/launch, "
+             "MFMA instr/launch, VALU instr/launch, SQ_VALU_MFMA_BUSY_CYCLES/launch, "
+             "GRBM_GUI_ACTIVE/launch, f64 MFMA TFLOP/s at the trace's average launch time"]
+    for k in sorted(per):
+        c = per[k]
+        mean = {n: sum(v) / len(v) for n, v in c.items()}
+        n = len(c.get("SQ_INSTS_VALU", c.get(MFMA_COUNTERS[0], [0])))
+        f64 = 512.0 * mean.get("SQ_INSTS_VALU_MFMA_MOPS_F64", 0.0)
+        f32 = 512.0 * mean.get("SQ_INSTS_VALU_MFMA_MOPS_F32", 0.0)
+        busy = mean.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0)
+        act = mean.get("GRBM_GUI_ACTIVE", 0.0)
+        rate = f64 / (avg_us[k] * 1e-6) / 1e12 if k in avg_us and avg_us[k] > 0 else float("nan")
+        lines.append(f"mfma.{k}: {n} {f64:.4g} {f32:.4g} {mean.get('SQ_INSTS_MFMA', 0.0):.4g} "
+                     f"{mean.get('SQ_INSTS_VALU', 0.0):.4g} {busy:.4g} {act:.4g} {rate:.4g}")
+    return "\n".join(lines) + "\n"
+
+
 def read_rocprof_table(digest):
     """{kernel: {calls, avg_us, share}} from the committed rocprofv3 kernel
     trace summary of this workload, when it was taken on the current kernel
@@ -277,32 +330,31 @@ def cpu_info():
 def learned_schedule_row(rt, torch, np, synth, steps, ntrain, nsolve):
     """Learn the 15 threshold multipliers c_k = zeta_k / zeta_0 of RTCUR-F
     by gradient descent through the library's differentiable unrolled pass
-    (K = 15 iterations, gate temperature 0.05), on seeded instances of the
-    200^3 rank-5 alpha-0.3 recipe; the loss is the relative error of L^15
-    against the planted low-rank part on the sampled blocks.  Then solve
-    held-out instances to tol 1e-5 with the learned multipliers (the decay
-    by gamma = 0.7 continues after them) and with the geometric schedule,
-    and time both."""
+    (K = 15 iterations, gate temperature 0.05): `steps` Adam steps, each on
+    one instance drawn (seeded) from a pool of `ntrain` seeded instances of
+    the 200^3 rank-5 alpha-0.3 recipe, drawn on the device; the loss is the
+    relative error of L^15 against the planted low-rank part on the sampled
+    blocks.  Then solve held-out instances (the host recipe, seeds 5000..)
+    to tol 1e-5 with the learned multipliers (the decay by gamma = 0.7
+    continues after them) and with the geometric schedule, and time both."""
     from paper_2108_10448_amd.unrolled import UnrolledRTCUR
     K, tau, gamma = 15, 0.05, 0.7
     dims, ranks, alpha = (200, 200, 200), (5, 5, 5), 0.3
     I, _ = synth.sample_sizes(dims, ranks, 3.0)
-    log(f"learned schedule: {ntrain} training instances, {steps} steps")
+    log(f"learned schedule: {steps} steps over a pool of {ntrain} training instances")
     plan = rt.unroll_plan(dims, ranks, I, K=K, seed=0)
-    idx = plan.block_index()
-    data = []
-    for j in range(ntrain):
-        inst = synth.tucker_plus_sparse(dims, ranks, alpha, seed=1000 + j, storage=np.float32)
-        data.append((torch.from_numpy(inst.X), torch.from_numpy(inst.L_star.reshape(-1)[idx])))
+    idx = torch.from_numpy(plan.block_index()).to("cuda:0")
+    pick = np.random.default_rng(12345).integers(0, ntrain, size=steps)
     theta = torch.tensor([(k + 1) * math.log(gamma) for k in range(K)], dtype=torch.float64,
                          requires_grad=True)
     opt = torch.optim.Adam([theta], lr=0.05)
     losses = []
     t0 = time.perf_counter()
     for step in range(steps):
-        Xh, Lh = data[step % ntrain]
-        X = Xh.to("cuda:0")
-        Ls = Lh.to("cuda:0")
+        X, Lfull = synth.tucker_plus_sparse_device(dims, ranks, alpha, 1000 + int(pick[step]),
+                                                   "cuda:0")
+        Ls = Lfull.reshape(-1)[idx]
+        del Lfull
         zeta0 = float(X.abs().max())
         L = UnrolledRTCUR.apply(X, zeta0 * torch.exp(theta), plan, tau)
         loss = ((L - Ls) ** 2).sum() / (Ls ** 2).sum()
@@ -337,7 +389,10 @@ def learned_schedule_row(rt, torch, np, synth, steps, ntrain, nsolve):
     out = {"workload": "200^3 float32 storage, rank (5,5,5), alpha 0.3, RTCUR-F, chidori "
                        f"|I_i|={I[0]}, K=15 unrolled, gate tau={tau}; loss ||L^15 - L*||^2 / "
                        "||L*||^2 on the sampled blocks",
-           "train_instances": ntrain, "steps": steps, "train_s": t_train,
+           "train_pool": ntrain, "train_draw": "one instance per step, seeded draw from "
+                                                 "the pool (device recipe, seeds 1000..)",
+           "distinct_instances_seen": int(len(set(pick.tolist()))),
+           "steps": steps, "train_s": t_train,
            "ms_per_step": 1e3 * t_train / max(1, steps),
            "loss_first": losses[0] if losses else None,
            "loss_last5_mean": float(np.mean(losses[-5:])) if losses else None,
@@ -349,12 +404,16 @@ def learned_schedule_row(rt, torch, np, synth, steps, ntrain, nsolve):
 
 
 def main():
-    if len(sys.argv) > 1 and sys.argv[1] in ("--summarize-trace", "--summarize-counters"):
+    if len(sys.argv) > 1 and sys.argv[1] in ("--summarize-trace", "--summarize-counters",
+                                             "--summarize-mfma"):
         # host-side: turn rocprofv3 output into the text summaries under profiles/
         mode, args = sys.argv[1], sys.argv[2:]
         if mode == "--summarize-trace":
             d, out, cmd = args[0], args[1], args[2]
             text = summarize_trace(d, cmd)
+        elif mode == "--summarize-mfma":
+            d, out, cmd = args[0], args[1], args[2]
+            text = summarize_mfma(d, cmd)
         else:
             fd, wd, out, c1, c2 = args[:5]
             text = summarize_counters(fd, wd, (c1, c2))
@@ -373,16 +432,18 @@ def main():
                     help="timed solves for the side rows (0: skip them)")
     ap.add_argument("--no-arms", action="store_true",
                     help="skip the float64 and bfloat16 arms")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="built-in tile shapes instead of the autotuner's for the 300^3 arms")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 64-instance batch side row")
     ap.add_argument("--no-video", action="store_true",
                     help="skip the video-shaped 4-mode side rows")
     ap.add_argument("--copy-calib", action="store_true",
                     help="run a plain 1 GiB device copy after the timed region")
-    ap.add_argument("--learn-steps", type=int, default=60,
+    ap.add_argument("--learn-steps", type=int, default=200,
                     help="Adam steps of the learned threshold schedule (0: skip the row)")
-    ap.add_argument("--learn-instances", type=int, default=16,
-                    help="seeded 200^3 training instances of the learned schedule")
+    ap.add_argument("--learn-instances", type=int, default=512,
+                    help="pool of seeded 200^3 training instances of the learned schedule")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: RTCUR's hot loop is measured on a "
@@ -447,8 +508,18 @@ def main():
         out["traffic"] = read_traffic(dom, digest) if dtype == torch.float32 else None
         return out
 
+    tuned = {}
+
     def arm(dtype, name, steps, warmup, with_roofline=True):
         h = rt.create(0, variant="F", dtype=dtype)
+        if not args.no_autotune:
+            # the tile shapes for this problem from the library's autotuner
+            # (timed before, and outside, the measured solves)
+            t0 = time.perf_counter()
+            got = rt.autotune(h, X, ranks, I, iters=8, reps=3)
+            got["autotune_s"] = time.perf_counter() - t0
+            tuned[name] = got
+            log(f"{name}: autotuned tiles {got}")
         for _ in range(warmup):
             rt.solve(h, X, ranks, I, tol=1e-5, gamma=0.7, max_iter=100, seed=0)
         log(f"timing RTCUR-F {name}: {steps} solves, no events")
@@ -505,11 +576,12 @@ def main():
 
     rows = {}
 
-    def side(variant, dtype, name, Xs=None, inst_=None, I_=None):
+    def side(variant, dtype, name, Xs=None, inst_=None, I_=None, graphs=False):
         Xs = X if Xs is None else Xs
         inst_ = inst if inst_ is None else inst_
         I_ = I if I_ is None else I_
         hh = rt.create(0, variant=variant, dtype=dtype)
+        rt.set_graphs(hh, graphs)
         inf, ts = time_solves(rt, torch, hh, Xs, list(inst_.ranks), I_, args.side_steps, 1)
         Lr = rt.reconstruct(hh)
         Ls_ = torch.from_numpy(inst_.L_star).to("cuda:0")
@@ -523,6 +595,8 @@ def main():
         log(f"{name}: {rows[name]}")
 
     if args.side_steps > 0:
+        # the primary configuration with replayed iteration graphs (opt-in)
+        side("F", torch.float32, "F_f32_graphs", graphs=True)
         side("R", torch.float32, "R_f32")
         side("R", torch.float64, "R_f64")
         # the 100^3 float64 workload (rank 3, alpha 0.2, |I_i| = 42)
@@ -724,6 +798,7 @@ def main():
         "true_rel_err": prim["true_rel_err"],
         "eig_steps_per_solve": prim["eig_steps_per_solve"],
         "roofline": prim["roofline"],
+        "tiles_autotuned": tuned or None,
         "arms": arms,
         "variants": rows,
         "outliers_full_grid": outlier_row,

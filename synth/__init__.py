@@ -93,6 +93,31 @@ def tucker_plus_sparse(dims: Sequence[int], ranks: Sequence[int], alpha: float,
     return Instance(X, L, S, dims, ranks, alpha, seed, meta)
 
 
+def tucker_plus_sparse_device(dims: Sequence[int], ranks: Sequence[int], alpha: float,
+                              seed: int, device, c: float = 1.0):
+    """The recipe of tucker_plus_sparse drawn with torch on `device` (for
+    training sets too large to draw on the host): N(0,1) core, QR-orthonormal
+    N(0,1) factors, Bernoulli(alpha) support, values U[-amp, amp] with
+    amp = c mean|L*|, in that order from one torch.Generator seeded with
+    `seed` (a different stream of numbers than numpy's for the same seed).
+    Returns (X float32, L* float64) on the device."""
+    import torch
+    dims = tuple(int(d) for d in dims)
+    ranks = tuple(int(r) for r in ranks)
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    f64 = torch.float64
+    L = torch.randn(ranks, generator=g, device=device, dtype=f64)
+    for k, (d, r) in enumerate(zip(dims, ranks)):
+        U = torch.linalg.qr(torch.randn((d, r), generator=g, device=device, dtype=f64))[0]
+        L = torch.movedim(torch.tensordot(U, L, dims=([1], [k])), 0, k)
+    mask = torch.rand(dims, generator=g, device=device, dtype=f64) < alpha
+    amp = c * float(L.abs().mean())
+    vals = (torch.rand(dims, generator=g, device=device, dtype=f64) * 2.0 - 1.0) * amp
+    X = (L + torch.where(mask, vals, torch.zeros_like(vals))).to(torch.float32)
+    return X, L
+
+
 def video_like(dims: Sequence[int] = (240, 320, 3, 400),
                ranks: Sequence[int] = (10, 10, 3, 5), n_rects: int = 40,
                side: tuple = (20, 60), coverage: float = 0.05, seed: int = 0,

@@ -40,3 +40,23 @@ def test_video_like_recipe():
     cov = float(np.mean(occ[:, :, 0, :]))
     assert abs(cov - v.meta["coverage"]) < 1e-12
     assert 0.035 < cov < 0.065
+
+
+def test_device_recipe_matches_the_host_recipe_in_distribution():
+    # the torch-drawn variant (on the CPU here): exact multilinear rank,
+    # orthonormal-factor scale, Bernoulli(alpha) support, values within amp,
+    # reproducible per seed
+    import torch
+    X, L = synth.tucker_plus_sparse_device((30, 28, 26), (3, 2, 4), 0.25, seed=7, device="cpu")
+    assert X.dtype == torch.float32 and L.dtype == torch.float64 and X.shape == (30, 28, 26)
+    Ln = L.numpy()
+    for k, r in enumerate((3, 2, 4)):
+        sv = np.linalg.svd(np.moveaxis(Ln, k, 0).reshape(Ln.shape[k], -1), compute_uv=False)
+        assert sv[r - 1] > 1e-8 * sv[0] and sv[r] < 1e-12 * sv[0]
+    S = X.double().numpy() - Ln
+    supp = np.abs(S) > 1e-5 * np.abs(Ln).mean()
+    assert abs(supp.mean() - 0.25) < 0.02
+    amp = np.abs(Ln).mean()
+    assert np.abs(S).max() <= amp * (1 + 1e-6) + 1e-6
+    X2, _ = synth.tucker_plus_sparse_device((30, 28, 26), (3, 2, 4), 0.25, seed=7, device="cpu")
+    assert torch.equal(X, X2)
