@@ -114,7 +114,8 @@ def tucker_plus_sparse_device(dims: Sequence[int], ranks: Sequence[int], alpha: 
     mask = torch.rand(dims, generator=g, device=device, dtype=f64) < alpha
     amp = c * float(L.abs().mean())
     vals = (torch.rand(dims, generator=g, device=device, dtype=f64) * 2.0 - 1.0) * amp
-    X = (L + torch.where(mask, vals, torch.zeros_like(vals))).to(torch.float32)
+    L = L.contiguous()
+    X = (L + torch.where(mask, vals, torch.zeros_like(vals))).to(torch.float32).contiguous()
     return X, L
 
 

@@ -49,6 +49,7 @@ def test_device_recipe_matches_the_host_recipe_in_distribution():
     import torch
     X, L = synth.tucker_plus_sparse_device((30, 28, 26), (3, 2, 4), 0.25, seed=7, device="cpu")
     assert X.dtype == torch.float32 and L.dtype == torch.float64 and X.shape == (30, 28, 26)
+    assert X.is_contiguous() and L.is_contiguous()
     Ln = L.numpy()
     for k, r in enumerate((3, 2, 4)):
         sv = np.linalg.svd(np.moveaxis(Ln, k, 0).reshape(Ln.shape[k], -1), compute_uv=False)
