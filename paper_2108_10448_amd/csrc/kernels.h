@@ -1694,12 +1694,12 @@ __global__ __launch_bounds__(kThreads) void k_eig(Prob P, const double* __restri
 // --------------------------- Z_i = Y_i^T U_i  and the core's first phase
 // Workgroups [0, nz): Z_i (m_i x RP, float64, row per column) with
 // U_i = C_i(I_i, :), so that V_i S_i^-1 = Z_i; 64 columns per workgroup,
-// four adjacent lanes per column each summing a quarter of the s_i rows.
+// one per lane, each wave summing a quarter of the s_i rows.
 // Workgroups [nz, nz + s_0): T[a] = R(a, :, ..) x_{l >= 1} W_l^T, the core
 // G = R x_i W_i^T before its last contraction (with W_0, done by k_hexp).
 template <typename T, int RP>
 __device__ void zmat_tile(const Prob& P, const T* __restrict__ C, const double* __restrict__ Y,
-                          double* __restrict__ Zbuf, int2 tl, double* ys, int sf) {
+                          double* __restrict__ Zbuf, int2 tl, double* ys, double* red, int sf) {
     const int i = tl.x;
     const BlockDev& bd = P.blk[1 + i];
     const int s = P.s[i], m = bd.ncols;
@@ -1707,42 +1707,46 @@ __device__ void zmat_tile(const Prob& P, const T* __restrict__ C, const double* 
     for (int e = threadIdx.x; e < s * RP; e += kThreads) ys[e] = Yi[e];
     if (sf) return;
     __syncthreads();
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int quarter = lane & 3;
-    const int c = tl.y + w * 16 + (lane >> 2);
+    // lane = column (64 per workgroup: each row's loads are one coalesced
+    // 64-column segment per wave), wave = a quarter of the rows of U_i (its
+    // row index is uniform: a scalar load); the four waves' partial sums are
+    // added in wave order through LDS
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // (wave-uniform)
+    const int c = tl.y + lane;
     const int cc = c < m ? c : m - 1;
     const int qlen = (s + 3) / 4;
-    const int a0 = quarter * qlen;
+    const int a0 = w * qlen, a1 = min(s, a0 + qlen);
     const int32_t* Ii = P.I[i];
     const T* base = C + bd.off + cc;
     double acc[RP];
 #pragma unroll
     for (int p = 0; p < RP; ++p) acc[p] = 0.0;
     constexpr int U = 16;
-    for (int b0 = 0; b0 < qlen; b0 += U) {
+    for (int b0 = a0; b0 < a1; b0 += U) {
         T u[U];
 #pragma unroll
         for (int q = 0; q < U; ++q) {
-            int a = a0 + b0 + q;
-            a = (b0 + q < qlen && a < s) ? a : a0;
-            u[q] = base[(int64_t)Ii[a < s ? a : s - 1] * m];
+            const int a = b0 + q < a1 ? b0 + q : a0;  // (masked below)
+            u[q] = base[(int64_t)Ii[a] * m];
         }
 #pragma unroll
         for (int q = 0; q < U; ++q) {
-            const int a = a0 + b0 + q;
-            if (b0 + q < qlen && a < s) {
+            if (b0 + q < a1) {  // uniform
                 const double uv = (double)u[q];
 #pragma unroll
-                for (int p = 0; p < RP; ++p) acc[p] = fma(uv, ys[a * RP + p], acc[p]);
+                for (int p = 0; p < RP; ++p) acc[p] = fma(uv, ys[(b0 + q) * RP + p], acc[p]);
             }
         }
     }
 #pragma unroll
-    for (int p = 0; p < RP; ++p) acc[p] = quad_sum(acc[p]);
-    if (quarter == 0 && c < m) {
-        double* Zi = Zbuf + P.zoff[i] + (int64_t)c * RP;
-#pragma unroll
-        for (int p = 0; p < RP; ++p) Zi[p] = acc[p];
+    for (int p = 0; p < RP; ++p) red[(w * RP + p) * 64 + lane] = acc[p];
+    __syncthreads();
+    for (int e = threadIdx.x; e < 64 * RP; e += kThreads) {
+        const int col = e & 63, p = e >> 6;
+        const double z = ((red[p * 64 + col] + red[(RP + p) * 64 + col]) +
+                          red[(2 * RP + p) * 64 + col]) + red[(3 * RP + p) * 64 + col];
+        if (tl.y + col < m) Zbuf[P.zoff[i] + (int64_t)(tl.y + col) * RP + p] = z;
     }
 }
 
@@ -1973,7 +1977,7 @@ __global__ __launch_bounds__(kThreads) void k_zcore(Prob P, const T* __restrict_
     static_assert(kSliceBytes <= (int)sizeof(double) * kCoreLds / 2, "staging fits");
     T* rs = reinterpret_cast<T*>(buf + kCoreLds / 2);
     if ((int)blockIdx.x < nz) {
-        zmat_tile<T, RP>(P, C, Y, Zbuf, ztiles[blockIdx.x], sh, sf);
+        zmat_tile<T, RP>(P, C, Y, Zbuf, ztiles[blockIdx.x], sh, buf, sf);
         return;
     }
     core_slice<T, RP>(P, C + P.blk[0].off, W, Tbuf, (int)blockIdx.x - nz, buf, sh, rs, sf);
