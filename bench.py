@@ -368,7 +368,7 @@ def learned_schedule_row(rt, torch, np, synth, steps, ntrain, nsolve):
     geo = np.array([gamma ** (k + 1) for k in range(K)])
     # held-out comparison on the real solver
     rows = []
-    for j in range(2):
+    for j in range(4):
         inst = synth.tucker_plus_sparse(dims, ranks, alpha, seed=5000 + j, storage=np.float32)
         X = torch.from_numpy(inst.X).to("cuda:0")
         Ls = torch.from_numpy(inst.L_star).to("cuda:0")
@@ -398,7 +398,13 @@ def learned_schedule_row(rt, torch, np, synth, steps, ntrain, nsolve):
            "loss_last5_mean": float(np.mean(losses[-5:])) if losses else None,
            "multipliers_learned": [float(v) for v in mult],
            "multipliers_geometric": [float(v) for v in geo],
-           "held_out": rows}
+           "held_out": rows,
+           "held_out_iters_mean": {
+               name: float(np.mean([r[name]["iters"] for r in rows])) for name in ("geometric",
+                                                                                  "learned")},
+           "held_out_time_ms_mean": {
+               name: float(np.mean([r[name]["time_to_tol_ms_p50"] for r in rows]))
+               for name in ("geometric", "learned")}}
     log(f"learned schedule: {out}")
     return out
 
@@ -657,7 +663,7 @@ def main():
             rb.append(sp["ranks"])
             sb.append(sp["seed"])
             del ib
-        # handle count: 2, 4 and 8 handles on their own streams with the
+        # handle count: 2, 4, 8 and 16 handles on their own streams with the
         # built-in tiles; the fastest is kept for the tuned run
         def rate_with(k):
             sts = [torch.cuda.Stream() for _ in range(k)]
@@ -672,7 +678,7 @@ def main():
                 rt.destroy(hh)
             return dt
         rt.autotune_clear()
-        by_handles = {k: rate_with(k) for k in (2, 4, 8)}
+        by_handles = {k: rate_with(k) for k in (2, 4, 8, 16)}
         nh = min(by_handles, key=by_handles.get)
         streams = [torch.cuda.Stream() for _ in range(nh)]
         hs = [rt.create(0, stream=st, dtype=torch.float32) for st in streams]

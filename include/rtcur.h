@@ -162,10 +162,13 @@ int rtcur_outliers(rtcur_t h, const void* X, int x_dtype, double zeta, void* S_o
  * ranks), solved concurrently: each of the nh handles is driven by its own
  * host thread, so handles bound to distinct streams overlap their kernels on
  * the device.  Schedule: one work queue holds the instances in decreasing
- * number of entries (ties: lower j first); each handle's thread takes the
- * next instance whenever its previous solve has returned, so that slow
- * instances (many iterations or eigensolver steps) do not hold back the
- * others.  Which handle solves which instance depends on timing; infos[j]
+ * expected cost (ties: lower j first) -- the solve times this process last
+ * measured in a batch for the same problem (sizes, ranks, sample sizes, the
+ * first handle's compute dtype and variant, gamma, tol, max_iter) when every
+ * instance has one, else the number of entries; each handle's thread takes
+ * the next instance whenever its previous solve has returned, so that slow
+ * instances (many iterations or eigensolver steps) start first and do not
+ * hold back the others.  Which handle solves which instance depends on timing; infos[j]
  * records it (batch_slot, batch_seq).  Each instance is Algorithm 1 exactly
  * as rtcur_solve runs it (same results bit for bit, whichever handle runs
  * it).

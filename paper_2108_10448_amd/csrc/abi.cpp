@@ -8,6 +8,8 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <map>
+#include <mutex>
 #include <thread>
 #include <vector>
 
@@ -174,6 +176,30 @@ int rtcur_outliers(rtcur_t h, const void* X, int x_dtype, double zeta, void* S_o
     return rtcur::outliers(h, X, x_dtype, zeta, S_out, L_out, out_dtype);
 }
 
+// Solve times of batch instances, by problem: the batch queue's order.
+static std::mutex g_batch_mu;
+static std::map<std::vector<int64_t>, double> g_batch_ms;
+
+static std::vector<int64_t> batch_key(rtcur_t h, int32_t j, int x_dtype, const int32_t* n,
+                                      const int64_t* dims, const int32_t* ranks,
+                                      const int64_t* I_sizes, const int64_t* J_sizes,
+                                      double gamma, double tol, int32_t max_iter) {
+    std::vector<int64_t> k = {h->dtype, h->variant, x_dtype, n[j], max_iter, J_sizes ? 1 : 0};
+    int64_t tb, gb;
+    std::memcpy(&tb, &tol, sizeof(tb));
+    std::memcpy(&gb, &gamma, sizeof(gb));
+    k.push_back(tb);
+    k.push_back(gb);
+    for (int32_t q = 0; q < n[j] && q < rtcur::kMaxModes; ++q) {
+        const int64_t o = (int64_t)j * rtcur::kMaxModes + q;
+        k.push_back(dims[o]);
+        k.push_back(ranks[o]);
+        k.push_back(I_sizes[o]);
+        if (J_sizes) k.push_back(J_sizes[o]);
+    }
+    return k;
+}
+
 int rtcur_solve_batch(rtcur_t* hs, int32_t nh, int32_t count, const void* const* X,
                       int x_dtype, const int32_t* n, const int64_t* dims,
                       const int32_t* ranks, const int64_t* I_sizes, const int64_t* J_sizes,
@@ -211,9 +237,31 @@ int rtcur_solve_batch(rtcur_t* hs, int32_t nh, int32_t count, const void* const*
             v *= (double)dims[(int64_t)j * rtcur::kMaxModes + q];
         return v;
     };
+    // expected cost, longest first: the solve times last measured in this
+    // process for the same problem (sizes, ranks, sample sizes, the first
+    // handle's compute dtype and variant, gamma, tol, max_iter) when every
+    // instance has one, else the number of entries
+    std::vector<std::vector<int64_t>> keys;
+    std::vector<double> cost;
     try {
+        keys.resize(count);
+        cost.resize(count);
+        for (int32_t j = 0; j < count; ++j)
+            keys[j] = batch_key(hs[0], j, x_dtype, n, dims, ranks, I_sizes, J_sizes, gamma, tol,
+                                max_iter);
+        bool all = count > 0;
+        {
+            std::lock_guard<std::mutex> lk(g_batch_mu);
+            for (int32_t j = 0; j < count; ++j) {
+                auto it = g_batch_ms.find(keys[j]);
+                if (it == g_batch_ms.end()) all = false;
+                else cost[j] = it->second;
+            }
+        }
+        if (!all)
+            for (int32_t j = 0; j < count; ++j) cost[j] = entries(j);
         std::stable_sort(order.begin(), order.end(),
-                         [&](int32_t x, int32_t y) { return entries(x) > entries(y); });
+                         [&](int32_t x, int32_t y) { return cost[x] > cost[y]; });
     } catch (...) {
         return RTCUR_E_NOMEM;  // before any solve started
     }
@@ -237,6 +285,14 @@ int rtcur_solve_batch(rtcur_t* hs, int32_t nh, int32_t count, const void* const*
             inf.batch_slot = t;
             inf.batch_seq = seq;
             if (infos) infos[j] = inf;
+            if (rc >= 0) {
+                try {
+                    std::lock_guard<std::mutex> lk(g_batch_mu);
+                    g_batch_ms[keys[j]] = inf.solve_ms;
+                } catch (...) {
+                    // (the cost record is an optimisation of the order only)
+                }
+            }
         }
     };
     // Handles whose thread cannot be started run their lists on the calling
