@@ -61,6 +61,8 @@ struct rtcur_unroll_s {
            *Ab[3] = {nullptr, nullptr, nullptr};
     double *Rbar = nullptr, *zpart = nullptr;
     int* flag = nullptr;         // rank-test status of the forward pass
+    double* sk = nullptr;        // split-K partial tiles (grown on demand)
+    size_t sk_bytes = 0;
     int nzp = 0;
     std::vector<double> zhost;
 };
@@ -85,14 +87,49 @@ unsigned grid_for(int64_t n) {
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>(4096, (n + kT - 1) / kT));
 }
 
-// C = alpha op(A) op(B) + beta C (see k_gemm), optionally batched
+// C = alpha op(A) op(B) + beta C (see k_gemm), optionally batched.  A long
+// K over few output tiles is split into slices (about 512 workgroups in all,
+// at least 256 columns each) whose partial tiles k_splitk_sum adds in order.
 int gemm(rtcur_unroll_s* u, int M, int N, int Kd, double alpha, const double* A, int64_t lda,
          bool ta, const double* B, int64_t ldb, bool tb, double beta, double* C, int64_t ldc,
          int batch = 1, int64_t sa = 0, int64_t sb = 0, int64_t sc = 0) {
     if (M <= 0 || N <= 0) return 0;
+    const int64_t tiles = (int64_t)((N + 31) / 32) * ((M + 31) / 32) * batch;
+    int ksplit = 1;
+    if (tiles < 256 && Kd >= 512)
+        ksplit = (int)std::max<int64_t>(1, std::min<int64_t>(Kd / 256, 512 / tiles));
+    const int kper = ksplit > 1 ? ((Kd + ksplit - 1) / ksplit + 15) / 16 * 16 : Kd;
+    if (ksplit > 1) ksplit = (Kd + kper - 1) / kper;  // (no empty slice)
+    if (ksplit > 1) {
+        const size_t need = sizeof(double) * (size_t)M * N * batch * ksplit;
+        if (need > u->sk_bytes) {
+            if (u->sk) {
+                UCHK(hipStreamSynchronize(u->stream));  // (earlier slices may still read it)
+                UCHK(hipFree(u->sk));
+            }
+            u->sk = nullptr;
+            u->sk_bytes = 0;
+            if (hipMalloc(reinterpret_cast<void**>(&u->sk), need) != hipSuccess) {
+                (void)hipGetLastError();
+                return ufail(u, RTCUR_E_NOMEM, "split-K workspace allocation failed");
+            }
+            u->sk_bytes = need;
+        }
+        dim3 grid((unsigned)((N + 31) / 32), (unsigned)((M + 31) / 32),
+                  (unsigned)(batch * ksplit));
+        hipLaunchKernelGGL(k_gemm, grid, dim3(kT), 0, u->stream, M, N, Kd, 1.0, A, lda, sa,
+                           ta ? 1 : 0, B, ldb, sb, tb ? 1 : 0, 0.0, u->sk, (int64_t)N,
+                           (int64_t)M * N, ksplit, kper);
+        UCHK(hipGetLastError());
+        hipLaunchKernelGGL(k_splitk_sum, dim3(grid_for((int64_t)M * N * batch)), dim3(kT), 0,
+                           u->stream, M, N, batch, ksplit, (const double*)u->sk, alpha, beta, C,
+                           ldc, sc);
+        UCHK(hipGetLastError());
+        return 0;
+    }
     dim3 grid((unsigned)((N + 31) / 32), (unsigned)((M + 31) / 32), (unsigned)batch);
     hipLaunchKernelGGL(k_gemm, grid, dim3(kT), 0, u->stream, M, N, Kd, alpha, A, lda, sa,
-                       ta ? 1 : 0, B, ldb, sb, tb ? 1 : 0, beta, C, ldc, sc);
+                       ta ? 1 : 0, B, ldb, sb, tb ? 1 : 0, beta, C, ldc, sc, 1, Kd);
     UCHK(hipGetLastError());
     return 0;
 }
@@ -220,6 +257,23 @@ int lupdate(rtcur_unroll_s* u, int k) {
                        u->G + (int64_t)i * kJacMax * kJacMax, s)))
             return rc;
     }
+    // From the second iteration on, each Gram is first expressed in the
+    // previous iteration's eigenbasis (V^T G V, nearly diagonal: the Grams
+    // change little from one iteration to the next), so that the Jacobi
+    // sweeps start from a nearly diagonal matrix and stop after a few; the
+    // eigenvectors are rotated back afterwards.  Same eigenpairs up to
+    // rounding.
+    const bool warm = k >= 2;
+    if (warm) {
+        for (int i = 0; i < 3; ++i) {
+            const int s = u->s[i];
+            double* Gi = u->G + (int64_t)i * kJacMax * kJacMax;
+            const double* Vp = ck_V(u, k - 1, i);
+            if ((rc = gemm(u, s, s, s, 1.0, Gi, s, false, Vp, s, false, 0.0, u->Wa, s)) ||
+                (rc = gemm(u, s, s, s, 1.0, Vp, s, true, u->Wa, s, false, 0.0, Gi, s)))
+                return rc;
+        }
+    }
     // one workgroup per mode (equal s: one launch; else one per mode)
     const size_t lds = sizeof(double) * 2 * kJacMax * (kJacMax + 1);
     const bool same = u->s[0] == u->s[1] && u->s[1] == u->s[2];
@@ -227,11 +281,22 @@ int lupdate(rtcur_unroll_s* u, int k) {
         const int nm = same ? 3 : 1;
         // eigenpairs straight into checkpoint k (slots kJacMax^2 and kJacMax
         // apart; one launch covers the three modes when their sizes agree)
-        hipLaunchKernelGGL(k_jacobi, dim3(nm), dim3(kT), lds, u->stream,
+        hipLaunchKernelGGL(k_jacobi, dim3(nm), dim3(kJT), lds, u->stream,
                            u->G + (int64_t)i * kJacMax * kJacMax, (int64_t)kJacMax * kJacMax,
                            u->s[i], ck_lam(u, k, i), (int64_t)kJacMax, ck_V(u, k, i),
                            (int64_t)kJacMax * kJacMax);
         UCHK(hipGetLastError());
+    }
+    if (warm) {
+        for (int i = 0; i < 3; ++i) {
+            const int s = u->s[i];
+            double* Vk = ck_V(u, k, i);
+            if ((rc = gemm(u, s, s, s, 1.0, ck_V(u, k - 1, i), s, false, Vk, s, false, 0.0, u->Wb,
+                           s)))
+                return rc;
+            UCHK(hipMemcpyAsync(Vk, u->Wb, sizeof(double) * s * s, hipMemcpyDeviceToDevice,
+                                u->stream));
+        }
     }
     for (int i = 0; i < 3; ++i) {
         const int s = u->s[i];
@@ -305,6 +370,9 @@ int eval_adjoint_block(rtcur_unroll_s* u, int k, int i, const double* F, int row
 int release(rtcur_unroll_s* u) {
     if (u->arena) (void)hipFree(u->arena);
     u->arena = nullptr;
+    if (u->sk) (void)hipFree(u->sk);
+    u->sk = nullptr;
+    u->sk_bytes = 0;
     return 0;
 }
 

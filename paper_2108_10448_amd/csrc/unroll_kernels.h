@@ -34,35 +34,42 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 // operand tile loaded along its contiguous index).  Lane l feeds A row l%16
 // at k = l/16 and B column l%16 at k = l/16; accumulator register v of lane
 // l is row 4v + l/16, column l%16.
+// With ksplit > 1 (long K, few output tiles): blockIdx.z = batch * ksplit +
+// slice; the workgroup sums slice `slice` of K (kper columns, a multiple of
+// 16) and writes its partial tile, alpha = 1 and beta = 0, to C + blockIdx.z
+// * sc (the partial buffer); k_splitk_sum adds the slices in order.
 __global__ __launch_bounds__(kT) void k_gemm(int M, int N, int K, double alpha,
                                              const double* __restrict__ A, int64_t lda,
                                              int64_t sa, int ta, const double* __restrict__ B,
                                              int64_t ldb, int64_t sb, int tb, double beta,
-                                             double* __restrict__ C, int64_t ldc, int64_t sc) {
+                                             double* __restrict__ C, int64_t ldc, int64_t sc,
+                                             int ksplit, int kper) {
     __shared__ double As[32][17];
     __shared__ double Bs[16][33];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wr = w >> 1, wc = w & 1;
     const int row0 = blockIdx.y * 32, col0 = blockIdx.x * 32;
-    const int64_t bz = blockIdx.z;
+    const int64_t bz = blockIdx.z / ksplit;
+    const int slice = (int)(blockIdx.z % ksplit);
+    const int kb = slice * kper, ke = min(K, kb + kper);
     A += bz * sa;
     B += bz * sb;
-    C += bz * sc;
+    C += (ksplit > 1 ? (int64_t)blockIdx.z : bz) * sc;
     v4d acc = {0.0, 0.0, 0.0, 0.0};
-    for (int k0 = 0; k0 < K; k0 += 16) {
+    for (int k0 = kb; k0 < ke; k0 += 16) {
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
             const int e = tid + u * kT;  // 512 entries of each tile
             // A tile 32 x 16: along k when A is row-major, along i when transposed
             const int ai = ta ? (e & 31) : (e >> 4), ak = ta ? (e >> 5) : (e & 15);
             const int gi = row0 + ai, gk = k0 + ak;
-            As[ai][ak] = (gi < M && gk < K) ? A[ta ? (int64_t)gk * lda + gi : (int64_t)gi * lda + gk]
-                                            : 0.0;
+            As[ai][ak] = (gi < M && gk < ke) ? A[ta ? (int64_t)gk * lda + gi : (int64_t)gi * lda + gk]
+                                             : 0.0;
             // B tile 16 x 32: along j when B is row-major, along k when transposed
             const int bk = tb ? (e & 15) : (e >> 5), bj = tb ? (e >> 4) : (e & 31);
             const int hk = k0 + bk, hj = col0 + bj;
-            Bs[bk][bj] = (hk < K && hj < N) ? B[tb ? (int64_t)hj * ldb + hk : (int64_t)hk * ldb + hj]
-                                            : 0.0;
+            Bs[bk][bj] = (hk < ke && hj < N) ? B[tb ? (int64_t)hj * ldb + hk : (int64_t)hk * ldb + hj]
+                                             : 0.0;
         }
         __syncthreads();
 #pragma unroll
@@ -79,6 +86,24 @@ __global__ __launch_bounds__(kT) void k_gemm(int M, int N, int K, double alpha,
             double* c = C + (int64_t)i * ldc + j;
             *c = beta == 0.0 ? alpha * acc[v] : alpha * acc[v] + beta * *c;
         }
+    }
+}
+
+// C = alpha sum_slice P[b * ksplit + slice] + beta C over batch x M x N, the
+// slices added in order (P: M x N per slice, contiguous).
+__global__ __launch_bounds__(kT) void k_splitk_sum(int M, int N, int batch, int ksplit,
+                                                   const double* __restrict__ P, double alpha,
+                                                   double beta, double* __restrict__ C,
+                                                   int64_t ldc, int64_t sc) {
+    const int64_t mn = (int64_t)M * N, tot = mn * batch;
+    for (int64_t e = (int64_t)blockIdx.x * kT + threadIdx.x; e < tot;
+         e += (int64_t)gridDim.x * kT) {
+        const int64_t b = e / mn, ij = e % mn;
+        const int i = (int)(ij / N), j = (int)(ij % N);
+        double v = 0.0;
+        for (int q = 0; q < ksplit; ++q) v += P[(b * ksplit + q) * mn + ij];
+        double* c = C + b * sc + (int64_t)i * ldc + j;
+        *c = beta == 0.0 ? alpha * v : alpha * v + beta * *c;
     }
 }
 
@@ -282,13 +307,17 @@ __global__ void k_rank_check(const double* __restrict__ lam, int r, double smax,
 // cyclic Jacobi with the round-robin parallel ordering (n2/2 disjoint
 // rotations per round, n2 = s rounded up to even, index n2-1 fixed when s is
 // odd... every index meets every other once per sweep), one workgroup per
-// matrix (blockIdx.x selects it), A and V in LDS.  Sweeps stop when the
-// off-diagonal mass is below 1e-30 of the diagonal's (squares) or after 40.
+// matrix (blockIdx.x selects it), A and V in LDS.  A round applies its
+// rotations in place, first to the rows of each pair, then to the columns
+// (of A and V): the pairs are disjoint, so each work item reads and writes
+// only its own two entries.  Sweeps stop when the off-diagonal mass is below
+// 1e-30 of the diagonal's (squares) or after 40.
 // Output: lam (s, decreasing) and V (s x s, V[i * s + j] = component i of
 // eigenvector j, in the same order).
 constexpr int kJacMax = 96;
+constexpr int kJT = 512;  // threads of k_jacobi
 
-__global__ __launch_bounds__(kT) void k_jacobi(const double* __restrict__ Gall, int64_t gstride,
+__global__ __launch_bounds__(kJT) void k_jacobi(const double* __restrict__ Gall, int64_t gstride,
                                                int s, double* __restrict__ lam_all,
                                                int64_t lstride, double* __restrict__ V_all,
                                                int64_t vstride) {
@@ -296,16 +325,16 @@ __global__ __launch_bounds__(kT) void k_jacobi(const double* __restrict__ Gall, 
     const int ld = kJacMax + 1;
     double* A = jsm;                       // s x ld
     double* V = jsm + kJacMax * ld;        // s x ld
-    __shared__ double jc[kJacMax], js[kJacMax];
-    __shared__ int jp[kJacMax], ord[kJacMax];
-    __shared__ double red[2][kT / 64];
+    __shared__ double jc[kJacMax], js[kJacMax];  // one round's rotations, per pair
+    __shared__ int jp[kJacMax], jq[kJacMax], ord[kJacMax];
+    __shared__ double red[2][kJT / 64];
     __shared__ int stop;
     const double* G = Gall + blockIdx.x * gstride;
     double* lam = lam_all + blockIdx.x * lstride;
     double* Vout = V_all + blockIdx.x * vstride;
     const int tid = threadIdx.x;
     const int n2 = s + (s & 1);
-    for (int e = tid; e < s * s; e += kT) {
+    for (int e = tid; e < s * s; e += kJT) {
         const int i = e / s, j = e % s;
         A[i * ld + j] = 0.5 * (G[i * s + j] + G[j * s + i]);
         V[i * ld + j] = i == j ? 1.0 : 0.0;
@@ -313,7 +342,7 @@ __global__ __launch_bounds__(kT) void k_jacobi(const double* __restrict__ Gall, 
     __syncthreads();
     for (int sweep = 0; sweep < 40; ++sweep) {
         double off = 0.0, dg = 0.0;
-        for (int e = tid; e < s * s; e += kT) {
+        for (int e = tid; e < s * s; e += kJT) {
             const int i = e / s, j = e % s;
             const double v = A[i * ld + j];
             if (i == j) dg += v * v;
@@ -330,7 +359,7 @@ __global__ __launch_bounds__(kT) void k_jacobi(const double* __restrict__ Gall, 
         __syncthreads();
         if (tid == 0) {
             double a = 0.0, b = 0.0;
-            for (int q = 0; q < kT / 64; ++q) {
+            for (int q = 0; q < kJT / 64; ++q) {
                 a += red[0][q];
                 b += red[1][q];
             }
@@ -355,44 +384,42 @@ __global__ __launch_bounds__(kT) void k_jacobi(const double* __restrict__ Gall, 
                         sn = t * c;
                     }
                 }
-                // J[p][p] = J[q][q] = c, J[p][q] = sn, J[q][p] = -sn: column i of J is
-                // c at row i and js[i] at row jp[i]
-                if (p < s) {
-                    jp[p] = q < s ? q : p;
-                    jc[p] = c;
-                    js[p] = q < s ? -sn : 0.0;
-                }
-                if (q < s) {
-                    jp[q] = p < s ? p : q;
-                    jc[q] = c;
-                    js[q] = p < s ? sn : 0.0;
-                }
+                // J[p][p] = J[q][q] = c, J[p][q] = sn, J[q][p] = -sn (the
+                // identity for a pair with the padding index)
+                const bool in = p < s && q < s;
+                jp[tid] = in ? p : -1;
+                jq[tid] = q;
+                jc[tid] = c;
+                js[tid] = sn;
             }
             __syncthreads();
-            // A <- J^T A J and V <- V J, each entry from the old values
-            constexpr int kPer = (kJacMax * kJacMax + kT - 1) / kT;
-            double na[kPer], nv[kPer];
-#pragma unroll
-            for (int u = 0; u < kPer; ++u) {
-                const int e = tid + u * kT;
-                if (e < s * s) {
-                    const int i = e / s, j = e % s;
-                    const int i2 = jp[i], j2 = jp[j];
-                    const double ci = jc[i], si = js[i], cj = jc[j], sj = js[j];
-                    na[u] = ci * (cj * A[i * ld + j] + sj * A[i * ld + j2]) +
-                            si * (cj * A[i2 * ld + j] + sj * A[i2 * ld + j2]);
-                    nv[u] = cj * V[i * ld + j] + sj * V[i * ld + j2];
-                }
+            // A <- J^T A (the rows of each pair), then A <- A J and V <- V J
+            // (its columns), in place: the pairs are disjoint, so each item
+            // reads and writes only its own two entries
+            const int npair = n2 / 2, items = npair * s;
+            for (int e = tid; e < items; e += kJT) {
+                const int t = e / s, j = e - t * s;
+                const int p = jp[t];
+                if (p < 0) continue;
+                const int q = jq[t];
+                const double c = jc[t], sn = js[t];
+                const double a = A[p * ld + j], b = A[q * ld + j];
+                A[p * ld + j] = c * a - sn * b;
+                A[q * ld + j] = sn * a + c * b;
             }
             __syncthreads();
-#pragma unroll
-            for (int u = 0; u < kPer; ++u) {
-                const int e = tid + u * kT;
-                if (e < s * s) {
-                    const int i = e / s, j = e % s;
-                    A[i * ld + j] = na[u];
-                    V[i * ld + j] = nv[u];
-                }
+            for (int e = tid; e < items; e += kJT) {
+                const int t = e / s, i = e - t * s;
+                const int p = jp[t];
+                if (p < 0) continue;
+                const int q = jq[t];
+                const double c = jc[t], sn = js[t];
+                const double a = A[i * ld + p], b = A[i * ld + q];
+                A[i * ld + p] = c * a - sn * b;
+                A[i * ld + q] = sn * a + c * b;
+                const double va = V[i * ld + p], vb = V[i * ld + q];
+                V[i * ld + p] = c * va - sn * vb;
+                V[i * ld + q] = sn * va + c * vb;
             }
             __syncthreads();
         }
@@ -409,7 +436,7 @@ __global__ __launch_bounds__(kT) void k_jacobi(const double* __restrict__ Gall, 
     }
     __syncthreads();
     if (tid < s) lam[tid] = A[ord[tid] * ld + ord[tid]];
-    for (int e = tid; e < s * s; e += kT) {
+    for (int e = tid; e < s * s; e += kJT) {
         const int i = e / s, j = e % s;
         Vout[i * s + j] = V[i * ld + ord[j]];
     }
