@@ -54,6 +54,13 @@ __device__ __forceinline__ double lane63(double v) {
     return __hiloint2double(hi, lo);
 }
 
+// v of lane l (l wave-uniform), in every lane
+__device__ __forceinline__ double lane_value(double v, int l) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+
 // sum over each quad of lanes (xor 1, xor 2), result in all four lanes
 __device__ __forceinline__ double quad_sum(double v) {
     v += dpp_mov<0xB1, 0xF>(v);  // quad_perm [1,0,3,2]
@@ -636,6 +643,16 @@ __device__ __forceinline__ double eig_start(uint32_t a, uint32_t p, uint32_t sal
     return (double)(eig_hash(a, p + 131u * salt) >> 8) * 0x1p-23 - 1.0 + 0x1p-24;
 }
 
+// Element (row, col) of the eigensolver's row-major s x RP blocks in LDS
+// (sh.qs, sh.zs): the column index XOR the row's low bits, so that a
+// thread's own row (lanes on consecutive rows, RP doubles apart) spreads
+// over the banks instead of landing on one, while a row stays contiguous
+// for the matrix-core operand loads (lanes on the columns of one row).
+template <int RP>
+__device__ __forceinline__ int rsw(int row, int col) {
+    return row * RP + (col ^ (row & (RP - 1)));
+}
+
 template <int RP>
 // The small arrays come first so that their fixed addresses fit the 16-bit
 // immediate offset of LDS instructions (no address register each); the row
@@ -677,8 +694,8 @@ __device__ void eig_tm(int sp, bool wantT, EigShared<RP>& sh) {
             for (int u = 0; u < 2; ++u) {
                 const int jj = j + u < j1 ? j + u : j0;
                 const int b = 4 * jj + kq;
-                double zv = sh.zs[b * RP + cc];
-                double qv = sh.qs[b * RP + cc];
+                double zv = sh.zs[rsw<RP>(b, cc)];
+                double qv = sh.qs[rsw<RP>(b, cc)];
                 zv = (col < RP && j + u < j1) ? zv : 0.0;
                 qv = col < RP ? qv : 0.0;
                 acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(isM ? zv : qv, zv, acc[u], 0, 0, 0);
@@ -777,31 +794,39 @@ template <int RP>
 struct EigChol<RP, true> {
     __device__ __forceinline__ bool factor(double* M, int r, EigShared<RP>& sh) {
         if (threadIdx.x < 64) {
-            const int lane = threadIdx.x;
+            // lane c < RP holds column c of R in registers and forms it left
+            // to right: R[j][c] = (M[j][c] - sum_{k<j} R[k][j] R[k][c]) / R_jj,
+            // the R[k][j] read from lane j; the terms are subtracted in
+            // increasing k, the order in which a right-looking update applies
+            // them, so that R is the same to the bit.  Lanes >= RP shadow
+            // lane c % RP and store nothing.
+            const int lane = threadIdx.x, c = lane & (RP - 1);
+            double R[RP];
+#pragma unroll
+            for (int k = 0; k < RP; ++k) R[k] = M[k * RP + c];
             bool ok = true;
-            for (int j = 0; j < r; ++j) {
-                const double d = M[j * RP + j];  // the pivot after steps 0..j-1
-                ok = ok && d > 0.0;
-                const double ri = rsqrt(d > 0.0 ? d : 1.0);
-                wave_sync();
-                if (lane >= j && lane < r) {
-                    const double v = M[j * RP + lane];
-                    M[j * RP + lane] = lane == j ? d * ri : v * ri;
-                }
-                if (lane == 0) sh.dv[j] = ri;
-                wave_sync();
-                for (int e = lane; e < RP * RP; e += 64) {
-                    const int i = e / RP, c = e % RP;
-                    if (i > j && c >= i && c < r) M[e] -= M[j * RP + i] * M[j * RP + c];
-                }
-                wave_sync();
+            double dc = 1.0;  // 1 / R_cc
+#pragma unroll
+            for (int j = 0; j < RP; ++j) {
+                double v = R[j];
+#pragma unroll
+                for (int k = 0; k < j; ++k) v -= lane_value(R[k], j) * R[k];
+                const bool jin = j < r;
+                const double d = lane_value(v, j);  // the pivot
+                ok = ok && (!jin || d > 0.0);
+                const double ri = rsqrt((jin && d > 0.0) ? d : 1.0);
+                if (c == j) dc = ri;
+                // row j of R: the pivot, the scaled entries right of it
+                // inside the r x r block, zero elsewhere (identity beyond r);
+                // entries below the diagonal (j > c) are not part of R
+                R[j] = c == j ? (jin ? d * ri : 1.0) : (c > j ? ((jin && c < r) ? v * ri : 0.0) : 0.0);
             }
-            // the identity beyond r: R_jj = 1 (j >= r), R_jc = 0 (c > j, j or c >= r)
-            for (int e = lane; e < RP * RP; e += 64) {
-                const int i = e / RP, c = e % RP;
-                if (c >= i && (i >= r || c >= r)) M[e] = i == c ? 1.0 : 0.0;
+            if (lane < RP) {
+#pragma unroll
+                for (int k = 0; k < RP; ++k)
+                    if (k <= c) M[k * RP + c] = R[k];
+                sh.dv[c] = c < r ? dc : 1.0;
             }
-            if (lane >= r && lane < RP) sh.dv[lane] = 1.0;
             if (lane == 0) sh.cok = ok ? 1 : 0;
         }
         __syncthreads();
@@ -854,7 +879,7 @@ __device__ __forceinline__ void eig_gq(const double* G, int sp, int s, EigShared
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 av[u] = G[gram_at(t, j >> 4, col, 4 * u + kq, nt)];
-                bv[u] = sh.qs[(j + 4 * u + kq) * RP + cc];
+                bv[u] = sh.qs[rsw<RP>(j + 4 * u + kq, cc)];
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u)
@@ -864,7 +889,7 @@ __device__ __forceinline__ void eig_gq(const double* G, int sp, int s, EigShared
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int row = 16 * t + 4 * v + kq;
-            if (row < s && col < RP) sh.zs[row * RP + col] = acc[v];
+            if (row < s && col < RP) sh.zs[rsw<RP>(row, col)] = acc[v];
         }
     }
     __syncthreads();
@@ -986,7 +1011,7 @@ __device__ __noinline__ int eig_guarded(const double* G, int sp, int s, int r, i
     int steps = 0;
     double x[RP], z[RP], q[RP];
 #pragma unroll
-    for (int p = 0; p < RP; ++p) q[p] = act ? sh.qs[a * RP + p] : 0.0;
+    for (int p = 0; p < RP; ++p) q[p] = act ? sh.qs[rsw<RP>(a, p)] : 0.0;
 #pragma unroll
     for (int p = 0; p < RP; ++p)
         x[p] = p < r ? q[p] : ((act && p < m) ? eig_start(a, p, 7u) : 0.0);
@@ -995,12 +1020,12 @@ __device__ __noinline__ int eig_guarded(const double* G, int sp, int s, int r, i
         __syncthreads();
         if (act) {
 #pragma unroll
-            for (int p = 0; p < RP; ++p) sh.qs[a * RP + p] = x[p];
+            for (int p = 0; p < RP; ++p) sh.qs[rsw<RP>(a, p)] = x[p];
         }
         __syncthreads();
         eig_gq<RP>(G, sp, s, sh);
 #pragma unroll
-        for (int p = 0; p < RP; ++p) z[p] = act ? sh.zs[a * RP + p] : 0.0;
+        for (int p = 0; p < RP; ++p) z[p] = act ? sh.zs[rsw<RP>(a, p)] : 0.0;
         if (it > 0 && (it % kEigCheck == 0 || it == kEigGuardMax)) {
             eig_tm<RP>(sp, true, sh);  // T = Q^T Z
             if (threadIdx.x < RP * RP) {
@@ -1045,7 +1070,7 @@ __device__ __noinline__ int eig_guarded(const double* G, int sp, int s, int r, i
         __syncthreads();
         if (act) {
 #pragma unroll
-            for (int p = 0; p < RP; ++p) sh.zs[a * RP + p] = z[p];
+            for (int p = 0; p < RP; ++p) sh.zs[rsw<RP>(a, p)] = z[p];
         }
         __syncthreads();
         bool ok = true;
@@ -1060,7 +1085,7 @@ __device__ __noinline__ int eig_guarded(const double* G, int sp, int s, int r, i
                 for (int p = 0; p < RP; ++p) z[p] = x[p];
                 if (act) {
 #pragma unroll
-                    for (int p = 0; p < RP; ++p) sh.zs[a * RP + p] = z[p];
+                    for (int p = 0; p < RP; ++p) sh.zs[rsw<RP>(a, p)] = z[p];
                 }
                 __syncthreads();
             }
@@ -1073,7 +1098,7 @@ __device__ __noinline__ int eig_guarded(const double* G, int sp, int s, int r, i
     __syncthreads();
     if (act) {
 #pragma unroll
-        for (int p = 0; p < RP; ++p) sh.qs[a * RP + p] = res < 0 ? q[p] : (p < r ? x[p] : 0.0);
+        for (int p = 0; p < RP; ++p) sh.qs[rsw<RP>(a, p)] = res < 0 ? q[p] : (p < r ? x[p] : 0.0);
     }
     if (threadIdx.x == 0) *steps_out = steps;
     __syncthreads();
@@ -1170,7 +1195,7 @@ __device__ __forceinline__ void eig_gq_tm(const double* G, int sp, int s, EigSha
         // (loaded up front, so that the tile's epilogue does not wait on LDS)
         double qa[4];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) qa[v] = col < RP ? sh.qs[(16 * t + 4 * v + kq) * RP + cc] : 0.0;
+        for (int v = 0; v < 4; ++v) qa[v] = col < RP ? sh.qs[rsw<RP>(16 * t + 4 * v + kq, cc)] : 0.0;
         v4d acc = {0.0, 0.0, 0.0, 0.0};
         // two operand sets of 16 columns, each loaded while the other one's
         // products run
@@ -1179,7 +1204,7 @@ __device__ __forceinline__ void eig_gq_tm(const double* G, int sp, int s, EigSha
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 av[u] = G[gram_at(t, j >> 4, col, 4 * u + kq, nt)];
-                bv[u] = sh.qs[(j + 4 * u + kq) * RP + cc];
+                bv[u] = sh.qs[rsw<RP>(j + 4 * u + kq, cc)];
             }
         };
         auto mul = [&](const double (&av)[4], const double (&bv)[4]) {
@@ -1204,7 +1229,7 @@ __device__ __forceinline__ void eig_gq_tm(const double* G, int sp, int s, EigSha
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int row = 16 * t + 4 * v + kq;
-            if (row < s && col < RP) sh.zs[row * RP + col] = acc[v];
+            if (row < s && col < RP) sh.zs[rsw<RP>(row, col)] = acc[v];
             tacc = __builtin_amdgcn_mfma_f64_16x16x4f64(qa[v], acc[v], tacc, 0, 0, 0);
             macc = __builtin_amdgcn_mfma_f64_16x16x4f64(acc[v], acc[v], macc, 0, 0, 0);
         }
@@ -1369,7 +1394,7 @@ __device__ __forceinline__ void eig_finish_lds(const Prob& P, int i, int s, int 
         // y = q T^-1 = (q R^-1) R^-T, q the thread's row of sh.qs
         double qr[RP], u[RP];
 #pragma unroll
-        for (int k = 0; k < RP; ++k) qr[k] = sh.qs[a * RP + k];
+        for (int k = 0; k < RP; ++k) qr[k] = sh.qs[rsw<RP>(a, k)];
         double* Yi = Y + P.woff[i];
 #pragma unroll
         for (int p = 0; p < RP; ++p) Wi[a * RP + p] = p < r ? qr[p] : 0.0;
@@ -1478,12 +1503,12 @@ __global__ __launch_bounds__(kThreads) void k_eig(Prob P, const double* __restri
                 const int b = e / RP, p = e % RP;
                 const double v = att == 0 ? Bd[P.boff[i] + (int64_t)P.I[i][b] * RP + p]
                                           : eig_start(b, p, att);
-                sh.qs[e] = p < r ? v : 0.0;
+                sh.qs[rsw<RP>(b, p)] = p < r ? v : 0.0;
             }
             __syncthreads();
             eig_gq<RP>(G, sp, s, sh);
 #pragma unroll
-            for (int p = 0; p < RP; ++p) z[p] = act ? sh.zs[a * RP + p] : 0.0;
+            for (int p = 0; p < RP; ++p) z[p] = act ? sh.zs[rsw<RP>(a, p)] : 0.0;
             ok = true;
             for (int rep = 0; rep < 2 && ok; ++rep) {
                 eig_tm<RP>(sp, false, sh);  // M = Z^T Z
@@ -1495,7 +1520,7 @@ __global__ __launch_bounds__(kThreads) void k_eig(Prob P, const double* __restri
                     for (int p = 0; p < RP; ++p) z[p] = q[p];
                     if (rep == 0 && act) {
 #pragma unroll
-                        for (int p = 0; p < RP; ++p) sh.zs[a * RP + p] = z[p];
+                        for (int p = 0; p < RP; ++p) sh.zs[rsw<RP>(a, p)] = z[p];
                     }
                     __syncthreads();
                 }
@@ -1516,7 +1541,7 @@ __global__ __launch_bounds__(kThreads) void k_eig(Prob P, const double* __restri
         __syncthreads();
         if (act) {
 #pragma unroll
-            for (int p = 0; p < RP; ++p) sh.qs[a * RP + p] = q[p];
+            for (int p = 0; p < RP; ++p) sh.qs[rsw<RP>(a, p)] = q[p];
         }
     }
     int steps = 0;
@@ -1532,44 +1557,28 @@ __global__ __launch_bounds__(kThreads) void k_eig(Prob P, const double* __restri
             __syncthreads();
             if (act) {
 #pragma unroll
-                for (int p = 0; p < RP; ++p) sh.qs[a * RP + p] = q[p];
+                for (int p = 0; p < RP; ++p) sh.qs[rsw<RP>(a, p)] = q[p];
             }
             __syncthreads();
             eig_gq_tm<RP>(G, sp, s, sh);  // Z = G Q, T = Q^T Z, M = Z^T Z
 #pragma unroll
-            for (int p = 0; p < RP; ++p) z[p] = act ? sh.zs[a * RP + p] : 0.0;
+            for (int p = 0; p < RP; ++p) z[p] = act ? sh.zs[rsw<RP>(a, p)] : 0.0;
+            // (RP <= 8 only: RP = 16 runs plain_lds) T in registers
             double rn = 0.0, tn = 0.0;
-            if constexpr (RP <= 8) {
-                double Tr[RP][RP];
+            double Tr[RP][RP];
 #pragma unroll
-                for (int k = 0; k < RP; ++k)
-#pragma unroll
-                    for (int p = 0; p < RP; ++p) {
-                        Tr[k][p] = sh.tm[k * RP + p];
-                        tn += Tr[k][p] * Tr[k][p];
-                    }
+            for (int k = 0; k < RP; ++k)
 #pragma unroll
                 for (int p = 0; p < RP; ++p) {
-                    double v = z[p];
-#pragma unroll
-                    for (int k = 0; k < RP; ++k) v -= q[k] * Tr[k][p];
-                    rn += act ? v * v : 0.0;
+                    Tr[k][p] = sh.tm[k * RP + p];
+                    tn += Tr[k][p] * Tr[k][p];
                 }
-            } else {
-                // T read from LDS as it is used (no register copy; one
-                // column's loads at a time)
 #pragma unroll
-                for (int p = 0; p < RP; ++p) {
-                    double v = z[p];
+            for (int p = 0; p < RP; ++p) {
+                double v = z[p];
 #pragma unroll
-                    for (int k = 0; k < RP; ++k) {
-                        const double t = sh.tm[k * RP + p];
-                        v -= q[k] * t;
-                        tn += t * t;
-                    }
-                    rn += act ? v * v : 0.0;
-                    __builtin_amdgcn_sched_barrier(0);
-                }
+                for (int k = 0; k < RP; ++k) v -= q[k] * Tr[k][p];
+                rn += act ? v * v : 0.0;
             }
             rn = block_sum<4>(rn, sh.red);
             if (rn <= rtol * rtol * tn) return 0;
@@ -1604,22 +1613,40 @@ __global__ __launch_bounds__(kThreads) void k_eig(Prob P, const double* __restri
             double qr[RP], zr[RP];
 #pragma unroll
             for (int k = 0; k < RP; ++k) {
-                qr[k] = sh.qs[a * RP + k];
-                zr[k] = sh.zs[a * RP + k];
+                qr[k] = sh.qs[rsw<RP>(a, k)];
+                zr[k] = sh.zs[rsw<RP>(a, k)];
             }
-            double rn = 0.0, tn = 0.0;
+            // ||T||_F^2: four entries per lane and a wave sum, the same in
+            // every wave
+            double tn = 0.0;
+#pragma unroll
+            for (int u = 0; u < RP * RP / 64; ++u) {
+                const double t = sh.tm[(threadIdx.x & 63) + 64 * u];
+                tn += t * t;
+            }
+            tn = wave_sum(tn);
+            // the row's residual z - q T, one row of T at a time (RP
+            // independent sums; the next row's loads issued before this
+            // row's products, two rows in flight at most)
+            double v[RP], tr[2][RP];
 #pragma unroll
             for (int p = 0; p < RP; ++p) {
-                double v = zr[p];
-#pragma unroll
-                for (int k = 0; k < RP; ++k) {
-                    const double t = sh.tm[k * RP + p];
-                    v -= qr[k] * t;
-                    tn += t * t;
-                }
-                rn += v * v;
-                __builtin_amdgcn_sched_barrier(0);
+                v[p] = zr[p];
+                tr[0][p] = sh.tm[p];
             }
+#pragma unroll
+            for (int k = 0; k < RP; ++k) {
+                if (k + 1 < RP) {
+#pragma unroll
+                    for (int p = 0; p < RP; ++p) tr[(k + 1) & 1][p] = sh.tm[(k + 1) * RP + p];
+                }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int p = 0; p < RP; ++p) v[p] -= qr[k] * tr[k & 1][p];
+            }
+            double rn = 0.0;
+#pragma unroll
+            for (int p = 0; p < RP; ++p) rn += v[p] * v[p];
             rn = block_sum<4>(act ? rn : 0.0, sh.red);
             if (rn <= rtol * rtol * tn) return 0;
             if (it >= limit) return 1;
@@ -1637,7 +1664,7 @@ __global__ __launch_bounds__(kThreads) void k_eig(Prob P, const double* __restri
             ch.solve(zr, qr, sh);
             if (act) {
 #pragma unroll
-                for (int p = 0; p < RP; ++p) sh.qs[a * RP + p] = qr[p];
+                for (int p = 0; p < RP; ++p) sh.qs[rsw<RP>(a, p)] = qr[p];
             }
         }
     };
@@ -1649,7 +1676,7 @@ __global__ __launch_bounds__(kThreads) void k_eig(Prob P, const double* __restri
         if constexpr (!kRowsLds) {
             if (act) {
 #pragma unroll
-                for (int p = 0; p < RP; ++p) sh.qs[a * RP + p] = q[p];
+                for (int p = 0; p < RP; ++p) sh.qs[rsw<RP>(a, p)] = q[p];
             }
         }
         if (threadIdx.x == 0) sh.gsteps = 0;
@@ -1657,7 +1684,7 @@ __global__ __launch_bounds__(kThreads) void k_eig(Prob P, const double* __restri
         const int g = eig_guarded<RP>(G, sp, s, r, m, rtol, &sh, &sh.gsteps);
         if constexpr (!kRowsLds) {
 #pragma unroll
-            for (int p = 0; p < RP; ++p) q[p] = act ? sh.qs[a * RP + p] : 0.0;
+            for (int p = 0; p < RP; ++p) q[p] = act ? sh.qs[rsw<RP>(a, p)] : 0.0;
         }
         steps += sh.gsteps;
         // a few plain steps from the Ritz vectors (or, after a breakdown of
