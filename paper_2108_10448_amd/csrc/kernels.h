@@ -421,8 +421,10 @@ __global__ __launch_bounds__(kThreads) void k_ht(
 #pragma unroll
     for (int p = 0; p < RP; ++p) h[p] = T(0);
     if (haveL) {
+        // rows p >= r of a block's H are padding: never written, not read
 #pragma unroll
-        for (int p = 0; p < RP; ++p) h[p] = H[bd.hoff + (int64_t)p * bd.ncols + cc];
+        for (int p = 0; p < RP; ++p)
+            if (p < bd.r) h[p] = H[bd.hoff + (int64_t)p * bd.ncols + cc];  // (uniform)
     }
     if (sf) return;
     if (haveL) {
@@ -2018,6 +2020,16 @@ __global__ __launch_bounds__(kThreads) void k_zcore(Prob P, const T* __restrict_
 constexpr int kBfacKC = 1024;
 constexpr int kBfacMaxKC = 64;  // column chunks (partial rows) per entry at most
 
+// Entry (c, p) of a B-factor work item's staged Z chunk (column c of the
+// chunk, RP doubles each) in LDS: p XOR bits of c above the columns that
+// share one 256-byte bank row, so that the lanes of a wave, on consecutive
+// columns and reading the same p, fall on distinct banks.
+template <int RP>
+__device__ __forceinline__ int zsw(int c, int p) {
+    constexpr int sh = RP == 4 ? 3 : (RP == 8 ? 2 : 1);
+    return c * RP + (p ^ ((c >> sh) & (RP - 1)));
+}
+
 // kSub: some mode stages several Z sub-chunks per work item (P.bsub > 1).
 template <typename T, int RP, bool kSub>
 __global__ __launch_bounds__(kThreads) void k_bfac(Prob P, const T* __restrict__ C,
@@ -2077,7 +2089,7 @@ __global__ __launch_bounds__(kThreads) void k_bfac(Prob P, const T* __restrict__
 #pragma unroll
             for (int q = 0; q < ZE; ++q) {
                 const int e = tid + q * kThreads;
-                zs[e] = e < cn * RP ? zv[q] : 0.0;
+                zs[zsw<RP>(e / RP, e % RP)] = e < cn * RP ? zv[q] : 0.0;
             }
         }
         if (sf) return;
@@ -2095,7 +2107,7 @@ __global__ __launch_bounds__(kThreads) void k_bfac(Prob P, const T* __restrict__
                 if (c < cn) {
                     double z[RP];
 #pragma unroll
-                    for (int p = 0; p < RP; ++p) z[p] = zs[c * RP + p];
+                    for (int p = 0; p < RP; ++p) z[p] = zs[zsw<RP>(c, p)];
 #pragma unroll
                     for (int j = 0; j < kBfacRowsPerWave; ++j) {
                         const double x = (double)cv[j][u];
@@ -2148,7 +2160,7 @@ __global__ __launch_bounds__(kThreads) void k_bfac(Prob P, const T* __restrict__
 #pragma unroll
                 for (int q = 0; q < ZE; ++q) {
                     const int e = tid + q * kThreads;
-                    zs[e] = e < cn * RP ? zv[q] : 0.0;
+                    zs[zsw<RP>(e / RP, e % RP)] = e < cn * RP ? zv[q] : 0.0;
                 }
             }
             if (sf) return;
@@ -2170,7 +2182,7 @@ __global__ __launch_bounds__(kThreads) void k_bfac(Prob P, const T* __restrict__
                     if (c < cn) {
                         double z[RP];
 #pragma unroll
-                        for (int p = 0; p < RP; ++p) z[p] = zs[c * RP + p];
+                        for (int p = 0; p < RP; ++p) z[p] = zs[zsw<RP>(c, p)];
 #pragma unroll
                         for (int j = 0; j < kBfacRowsPerWave; ++j) {
                             const double x = (double)cv[j][u];
@@ -2371,7 +2383,10 @@ __global__ __launch_bounds__(kThreads) void k_hexp_fac(
         __syncthreads();
         const double* Tg = Tb + (int)(cc / plen - g0) * rm * rl;
         const int64_t hoff = dense ? 0 : P.blk[tl.x].hoff;
-        for (int p = 0; p < RP; ++p) {
+        // a sampled block's H has the mode's r rows (the threshold pass reads
+        // no more); the full-unfolding H of a reconstruction all RP
+        const int prows = dense ? RP : rm;
+        for (int p = 0; p < prows; ++p) {
             double a = 0.0;
             if (p < rm) {
 #pragma unroll
@@ -2449,6 +2464,9 @@ __global__ __launch_bounds__(kThreads) void k_hexp(
         for (int k = 0; k < RP; ++k) bv[q][k] = Bf[rowoff[q] + k];
     if (sf) return;
     const int64_t hoff = dense ? 0 : P.blk[tl.x].hoff;
+    // a sampled block's H has the mode's r rows (the threshold pass reads no
+    // more); the full-unfolding H of a reconstruction all RP
+    const int prows = dense ? RP : rm;
     if constexpr (N <= 3) {
         // the B rows stay in registers: the q and u loops are unrolled to RP
         // and masked at the true ranks, so the core's LDS reads pipeline
@@ -2459,7 +2477,7 @@ __global__ __launch_bounds__(kThreads) void k_hexp(
             v1[k] = N == 3 ? (double)bv[N == 3 ? 1 : 0][k] : 0.0;
         }
         __syncthreads();  // gp staged
-        for (int p = 0; p < RP; ++p) {
+        for (int p = 0; p < prows; ++p) {
             double a = 0.0;
             if (p < rm) {
 #pragma unroll
@@ -2490,7 +2508,7 @@ __global__ __launch_bounds__(kThreads) void k_hexp(
     const double* v0 = vs + tid;
     const double* v1 = vs + RP * kThreads + tid;
     const double* v2 = vs + 2 * RP * kThreads + tid;
-    for (int p = 0; p < RP; ++p) {
+    for (int p = 0; p < prows; ++p) {
         double a = 0.0;
         if (p < rm) {
             for (int q = 0; q < r0; ++q) {
@@ -2594,7 +2612,8 @@ __global__ __launch_bounds__(kThreads) void k_evalblock(Prob P, int b,
     T L = T(0);
 #pragma unroll
     for (int p = 0; p < RP; ++p)
-        L = fma(Bf[P.boff[bd.mode] + xi * RP + p], H[bd.hoff + (int64_t)p * bd.ncols + c], L);
+        if (p < bd.r)  // (the block's H has r rows)
+            L = fma(Bf[P.boff[bd.mode] + xi * RP + p], H[bd.hoff + (int64_t)p * bd.ncols + c], L);
     out[e] = (double)L;
 }
 
