@@ -78,7 +78,7 @@ struct Prob {
     int64_t boff[kMaxModes];  // offset of B_i (d_i x rp) in the factor buffer
     int64_t woff[kMaxModes];  // offset of W_i / Y_i (s_i x rp), float64
     int64_t goff[kMaxModes];  // offset of the Gram of mode i (s_i x s_i)
-    int64_t zoff[kMaxModes];  // offset of Z_i (rp x m_i), float64
+    int64_t zoff[kMaxModes];  // offset of Z_i (m_i x r_i, row per column), float64
     int gitem0[kMaxModes];    // first Gram work item of mode i
     int gnkc[kMaxModes];      // Gram column chunks per output tile of mode i
     int gchunk[kMaxModes];    // columns per Gram chunk (multiple of 256)

@@ -1771,11 +1771,14 @@ __device__ void zmat_tile(const Prob& P, const T* __restrict__ C, const double* 
 #pragma unroll
     for (int p = 0; p < RP; ++p) red[(w * RP + p) * 64 + lane] = acc[p];
     __syncthreads();
-    for (int e = threadIdx.x; e < 64 * RP; e += kThreads) {
-        const int col = e & 63, p = e >> 6;
+    // Z_i is stored compactly, r_i doubles per column (the padded columns
+    // p >= r_i of Y_i are zero); consecutive threads write consecutive words
+    const int r = P.r[i];
+    for (int e = threadIdx.x; e < 64 * r; e += kThreads) {
+        const int col = e / r, p = e - col * r;
         const double z = ((red[p * 64 + col] + red[(RP + p) * 64 + col]) +
                           red[(2 * RP + p) * 64 + col]) + red[(3 * RP + p) * 64 + col];
-        if (tl.y + col < m) Zbuf[P.zoff[i] + (int64_t)(tl.y + col) * RP + p] = z;
+        if (tl.y + col < m) Zbuf[P.zoff[i] + (int64_t)(tl.y + col) * r + p] = z;
     }
 }
 
@@ -2058,7 +2061,8 @@ __global__ __launch_bounds__(kThreads) void k_bfac(Prob P, const T* __restrict__
     double acc[kBfacRowsPerWave][RP];
     if constexpr (!kSub) {
         const int c0 = kc * KC, cn = min(KC, m - c0);
-        const double* Zc = Zbuf + P.zoff[i] + (int64_t)c0 * RP;
+        const int r = P.r[i];
+        const double* Zc = Zbuf + P.zoff[i] + (int64_t)c0 * r;
         const int xb = rb * kBfacRows + w * kBfacRowsPerWave;
         const T* rowp[kBfacRowsPerWave];
 #pragma unroll
@@ -2079,17 +2083,19 @@ __global__ __launch_bounds__(kThreads) void k_bfac(Prob P, const T* __restrict__
         load_c(cv, 0);
         {
             // Z chunk -> LDS: every load of a thread issued before the stores
+            // (Z_i holds r doubles per column; the padding p >= r is staged as
+            // zero, its lanes loading a word the others fetch anyway)
             constexpr int ZE = KC * RP / kThreads;
             double zv[ZE];
 #pragma unroll
             for (int q = 0; q < ZE; ++q) {
-                const int e = tid + q * kThreads;
-                zv[q] = Zc[e < cn * RP ? e : 0];
+                const int e = tid + q * kThreads, c = e / RP, p = e % RP;
+                zv[q] = Zc[(e < cn * RP && p < r) ? c * r + p : 0];
             }
 #pragma unroll
             for (int q = 0; q < ZE; ++q) {
-                const int e = tid + q * kThreads;
-                zs[zsw<RP>(e / RP, e % RP)] = e < cn * RP ? zv[q] : 0.0;
+                const int e = tid + q * kThreads, c = e / RP, p = e % RP;
+                zs[zsw<RP>(c, p)] = (e < cn * RP && p < r) ? zv[q] : 0.0;
             }
         }
         if (sf) return;
@@ -2130,7 +2136,8 @@ __global__ __launch_bounds__(kThreads) void k_bfac(Prob P, const T* __restrict__
             const int c0 = (kc * nsub + sc) * KC;
             if (c0 >= m) break;  // uniform
             const int cn = min(KC, m - c0);
-            const double* Zc = Zbuf + P.zoff[i] + (int64_t)c0 * RP;
+            const int r = P.r[i];
+            const double* Zc = Zbuf + P.zoff[i] + (int64_t)c0 * r;
             const T* rowp[kBfacRowsPerWave];
 #pragma unroll
             for (int j = 0; j < kBfacRowsPerWave; ++j)
@@ -2150,17 +2157,19 @@ __global__ __launch_bounds__(kThreads) void k_bfac(Prob P, const T* __restrict__
             load_c(cv, 0);
             {
                 // Z chunk -> LDS: every load of a thread issued before the stores
+                // (Z_i holds r doubles per column; the padding p >= r is staged as
+                // zero, its lanes loading a word the others fetch anyway)
                 constexpr int ZE = KC * RP / kThreads;
                 double zv[ZE];
 #pragma unroll
                 for (int q = 0; q < ZE; ++q) {
-                    const int e = tid + q * kThreads;
-                    zv[q] = Zc[e < cn * RP ? e : 0];
+                    const int e = tid + q * kThreads, c = e / RP, p = e % RP;
+                    zv[q] = Zc[(e < cn * RP && p < r) ? c * r + p : 0];
                 }
 #pragma unroll
                 for (int q = 0; q < ZE; ++q) {
-                    const int e = tid + q * kThreads;
-                    zs[zsw<RP>(e / RP, e % RP)] = e < cn * RP ? zv[q] : 0.0;
+                    const int e = tid + q * kThreads, c = e / RP, p = e % RP;
+                    zs[zsw<RP>(c, p)] = (e < cn * RP && p < r) ? zv[q] : 0.0;
                 }
             }
             if (sf) return;

@@ -342,7 +342,7 @@ static void plan(Impl& im, const Shape& sh, int esize, size_t idx_bytes, int max
         const int64_t nt = (sh.s[i] + 15) / 16;
         im.g_elems += 256 * (nt * (nt + 1) / 2);
         P.zoff[i] = im.z_elems;
-        im.z_elems += (int64_t)RP * sh.m[i];
+        im.z_elems += (int64_t)sh.r[i] * sh.m[i];  // r_i words per column
     }
     // Gram work: upper-triangular 16x16 tile pairs x column chunks
     im.gram_items.clear();
