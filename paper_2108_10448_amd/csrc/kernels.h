@@ -864,6 +864,32 @@ __device__ __forceinline__ int gram_at(int t, int kt, int x, int y, int nt) {
     return tile * 256 + r * 16 + (c ^ r);
 }
 
+// Index of the tile pair (min(t, kt), max(t, kt)) in gram_at's order.
+__device__ __forceinline__ int gram_tile(int t, int kt, int nt) {
+    const int ta = t <= kt ? t : kt, tb = t <= kt ? kt : t;
+    return ta * nt - ta * (ta - 1) / 2 + (tb - ta);
+}
+
+// A lane's operand offsets for the products Z = G Q below (lane l: Gram
+// tile row l % 16 at k-step 4u + l / 16, and Q's row 4u + l / 16 of a
+// 16-row set at column l % 16): gram_at's offset within a tile is gu[u]
+// (upper tile) or gl[u] (lower tile, read through its mirror), and
+// rsw(16 j + 4u + l / 16, cc) is 16 j RP + qo[u].  Computed once, so that a
+// step's addresses are a wave-uniform base plus one of these registers.
+template <int RP>
+struct GqLane {
+    int gu[4], gl[4], qo[4];
+    __device__ __forceinline__ GqLane(int col, int kq, int cc) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int y = 4 * u + kq;
+            gu[u] = col * 16 + (y ^ col);
+            gl[u] = y * 16 + (col ^ y);
+            qo[u] = y * RP + (cc ^ (y & (RP - 1)));
+        }
+    }
+};
+
 // Z = G Q into zs (rows < s, columns < RP) on the float64 matrix cores, G in
 // the tile layout above, Q's rows s..sp-1 zero.  Wave w takes the 16-row
 // tiles w, w + 4, ...; per tile one accumulator chain over the rows of Q:
@@ -871,17 +897,21 @@ __device__ __forceinline__ int gram_at(int t, int kt, int x, int y, int nt) {
 // product j; accumulator register v of lane l is row 4v + l/16, column l%16.
 template <int RP>
 __device__ __forceinline__ void eig_gq(const double* G, int sp, int s, EigShared<RP>& sh) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // (wave-uniform)
     const int col = lane & 15, kq = lane >> 4, cc = col < RP ? col : RP - 1;
     const int nt = sp >> 4;
+    const GqLane<RP> L(col, kq, cc);
     for (int t = w; t < nt; t += 4) {
         v4d acc = {0.0, 0.0, 0.0, 0.0};
         for (int j = 0; j < sp; j += 16) {  // sp is a multiple of 16
             double av[4], bv[4];
+            const bool up = t <= (j >> 4);
+            const double* Gt = G + gram_tile(t, j >> 4, nt) * 256;
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                av[u] = G[gram_at(t, j >> 4, col, 4 * u + kq, nt)];
-                bv[u] = sh.qs[rsw<RP>(j + 4 * u + kq, cc)];
+                av[u] = Gt[up ? L.gu[u] : L.gl[u]];
+                bv[u] = sh.qs[j * RP + L.qo[u]];
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u)
@@ -1188,25 +1218,29 @@ __device__ __forceinline__ void gram_assemble2(const double* __restrict__ src0, 
 // operand (A[m][k] = Z[k][m]).  Per-wave partials are added in wave order.
 template <int RP>
 __device__ __forceinline__ void eig_gq_tm(const double* G, int sp, int s, EigShared<RP>& sh) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // (wave-uniform)
     const int col = lane & 15, kq = lane >> 4, cc = col < RP ? col : RP - 1;
     const int nt = sp >> 4;
+    const GqLane<RP> L(col, kq, cc);
     v4d tacc = {0.0, 0.0, 0.0, 0.0}, macc = {0.0, 0.0, 0.0, 0.0};
     for (int t = w; t < nt; t += 4) {
         // Q^T as the A operand of the T product: A[p][k] = Q[16t + 4v + k][p]
         // (loaded up front, so that the tile's epilogue does not wait on LDS)
         double qa[4];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) qa[v] = col < RP ? sh.qs[rsw<RP>(16 * t + 4 * v + kq, cc)] : 0.0;
+        for (int v = 0; v < 4; ++v) qa[v] = col < RP ? sh.qs[16 * t * RP + L.qo[v]] : 0.0;
         v4d acc = {0.0, 0.0, 0.0, 0.0};
         // two operand sets of 16 columns, each loaded while the other one's
         // products run
         double a0[4], b0[4], a1[4], b1[4];
         auto load = [&](double (&av)[4], double (&bv)[4], int j) {
+            const bool up = t <= (j >> 4);
+            const double* Gt = G + gram_tile(t, j >> 4, nt) * 256;
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                av[u] = G[gram_at(t, j >> 4, col, 4 * u + kq, nt)];
-                bv[u] = sh.qs[rsw<RP>(j + 4 * u + kq, cc)];
+                av[u] = Gt[up ? L.gu[u] : L.gl[u]];
+                bv[u] = sh.qs[j * RP + L.qo[u]];
             }
         };
         auto mul = [&](const double (&av)[4], const double (&bv)[4]) {
