@@ -101,7 +101,8 @@ def work_per_solve(dims, s, r, b, K, eig_steps):
     NC = sum(dims[i] * m[i] for i in range(n))
     N = NR + NC
     RP = 4 if max(r) <= 4 else 8 if max(r) <= 8 else 16
-    hcols = NR // s[0] + sum(m)           # H columns over all blocks
+    # H words over all blocks: r of the block's mode per column
+    hwords = NR // s[0] * r[0] + sum(m[i] * r[i] for i in range(n))
     return {
         # one read of X
         "absmax": ("hbm", int(math.prod(dims)) * b),
@@ -117,16 +118,16 @@ def work_per_solve(dims, s, r, b, K, eig_steps):
         "eig": ("alu", eig_steps / n * sum(2 * s[i] ** 2 * r[i] + 6 * s[i] * r[i] ** 2
                                            for i in range(n))
                 + K * sum(4 * s[i] ** 2 + 2 * s[i] * r[i] ** 2 for i in range(n))),
-        # read U_i (= the core block unfolded) for Z_i, write Z_i; read R for
-        # the core slices
-        "zcore": ("hbm", K * (sum(s[i] * m[i] * b + m[i] * RP * 8 for i in range(n))
+        # read U_i (= the core block unfolded) for Z_i, write Z_i (r_i float64
+        # words per column); read R for the core slices
+        "zcore": ("hbm", K * (sum(s[i] * m[i] * b + m[i] * r[i] * 8 for i in range(n))
                               + NR * b)),
         # read every fibre block and Z_i
-        "bfac": ("hbm", K * sum(dims[i] * m[i] * b + m[i] * RP * 8 for i in range(n))),
+        "bfac": ("hbm", K * sum(dims[i] * m[i] * b + m[i] * r[i] * 8 for i in range(n))),
         # write B_i (float64 and storage copies)
         "bred": ("hbm", K * sum(dims[i] * RP * (8 + b) for i in range(n))),
-        # write H on every block column
-        "hexp": ("hbm", K * hcols * RP * b),
+        # write H on every block column (the mode's r rows)
+        "hexp": ("hbm", K * hwords * b),
     }
 
 
