@@ -395,20 +395,8 @@ __global__ __launch_bounds__(kThreads) void k_ht(
     const bool valid = c < bd.ncols;
     const int cc = valid ? c : bd.ncols - 1;
     const int rows = min(TR, bd.nrows - tl.y);
-    kcur = iter_of(kcur, st);
-    double zeta = st->zeta0;
-    if (kcur < P.nsched) {
-        zeta *= P.zsched[kcur];
-    } else {
-        int j = 0;
-        if (P.nsched > 0) {
-            zeta *= P.zsched[P.nsched - 1];
-            j = P.nsched;
-        }
-        for (; j <= kcur; ++j) zeta *= gamma;
-    }
-
-    // all loads first
+    // all loads first (the threshold below comes after them: its chain of
+    // dependent loads of the loop state would otherwise delay every one)
     TB xb[TR], cb[TR];
     const int64_t base = bd.off + (int64_t)tl.y * bd.ncols + cc;
 #pragma unroll
@@ -425,6 +413,18 @@ __global__ __launch_bounds__(kThreads) void k_ht(
 #pragma unroll
         for (int p = 0; p < RP; ++p)
             if (p < bd.r) h[p] = H[bd.hoff + (int64_t)p * bd.ncols + cc];  // (uniform)
+    }
+    kcur = iter_of(kcur, st);
+    double zeta = st->zeta0;
+    if (kcur < P.nsched) {
+        zeta *= P.zsched[kcur];
+    } else {
+        int j = 0;
+        if (P.nsched > 0) {
+            zeta *= P.zsched[P.nsched - 1];
+            j = P.nsched;
+        }
+        for (; j <= kcur; ++j) zeta *= gamma;
     }
     if (sf) return;
     if (haveL) {
