@@ -1021,6 +1021,10 @@ __device__ void eig_jacobi(EigShared<RP>& sh) {
 constexpr int kEigCheck = 4;     // guarded iteration: Rayleigh-Ritz every 4 steps
 constexpr int kEigGuardMax = 400;
 
+// (defined below, with the plain iteration it serves first)
+template <int RP>
+__device__ __forceinline__ void eig_gq_tm(const double* G, int sp, int s, EigShared<RP>& sh);
+
 // Guarded subspace iteration for a slow gap (lambda_{r+1} / lambda_r close
 // to 1): the iterate gets m - r extra columns (m = min(RP, s)), so that the
 // top-r part converges at lambda_{m+1} / lambda_r, with a Rayleigh-Ritz
@@ -1055,11 +1059,14 @@ __device__ __noinline__ int eig_guarded(const double* G, int sp, int s, int r, i
             for (int p = 0; p < RP; ++p) sh.qs[rsw<RP>(a, p)] = x[p];
         }
         __syncthreads();
-        eig_gq<RP>(G, sp, s, sh);
+        eig_gq_tm<RP>(G, sp, s, sh);  // Z = G X, T = X^T Z, M = Z^T Z
 #pragma unroll
         for (int p = 0; p < RP; ++p) z[p] = act ? sh.zs[rsw<RP>(a, p)] : 0.0;
+        // sh.mm holds Z^T Z of the rows in sh.zs until a Rayleigh-Ritz check
+        // rotates them
+        bool mfresh = true;
         if (it > 0 && (it % kEigCheck == 0 || it == kEigGuardMax)) {
-            eig_tm<RP>(sp, true, sh);  // T = Q^T Z
+            mfresh = false;
             if (threadIdx.x < RP * RP) {
                 const int p = threadIdx.x / RP, t = threadIdx.x % RP;
                 sh.mm[threadIdx.x] = 0.5 * (sh.tm[p * RP + t] + sh.tm[t * RP + p]);
@@ -1099,15 +1106,17 @@ __device__ __noinline__ int eig_guarded(const double* G, int sp, int s, int r, i
             }
         }
         // Cholesky-QR twice over the m columns
-        __syncthreads();
-        if (act) {
+        if (!mfresh) {
+            __syncthreads();
+            if (act) {
 #pragma unroll
-            for (int p = 0; p < RP; ++p) sh.zs[rsw<RP>(a, p)] = z[p];
+                for (int p = 0; p < RP; ++p) sh.zs[rsw<RP>(a, p)] = z[p];
+            }
+            __syncthreads();
         }
-        __syncthreads();
         bool ok = true;
         for (int rep = 0; rep < 2; ++rep) {
-            eig_tm<RP>(sp, false, sh);  // M = Z^T Z
+            if (rep > 0 || !mfresh) eig_tm<RP>(sp, false, sh);  // M = Z^T Z
             EigChol<RP> ch;
             ok = ch.factor(sh.mm, m, sh);
             if (!ok) break;
