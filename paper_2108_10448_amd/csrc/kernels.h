@@ -1225,6 +1225,74 @@ __device__ __forceinline__ void gram_assemble2(const double* __restrict__ src0, 
 // Z[16t + 4v + l/16][l%16], which is exactly the B operand (row k = l/16,
 // column l%16) of the k-step v over the tile's rows, and for M also its A
 // operand (A[m][k] = Z[k][m]).  Per-wave partials are added in wave order.
+// NP (1 or 2) Z tiles of eig_gq_tm, t and t + 4, side by side: each
+// 16-column operand set of Q is loaded once for both, and the two tiles'
+// product chains interleave (each chain in its own k order, as alone);
+// the epilogues run in tile order.
+template <int RP, int NP>
+__device__ __forceinline__ void gq_tm_tiles(const double* G, int sp, int s, int nt, int t,
+                                            const GqLane<RP>& L, int col, int kq,
+                                            EigShared<RP>& sh, v4d& tacc, v4d& macc) {
+    // Q^T as the A operand of the T product: A[p][k] = Q[16t + 4v + k][p]
+    // (loaded up front, so that a tile's epilogue does not wait on LDS)
+    double qa[NP][4];
+#pragma unroll
+    for (int k = 0; k < NP; ++k)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            qa[k][v] = col < RP ? sh.qs[16 * (t + 4 * k) * RP + L.qo[v]] : 0.0;
+    v4d acc[NP];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) acc[k] = v4d{0.0, 0.0, 0.0, 0.0};
+    // two operand sets of 16 columns, each loaded while the other one's
+    // products run
+    double a0[NP][4], b0[4], a1[NP][4], b1[4];
+    auto load = [&](double (&av)[NP][4], double (&bv)[4], int j) {
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+            const int tk = t + 4 * k;
+            const bool up = tk <= (j >> 4);
+            const double* Gt = G + gram_tile(tk, j >> 4, nt) * 256;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) av[k][u] = Gt[up ? L.gu[u] : L.gl[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) bv[u] = sh.qs[j * RP + L.qo[u]];
+    };
+    auto mul = [&](const double (&av)[NP][4], const double (&bv)[4]) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const double b = col < RP ? bv[u] : 0.0;
+#pragma unroll
+            for (int k = 0; k < NP; ++k)
+                acc[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[k][u], b, acc[k], 0, 0, 0);
+        }
+    };
+    // (the scheduling barriers keep each set's loads ahead of the other
+    // set's products instead of next to their own use)
+    load(a0, b0, 0);
+    int j = 0;
+    for (; j + 32 <= sp; j += 32) {  // sp is a multiple of 16
+        load(a1, b1, j + 16);
+        __builtin_amdgcn_sched_barrier(0);
+        mul(a0, b0);
+        load(a0, b0, j + 32 < sp ? j + 32 : j);  // (at the end: reloaded, unused)
+        __builtin_amdgcn_sched_barrier(0);
+        mul(a1, b1);
+    }
+    if (j < sp) mul(a0, b0);  // an odd number of 16-column sets
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = 16 * (t + 4 * k) + 4 * v + kq;
+            if (row < s && col < RP) sh.zs[rsw<RP>(row, col)] = acc[k][v];
+            tacc = __builtin_amdgcn_mfma_f64_16x16x4f64(qa[k][v], acc[k][v], tacc, 0, 0, 0);
+            macc = __builtin_amdgcn_mfma_f64_16x16x4f64(acc[k][v], acc[k][v], macc, 0, 0, 0);
+        }
+    }
+}
+
 template <int RP>
 __device__ __forceinline__ void eig_gq_tm(const double* G, int sp, int s, EigShared<RP>& sh) {
     const int lane = threadIdx.x & 63;
@@ -1233,51 +1301,12 @@ __device__ __forceinline__ void eig_gq_tm(const double* G, int sp, int s, EigSha
     const int nt = sp >> 4;
     const GqLane<RP> L(col, kq, cc);
     v4d tacc = {0.0, 0.0, 0.0, 0.0}, macc = {0.0, 0.0, 0.0, 0.0};
-    for (int t = w; t < nt; t += 4) {
-        // Q^T as the A operand of the T product: A[p][k] = Q[16t + 4v + k][p]
-        // (loaded up front, so that the tile's epilogue does not wait on LDS)
-        double qa[4];
-#pragma unroll
-        for (int v = 0; v < 4; ++v) qa[v] = col < RP ? sh.qs[16 * t * RP + L.qo[v]] : 0.0;
-        v4d acc = {0.0, 0.0, 0.0, 0.0};
-        // two operand sets of 16 columns, each loaded while the other one's
-        // products run
-        double a0[4], b0[4], a1[4], b1[4];
-        auto load = [&](double (&av)[4], double (&bv)[4], int j) {
-            const bool up = t <= (j >> 4);
-            const double* Gt = G + gram_tile(t, j >> 4, nt) * 256;
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                av[u] = Gt[up ? L.gu[u] : L.gl[u]];
-                bv[u] = sh.qs[j * RP + L.qo[u]];
-            }
-        };
-        auto mul = [&](const double (&av)[4], const double (&bv)[4]) {
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], col < RP ? bv[u] : 0.0, acc,
-                                                           0, 0, 0);
-        };
-        // (the scheduling barriers keep each set's loads ahead of the other
-        // set's products instead of next to their own use)
-        load(a0, b0, 0);
-        int j = 0;
-        for (; j + 32 <= sp; j += 32) {  // sp is a multiple of 16
-            load(a1, b1, j + 16);
-            __builtin_amdgcn_sched_barrier(0);
-            mul(a0, b0);
-            load(a0, b0, j + 32 < sp ? j + 32 : j);  // (at the end: reloaded, unused)
-            __builtin_amdgcn_sched_barrier(0);
-            mul(a1, b1);
-        }
-        if (j < sp) mul(a0, b0);  // an odd number of 16-column sets
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int row = 16 * t + 4 * v + kq;
-            if (row < s && col < RP) sh.zs[rsw<RP>(row, col)] = acc[v];
-            tacc = __builtin_amdgcn_mfma_f64_16x16x4f64(qa[v], acc[v], tacc, 0, 0, 0);
-            macc = __builtin_amdgcn_mfma_f64_16x16x4f64(acc[v], acc[v], macc, 0, 0, 0);
-        }
+    // wave w takes the tiles w, w + 4, w + 8, ..., two at a time
+    for (int t = w; t < nt; t += 8) {
+        if (t + 4 < nt)  // (uniform)
+            gq_tm_tiles<RP, 2>(G, sp, s, nt, t, L, col, kq, sh, tacc, macc);
+        else
+            gq_tm_tiles<RP, 1>(G, sp, s, nt, t, L, col, kq, sh, tacc, macc);
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
