@@ -1220,11 +1220,6 @@ __device__ __forceinline__ void gram_assemble2(const double* __restrict__ src0, 
     }
 }
 
-// Z = G Q into zs as eig_gq, with T = Q^T Z and M = Z^T Z formed from each
-// Z tile while it is still in the accumulators: register v of lane l holds
-// Z[16t + 4v + l/16][l%16], which is exactly the B operand (row k = l/16,
-// column l%16) of the k-step v over the tile's rows, and for M also its A
-// operand (A[m][k] = Z[k][m]).  Per-wave partials are added in wave order.
 // NP (1 or 2) Z tiles of eig_gq_tm, t and t + 4, side by side: each
 // 16-column operand set of Q is loaded once for both, and the two tiles'
 // product chains interleave (each chain in its own k order, as alone);
@@ -1293,6 +1288,11 @@ __device__ __forceinline__ void gq_tm_tiles(const double* G, int sp, int s, int 
     }
 }
 
+// Z = G Q into zs as eig_gq, with T = Q^T Z and M = Z^T Z formed from each
+// Z tile while it is still in the accumulators: register v of lane l holds
+// Z[16t + 4v + l/16][l%16], which is exactly the B operand (row k = l/16,
+// column l%16) of the k-step v over the tile's rows, and for M also its A
+// operand (A[m][k] = Z[k][m]).  Per-wave partials are added in wave order.
 template <int RP>
 __device__ __forceinline__ void eig_gq_tm(const double* G, int sp, int s, EigShared<RP>& sh) {
     const int lane = threadIdx.x & 63;
