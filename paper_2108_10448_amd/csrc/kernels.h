@@ -773,11 +773,10 @@ __device__ __forceinline__ void wave_sync() {
 // Cholesky-QR factor of an RP x RP matrix M in LDS (its r x r block; the
 // identity beyond r) and the solve q = z R^-1 of a thread's row.  RP <= 8: R
 // in the registers of every thread (eig_chol, eig_trsm).  RP = 16 (where R
-// would not fit in registers): M is factored in place, in LDS, by wave 0
-// (right-looking: row j scaled by 1 / sqrt(pivot), then the trailing upper
-// triangle updated, lanes over its entries, steps in increasing j as in
-// eig_chol) and the solve reads R from there; M must be sh.mm and is
-// overwritten (its upper triangle becomes R).  Called by every thread.
+// would not fit in every thread's registers): wave 0 factors M with one
+// column of R per lane (the same operations, in the same order, as eig_chol)
+// and writes R over M's upper triangle, 1 / R_jj to sh.dv; the solve reads R
+// from there.  M must be sh.mm.  Called by every thread.
 template <int RP, bool kLds = (RP > 8)>
 struct EigChol {
     double R[RP][RP], di[RP];
