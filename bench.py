@@ -441,6 +441,10 @@ def main():
                     help="skip the float64 and bfloat16 arms")
     ap.add_argument("--no-autotune", action="store_true",
                     help="built-in tile shapes instead of the autotuner's for the 300^3 arms")
+    ap.add_argument("--hw-queues", type=int, default=16,
+                    help="GPU_MAX_HW_QUEUES for this process (0: leave the environment's): "
+                         "the batch rows solve on up to 16 handles, each on its own stream, "
+                         "and streams that share a hardware queue run their kernels in turn")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 64-instance batch side row")
     ap.add_argument("--no-video", action="store_true",
@@ -457,6 +461,10 @@ def main():
               "single MI355X (multi-GPU sharding is a design note, not built).",
               file=sys.stderr)
         sys.exit(2)
+
+    # hardware queues per process: read when the HIP runtime starts, below
+    if args.hw_queues > 0:
+        os.environ["GPU_MAX_HW_QUEUES"] = str(min(args.hw_queues, 32))
 
     import numpy as np
     import torch
@@ -721,6 +729,7 @@ def main():
         batch = {"workload": "64 independent 3-mode float32 tensors, d_i ~ U{64..256}, "
                              "r_i ~ U{2..8}, alpha ~ U[0.1, 0.4], RTCUR-F, upsilon 3, tol 1e-5",
                  "handles": nh,
+                 "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES"),
                  "tensors_per_s_by_handles": {str(k): len(Xb) / v for k, v in by_handles.items()},
                  "batch_ms": 1e3 * t_batch,
                  "tensors_per_s": len(Xb) / t_batch,

@@ -161,7 +161,10 @@ int rtcur_outliers(rtcur_t h, const void* X, int x_dtype, double zeta, void* S_o
 /* Many independent instances (a batch of tensors of uneven shapes and
  * ranks), solved concurrently: each of the nh handles is driven by its own
  * host thread, so handles bound to distinct streams overlap their kernels on
- * the device.  Schedule: one work queue holds the instances in decreasing
+ * the device (the HIP runtime maps a process's streams onto
+ * GPU_MAX_HW_QUEUES hardware queues, 4 unless set; streams that share a
+ * queue run their kernels one after another, so nh concurrent handles want
+ * at least nh queues, set before the runtime starts).  Schedule: one work queue holds the instances in decreasing
  * expected cost (ties: lower j first) -- the solve times this process last
  * measured in a batch for the same problem (sizes, ranks, sample sizes, the
  * first handle's compute dtype and variant, gamma, tol, max_iter) when every
