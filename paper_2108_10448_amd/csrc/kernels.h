@@ -1537,14 +1537,19 @@ __global__ __launch_bounds__(kThreads) void k_eig(Prob P, const double* __restri
         const int nkc = P.gnkc[i];
         const int total = npairs * 256;
         const double* src0 = gpart + (int64_t)P.gitem0[i] * 256;
-        // chunk counts up to 4 or 8: one load round per entry; more: rounds
-        // of 16 chunks, added in chunk order
-        if (nkc <= 4)
+        // chunk counts up to 4 or 8 (and 16 at RP = 16): pairs of entries,
+        // every chunk's load of a round in flight at once; more: rounds of
+        // 16 chunks, added in chunk order.  (Wider rounds at RP <= 8 raise
+        // the whole kernel's register count and measured slower.)
+        if (nkc <= 4) {
             gram_assemble2<12, 4>(src0, total, nkc, G);
-        else if (nkc <= 8)
+        } else if (nkc <= 8) {
             gram_assemble2<6, 8>(src0, total, nkc, G);
-        else
+        } else if (RP == 16 && nkc <= 16) {
+            gram_assemble2<3, 16>(src0, total, nkc, G);
+        } else {
             gram_assemble<4, 16, true>(src0, total, nkc, G);
+        }
     }
     // Q and Z rows s..sp-1 stay zero for the padded products (written after
     // the assembly's loads were issued; the barrier below orders both)
