@@ -2098,6 +2098,8 @@ __global__ __launch_bounds__(kThreads) void k_zcore(Prob P, const T* __restrict_
 // One extra workgroup finishes the core G from the slices of k_zcore.
 constexpr int kBfacKC = 1024;
 constexpr int kBfacMaxKC = 64;  // column chunks (partial rows) per entry at most
+// columns per B-factor work item (its Z chunk in LDS: KC x RP doubles)
+constexpr int bfac_kc(int rp) { return rp <= 8 ? kBfacKC : kBfacKC / 2; }
 
 // Entry (c, p) of a B-factor work item's staged Z chunk (column c of the
 // chunk, RP doubles each) in LDS: p XOR bits of c above the columns that
@@ -2119,17 +2121,20 @@ __global__ __launch_bounds__(kThreads) void k_bfac(Prob P, const T* __restrict__
                                                    const double* __restrict__ Tbuf,
                                                    double* __restrict__ Gd, const DevState* st) {
     const int sf = stop_flag(st);
-    constexpr int KC = RP <= 8 ? kBfacKC : kBfacKC / 2;
+    constexpr int KC = bfac_kc(RP);
     static_assert(KC * RP >= kCoreLds, "core_finish staging fits in zs");
     __shared__ double zs[KC * RP];
-    if ((int)blockIdx.x == nitems) {
+    if (blockIdx.x == 0) {
         // the core G = sum_a W_0[a]^T T[a] from k_zcore's slices, beside the
-        // B-factor items
+        // B-factor items: workgroup 0, so that it is dispatched first (it is
+        // the longest single workgroup) and overlaps the items
         if (sf) return;
         core_finish<RP>(P, W, Tbuf, Gd, zs, KC * RP);
         return;
     }
-    const int4 it = items[blockIdx.x];
+    const int item = (int)blockIdx.x - 1;  // the grid is nitems + 1
+    if (item >= nitems) return;
+    const int4 it = items[item];
     const int i = it.x, rb = it.y, kc = it.z;
     const BlockDev& bd = P.blk[1 + i];
     const int m = bd.ncols, d = bd.nrows;
@@ -2290,7 +2295,7 @@ __global__ __launch_bounds__(kThreads) void k_bfac(Prob P, const T* __restrict__
     for (int j = 0; j < kBfacRowsPerWave; ++j)
 #pragma unroll
         for (int p = 0; p < RP; ++p) acc[j][p] = wave_sum(acc[j][p]);
-    double* out = bpart + ((int64_t)blockIdx.x * kBfacRows + w * kBfacRowsPerWave) * RP;
+    double* out = bpart + ((int64_t)item * kBfacRows + w * kBfacRowsPerWave) * RP;
     if (lane < RP) {
 #pragma unroll
         for (int j = 0; j < kBfacRowsPerWave; ++j) {

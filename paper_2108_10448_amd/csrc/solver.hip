@@ -381,7 +381,7 @@ static void plan(Impl& im, const Shape& sh, int esize, size_t idx_bytes, int max
     im.z_tiles.clear();
     im.bfac_items.clear();
     im.n_bgroups = 0;
-    const int bkc = RP <= 8 ? kBfacKC : kBfacKC / 2;
+    const int bkc = bfac_kc(RP);
     for (int i = 0; i < n; ++i) {
         for (int64_t c0 = 0; c0 < sh.m[i]; c0 += 64) im.z_tiles.push_back(make_int2(i, (int)c0));
         // at most kBfacMaxKC partial rows per entry for k_bred: long modes
@@ -1338,7 +1338,7 @@ int autotune(rtcur_s* h, const void* X, int x_dtype, const Shape& sh, int iters,
     };
     int rmax = 1;
     for (int i = 0; i < sh.n; ++i) rmax = std::max(rmax, sh.r[i]);
-    const int bkc = pad_rank(rmax) <= 8 ? kBfacKC : kBfacKC / 2;
+    const int bkc = bfac_kc(pad_rank(rmax));
     auto bfac_split = [&](const Tune& t) {
         std::vector<int> v;
         for (int i = 0; i < sh.n; ++i) {
