@@ -389,12 +389,21 @@ static void plan(Impl& im, const Shape& sh, int esize, size_t idx_bytes, int max
         const int nsc = (int)((sh.m[i] + bkc - 1) / bkc);
         const int nsub = std::min(nsc, std::max((nsc + kBfacMaxKC - 1) / kBfacMaxKC,
                                                 tune.bfac_sub));
-        const int nkc = (nsc + nsub - 1) / nsub;
-        P.bitem0[i] = (int)im.bfac_items.size();
-        P.bnkc[i] = nkc;
+        P.bnkc[i] = (nsc + nsub - 1) / nsub;
         P.bsub[i] = nsub;
+    }
+    // items of the modes with the most sub-chunks per item (the longest
+    // workgroups) first, so that they are dispatched first and the shorter
+    // ones fill the CUs around them; a mode's items stay contiguous in (row
+    // block, chunk) order, as k_bred reads them
+    int border[kMaxModes];
+    for (int i = 0; i < n; ++i) border[i] = i;
+    std::stable_sort(border, border + n, [&](int a, int b) { return P.bsub[a] > P.bsub[b]; });
+    for (int q = 0; q < n; ++q) {
+        const int i = border[q];
+        P.bitem0[i] = (int)im.bfac_items.size();
         for (int rb = 0; rb * kBfacRows < sh.d[i]; ++rb, ++im.n_bgroups)
-            for (int kc = 0; kc < nkc; ++kc)
+            for (int kc = 0; kc < P.bnkc[i]; ++kc)
                 im.bfac_items.push_back(make_int4(i, rb, kc, im.n_bgroups));
     }
     int64_t bent = 0;
