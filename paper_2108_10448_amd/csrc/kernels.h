@@ -1797,11 +1797,12 @@ __global__ __launch_bounds__(kThreads) void k_eig(Prob P, const double* __restri
 }
 
 // --------------------------- Z_i = Y_i^T U_i  and the core's first phase
-// Workgroups [0, nz): Z_i (m_i x RP, float64, row per column) with
-// U_i = C_i(I_i, :), so that V_i S_i^-1 = Z_i; 64 columns per workgroup,
-// one per lane, each wave summing a quarter of the s_i rows.
-// Workgroups [nz, nz + s_0): T[a] = R(a, :, ..) x_{l >= 1} W_l^T, the core
-// G = R x_i W_i^T before its last contraction (with W_0, done by k_hexp).
+// Workgroups [0, s_0 cparts): T[a] = R(a, :, ..) x_{l >= 1} W_l^T (or a
+// part of its middle-mode rows), the core G = R x_i W_i^T before its last
+// contraction (with W_0, finished beside the B-factor items).
+// Workgroups [s_0 cparts, s_0 cparts + nz): Z_i (m_i x r_i, float64, row per
+// column) with U_i = C_i(I_i, :), so that V_i S_i^-1 = Z_i; 64 columns per
+// workgroup, one per lane, each wave summing a quarter of the s_i rows.
 template <typename T, int RP>
 __device__ void zmat_tile(const Prob& P, const T* __restrict__ C, const double* __restrict__ Y,
                           double* __restrict__ Zbuf, int2 tl, double* ys, double* red, int sf) {
@@ -2084,11 +2085,15 @@ __global__ __launch_bounds__(kThreads) void k_zcore(Prob P, const T* __restrict_
     // contraction of the middle modes)
     static_assert(kSliceBytes <= (int)sizeof(double) * kCoreLds / 2, "staging fits");
     T* rs = reinterpret_cast<T*>(buf + kCoreLds / 2);
-    if ((int)blockIdx.x < nz) {
-        zmat_tile<T, RP>(P, C, Y, Zbuf, ztiles[blockIdx.x], sh, buf, sf);
+    // the core slices (the longer workgroups) first, so that they are
+    // dispatched first and the Z tiles fill the CUs around them
+    const int ncore = P.s[0] * P.cparts;
+    if ((int)blockIdx.x < ncore) {
+        core_slice<T, RP>(P, C + P.blk[0].off, W, Tbuf, (int)blockIdx.x, buf, sh, rs, sf);
         return;
     }
-    core_slice<T, RP>(P, C + P.blk[0].off, W, Tbuf, (int)blockIdx.x - nz, buf, sh, rs, sf);
+    const int zt = (int)blockIdx.x - ncore;  // < nz: the grid is nz + ncore
+    if (zt < nz) zmat_tile<T, RP>(P, C, Y, Zbuf, ztiles[zt], sh, buf, sf);
 }
 
 // -------------------------------------------------------- B_i = C_i Z_i
