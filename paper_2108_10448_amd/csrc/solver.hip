@@ -382,8 +382,17 @@ static void plan(Impl& im, const Shape& sh, int esize, size_t idx_bytes, int max
     im.bfac_items.clear();
     im.n_bgroups = 0;
     const int bkc = bfac_kc(RP);
+    // Z tiles of the modes with more sampled rows (the longer workgroups)
+    // first
+    {
+        int zord[kMaxModes];
+        for (int i = 0; i < n; ++i) zord[i] = i;
+        std::stable_sort(zord, zord + n, [&](int a, int b) { return sh.s[a] > sh.s[b]; });
+        for (int q = 0; q < n; ++q)
+            for (int64_t c0 = 0; c0 < sh.m[zord[q]]; c0 += 64)
+                im.z_tiles.push_back(make_int2(zord[q], (int)c0));
+    }
     for (int i = 0; i < n; ++i) {
-        for (int64_t c0 = 0; c0 < sh.m[i]; c0 += 64) im.z_tiles.push_back(make_int2(i, (int)c0));
         // at most kBfacMaxKC partial rows per entry for k_bred: long modes
         // stage several Z sub-chunks per work item
         const int nsc = (int)((sh.m[i] + bkc - 1) / bkc);
@@ -409,10 +418,18 @@ static void plan(Impl& im, const Shape& sh, int esize, size_t idx_bytes, int max
     int64_t bent = 0;
     for (int i = 0; i < n; ++i) bent += sh.d[i] * RP;
     im.n_bred_wg = (int)((bent + kThreads - 1) / kThreads);
+    // H tiles of the blocks with more H rows (the block mode's rank: the
+    // longer workgroups) first; order does not change what a tile computes
     im.h_tiles.clear();
-    for (int b = 0; b <= n; ++b)
+    int hord[kMaxBlocks];
+    for (int b = 0; b <= n; ++b) hord[b] = b;
+    std::stable_sort(hord, hord + n + 1,
+                     [&](int a, int b) { return P.blk[a].r > P.blk[b].r; });
+    for (int q = 0; q <= n; ++q) {
+        const int b = hord[q];
         for (int cb = 0; cb * kThreads < P.blk[b].ncols; ++cb)
             im.h_tiles.push_back(make_int2(b, cb));
+    }
     // core slices T[a] = R(a, ..) x_{l >= 1} W_l^T: s_0 x prod_{l >= 1} r_l
     // with three modes the slice's middle-mode rows are split so that each
     // part is staged in one pass
