@@ -367,12 +367,22 @@ static void plan(Impl& im, const Shape& sh, int esize, size_t idx_bytes, int max
             nkc = std::max(1, std::min(nkc, std::max(kGramKCGroup, 1024 / npi)));
         }
         const int chunk = (int)align_up((size_t)((sh.m[i] + nkc - 1) / nkc), 256);
-        P.gitem0[i] = (int)im.gram_items.size();
         P.gnkc[i] = nkc;
         P.gchunk[i] = chunk;
+    }
+    // items of the modes with the longest chunks (the longer workgroups)
+    // first, so that they are dispatched first; a mode's items stay
+    // contiguous in (tile pair, chunk) order, as the eigensolver reads them
+    int gord[kMaxModes];
+    for (int i = 0; i < n; ++i) gord[i] = i;
+    std::stable_sort(gord, gord + n, [&](int a, int b) { return P.gchunk[a] > P.gchunk[b]; });
+    for (int q = 0; q < n; ++q) {
+        const int i = gord[q];
+        const int nt = (int)((sh.s[i] + 15) / 16);
+        P.gitem0[i] = (int)im.gram_items.size();
         for (int ta = 0; ta < nt; ++ta)
             for (int tb = ta; tb < nt; ++tb, ++pid)
-                for (int kc = 0; kc < nkc; ++kc)
+                for (int kc = 0; kc < P.gnkc[i]; ++kc)
                     im.gram_items.push_back(make_int4(i, ta | (tb << 16), kc, pid));
     }
     im.n_pairs = pid;
