@@ -322,11 +322,25 @@ static void plan(Impl& im, const Shape& sh, int esize, size_t idx_bytes, int max
         off += (int64_t)bd.nrows * bd.ncols;
         hoff += (int64_t)RP * bd.ncols;
         moff += (int64_t)bd.nrows * bd.words;
-        bd.tile0 = (int)im.ht_tiles.size();
-        for (int r0 = 0; r0 < bd.nrows; r0 += im.ht_rows)
-            for (int c0 = 0; c0 < bd.ncols; c0 += kTileCols)
-                im.ht_tiles.push_back(make_int4(b, r0, c0, 0));
-        bd.tile1 = (int)im.ht_tiles.size();
+    }
+    // gather / threshold tiles of the blocks with the most rows first (a
+    // block of fewer rows than a tile has short tiles: they fill in at the
+    // end); a block's tiles stay contiguous, in row-major tile order, as the
+    // error sums read them
+    {
+        int tord[kMaxBlocks];
+        for (int b = 0; b <= n; ++b) tord[b] = b;
+        std::stable_sort(tord, tord + n + 1, [&](int a, int b) {
+            return std::min(P.blk[a].nrows, im.ht_rows) > std::min(P.blk[b].nrows, im.ht_rows);
+        });
+        for (int q = 0; q <= n; ++q) {
+            BlockDev& bd = P.blk[tord[q]];
+            bd.tile0 = (int)im.ht_tiles.size();
+            for (int r0 = 0; r0 < bd.nrows; r0 += im.ht_rows)
+                for (int c0 = 0; c0 < bd.ncols; c0 += kTileCols)
+                    im.ht_tiles.push_back(make_int4(tord[q], r0, c0, 0));
+            bd.tile1 = (int)im.ht_tiles.size();
+        }
     }
     im.nblk_elems = off;
     im.h_elems = hoff;
