@@ -85,12 +85,17 @@ def test_random_shape(k):
     n, dims, ranks, I, J, variant, dtype, alpha = _case(j) if kind == "s" else _wide_case(j)
     k = j if kind == "s" else 100 + j
     slice_ = ranks[-1] * int(np.prod(I[1:-1])) if n > 2 else ranks[-1]
-    if slice_ > 2048 or int(np.prod(ranks)) > 4096:
-        pytest.skip("outside the library's documented limits")
     inst = synth.tucker_plus_sparse(dims, ranks, alpha=alpha, seed=50 + k)
     X = inst.X if dtype == "f64" else inst.X.astype(np.float32)
     K = 4
     label = f"{dims} r={ranks} I={I} J={J} {variant} {dtype}"
+    if slice_ > 2048 or int(np.prod(ranks)) > 4096:
+        # outside the documented limits: rejected before any device work
+        _, info, _ = run_gpu(X, inst.ranks, I, J, tol=0.0, max_iter=K, seed=7 + k,
+                             variant=variant, check=False,
+                             dtype=torch.float64 if dtype == "f64" else torch.float32)
+        assert info.status == E_INVAL, (label, info.status)
+        return
     try:
         res = oracle_rtcur(X, inst.ranks, I, J, None, 0.7, 0.0, K, 7 + k, variant)
         want = None
@@ -119,10 +124,14 @@ def test_random_shape_to_tolerance(j):
     # (unless e^(k) sits within 1e-9 of tol) and so must the returned iterate
     n, dims, ranks, I, J, variant, _, alpha = _case(200 + j)
     slice_ = ranks[-1] * int(np.prod(I[1:-1])) if n > 2 else ranks[-1]
-    if slice_ > 2048 or int(np.prod(ranks)) > 4096:
-        pytest.skip("outside the library's documented limits")
     inst = synth.tucker_plus_sparse(dims, ranks, alpha=min(alpha, 0.15), seed=300 + j)
     label = f"{dims} r={ranks} I={I} J={J} {variant} to tol"
+    if slice_ > 2048 or int(np.prod(ranks)) > 4096:
+        # outside the documented limits: rejected before any device work
+        _, info, _ = run_gpu(inst.X, inst.ranks, I, J, tol=1e-6, max_iter=100, seed=3 + j,
+                             variant=variant, check=False)
+        assert info.status == E_INVAL, (label, info.status)
+        return
     try:
         res = oracle_rtcur(inst.X, inst.ranks, I, J, None, 0.7, 1e-6, 100, 3 + j, variant)
     except OracleError as e:
