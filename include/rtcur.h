@@ -30,9 +30,10 @@
  *     to rtcur_create, in stream order; rtcur_solve returns after its device
  *     work has finished.
  *   - Limits: 2 <= n <= 4; 1 <= r_i <= 16 for every n; prod(r_i) <= 4096;
- *     s_i <= 256; r_{n-1} * prod_{0<l<n-1} s_l <= 2048 (one slice of the
- *     sampled core); prod(d_i) <= 2^40.  Shapes beyond them return
- *     RTCUR_E_INVAL before any device work.
+ *     s_i <= 256; with n = 4, r_3 * s_1 * s_2 <= 2048 (one slice of the
+ *     sampled core; with n = 3 every slice, r_2 * s_1 <= 4096, fits);
+ *     prod(d_i) <= 2^40.  Shapes beyond them return RTCUR_E_INVAL before
+ *     any device work.
  */
 #ifndef RTCUR_H
 #define RTCUR_H

@@ -54,10 +54,14 @@ int validate(rtcur_t h, int32_t n, const int64_t* dims, const int32_t* ranks,
     }
     if (core > rtcur::kMaxCore) return fail(h, RTCUR_E_INVAL, "prod(r_i) must be <= 4096");
     {
-        // one slice of the core, r_{n-1} x prod_{0 < l < n-1} |I_l|, fits in LDS
+        // one slice of the core, r_{n-1} x prod_{0 < l < n-1} |I_l|, fits in
+        // LDS: 4096 entries with three modes (always, as r_2 <= 16 and
+        // |I_1| <= 256), 2048 with four (whose next contraction also stays
+        // in LDS)
         int64_t slice = ranks[n - 1];
         for (int l = 1; l < n - 1; ++l) slice *= I_sizes[l];
-        if (slice > 2048) return fail(h, RTCUR_E_INVAL, "sampled core slice too large");
+        if (slice > (n == 3 ? 4096 : 2048))
+            return fail(h, RTCUR_E_INVAL, "sampled core slice too large");
     }
     int64_t total = 1;
     for (int i = 0; i < n; ++i) total *= sh.d[i];

@@ -1881,15 +1881,21 @@ __device__ __forceinline__ double lds_dot(const TX* x, int xs, const double* y, 
 
 constexpr int kCoreLds = 4096;  // doubles of LDS for one slice's partial core
 constexpr int kSliceBytes = 16384;  // bytes of R staged per pass (in buf's second half)
+// three-mode slices of more than kCoreLds / 2 entries (r_2 s_1 <= 4096): a
+// second kernel instance with the partial core in the first 4096 doubles and
+// the staging behind them
+constexpr int kCoreSliceBig = 4096;
+constexpr int kCoreLdsBig = kCoreSliceBig + kSliceBytes / 8;
 
 // T[a] for one slice a of the R block (row-major s_0 x ... x s_{n-1}):
 // contract the last mode (R staged through LDS), then the others in LDS;
 // each step puts the new rank index first, so T[a] ends up ordered
-// (r_1, .., r_{n-1}).
+// (r_1, .., r_{n-1}).  buf: the partial core in [0, half), the staged rows
+// (rs) and the next contraction's output from buf + half.
 template <typename T, int RP>
 __device__ void core_slice(const Prob& P, const T* __restrict__ R, const double* __restrict__ W,
                            double* __restrict__ Tbuf, int a, double* buf, double* ws, T* rs,
-                           int sf) {
+                           int sf, int half) {
     const int n = P.n;
     const int tid = threadIdx.x;
     int rows = 1;
@@ -1972,7 +1978,7 @@ __device__ void core_slice(const Prob& P, const T* __restrict__ R, const double*
     int lead = rq;
     int rest = rows;
     double* cur = buf;
-    double* nxt = buf + kCoreLds / 2;
+    double* nxt = buf + half;
     for (int l = n - 2; l >= 1; --l) {
         const int Kl = P.s[l], rl = P.r[l];
         rest /= Kl;
@@ -2070,7 +2076,8 @@ __device__ void core_finish(const Prob& P, const double* __restrict__ W,
     }
 }
 
-template <typename T, int RP>
+// kBig: three modes with r_2 s_1 > kCoreLds / 2 (the larger buffer).
+template <typename T, int RP, bool kBig>
 __global__ __launch_bounds__(kThreads) void k_zcore(Prob P, const T* __restrict__ C,
                                                     const double* __restrict__ Y,
                                                     double* __restrict__ Zbuf,
@@ -2079,17 +2086,20 @@ __global__ __launch_bounds__(kThreads) void k_zcore(Prob P, const T* __restrict_
                                                     double* __restrict__ Tbuf,
                                                     const DevState* st) {
     const int sf = stop_flag(st);
+    constexpr int NB = kBig ? kCoreLdsBig : kCoreLds;
+    constexpr int HALF = kBig ? kCoreSliceBig : kCoreLds / 2;
     __shared__ double sh[kMaxS * RP];
-    __shared__ double buf[kCoreLds];
-    // the slice's staged rows share buf's second half (free until the
+    __shared__ double buf[NB];
+    // the slice's staged rows share buf's second part (free until the
     // contraction of the middle modes)
-    static_assert(kSliceBytes <= (int)sizeof(double) * kCoreLds / 2, "staging fits");
-    T* rs = reinterpret_cast<T*>(buf + kCoreLds / 2);
+    static_assert(kSliceBytes <= (int)sizeof(double) * (NB - HALF), "staging fits");
+    static_assert(NB >= 4 * 16 * 64, "zmat_tile's wave partials fit");
+    T* rs = reinterpret_cast<T*>(buf + HALF);
     // the core slices (the longer workgroups) first, so that they are
     // dispatched first and the Z tiles fill the CUs around them
     const int ncore = P.s[0] * P.cparts;
     if ((int)blockIdx.x < ncore) {
-        core_slice<T, RP>(P, C + P.blk[0].off, W, Tbuf, (int)blockIdx.x, buf, sh, rs, sf);
+        core_slice<T, RP>(P, C + P.blk[0].off, W, Tbuf, (int)blockIdx.x, buf, sh, rs, sf, HALF);
         return;
     }
     const int zt = (int)blockIdx.x - ncore;  // < nz: the grid is nz + ncore

@@ -680,9 +680,16 @@ struct Runner {
         HIPCHK(pe());
         const int nz = (int)im.z_tiles.size();
         HIPCHK(pb(PK_ZCORE));
-        hipLaunchKernelGGL((k_zcore<TB, RP>), dim3(nz + P.s[0] * P.cparts), dim3(kThreads), 0, s, P, C,
-                           (const double*)im.Y, im.Z, im.d_z_tiles, nz, (const double*)im.W,
-                           im.Tc, im.st);
+        int srows = 1;  // rows of a sampled core slice
+        for (int l = 1; l < n - 1; ++l) srows *= P.s[l];
+        if (P.r[n - 1] * srows > kCoreLds / 2)  // (three modes only)
+            hipLaunchKernelGGL((k_zcore<TB, RP, true>), dim3(nz + P.s[0] * P.cparts),
+                               dim3(kThreads), 0, s, P, C, (const double*)im.Y, im.Z,
+                               im.d_z_tiles, nz, (const double*)im.W, im.Tc, im.st);
+        else
+            hipLaunchKernelGGL((k_zcore<TB, RP, false>), dim3(nz + P.s[0] * P.cparts),
+                               dim3(kThreads), 0, s, P, C, (const double*)im.Y, im.Z,
+                               im.d_z_tiles, nz, (const double*)im.W, im.Tc, im.st);
         HIPCHK(hipGetLastError());
         HIPCHK(pe());
         HIPCHK(pb(PK_BFAC));

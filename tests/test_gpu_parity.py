@@ -240,7 +240,6 @@ def test_shape_limits_rejected():
     X = torch.zeros((40, 300, 30), dtype=torch.float64, device="cuda:0")
     for ranks, I in [((17, 2, 2), (20, 20, 20)),      # r_i <= 16
                      ((2, 2, 2), (20, 257, 20)),      # |I_i| <= 256
-                     ((2, 2, 16), (20, 200, 20)),     # core slice 16 * 200 > 2048
                      ((5, 2, 2), (4, 20, 20))]:       # r_i <= |I_i|
         with pytest.raises(rt.RTCURError) as e:
             rt.solve(h, X, ranks, I)
@@ -248,6 +247,12 @@ def test_shape_limits_rejected():
     X4 = torch.zeros((12, 12, 12, 12), dtype=torch.float64, device="cuda:0")
     with pytest.raises(rt.RTCURError) as e:
         rt.solve(h, X4, (9, 9, 9, 9), (10, 10, 10, 10))    # prod r_i = 6561 > 4096
+    assert e.value.status == rt.E_INVAL
+    # four modes: core slice r_3 |I_1| |I_2| = 4 * 30 * 30 > 2048 (with three
+    # modes r_2 |I_1| <= 16 * 256 always fits)
+    X4 = torch.zeros((12, 30, 30, 12), dtype=torch.float64, device="cuda:0")
+    with pytest.raises(rt.RTCURError) as e:
+        rt.solve(h, X4, (2, 2, 2, 4), (10, 30, 30, 10))
     assert e.value.status == rt.E_INVAL
     # the handle still solves a valid problem afterwards
     inst = synth.tucker_plus_sparse((16, 16, 16), (2, 2, 2), alpha=0.1, seed=2)

@@ -48,6 +48,12 @@ def _in_rank_band(res, ranks, I):
     return res.min_sig_ratio <= band
 
 
+def _slice_limit(n):
+    """Entries of one sampled core slice, r_{n-1} prod_{0<l<n-1} |I_l|, that
+    the library accepts."""
+    return 4096 if n == 3 else 2048
+
+
 def _case(k):
     rng = np.random.default_rng(1000 + k)
     n = int(rng.integers(2, 5))
@@ -89,7 +95,7 @@ def test_random_shape(k):
     X = inst.X if dtype == "f64" else inst.X.astype(np.float32)
     K = 4
     label = f"{dims} r={ranks} I={I} J={J} {variant} {dtype}"
-    if slice_ > 2048 or int(np.prod(ranks)) > 4096:
+    if slice_ > _slice_limit(n) or int(np.prod(ranks)) > 4096:
         # outside the documented limits: rejected before any device work
         _, info, _ = run_gpu(X, inst.ranks, I, J, tol=0.0, max_iter=K, seed=7 + k,
                              variant=variant, check=False,
@@ -126,7 +132,7 @@ def test_random_shape_to_tolerance(j):
     slice_ = ranks[-1] * int(np.prod(I[1:-1])) if n > 2 else ranks[-1]
     inst = synth.tucker_plus_sparse(dims, ranks, alpha=min(alpha, 0.15), seed=300 + j)
     label = f"{dims} r={ranks} I={I} J={J} {variant} to tol"
-    if slice_ > 2048 or int(np.prod(ranks)) > 4096:
+    if slice_ > _slice_limit(n) or int(np.prod(ranks)) > 4096:
         # outside the documented limits: rejected before any device work
         _, info, _ = run_gpu(inst.X, inst.ranks, I, J, tol=1e-6, max_iter=100, seed=3 + j,
                              variant=variant, check=False)
@@ -151,3 +157,22 @@ def test_random_shape_to_tolerance(j):
         assert info.iters == res.iters, (label, info.iters, res.iters)
     if info.iters == res.iters:
         compare(res, h, info, fp64=True, label=label)
+
+
+@pytest.mark.parametrize("variant,dtype", [("F", "f64"), ("F", "f32"), ("R", "f64")])
+def test_large_core_slice(variant, dtype):
+    # three modes with a sampled core slice of r_2 |I_1| = 12 * 250 = 3000
+    # entries (beyond half the common slice buffer): the larger k_zcore
+    # instance, against the oracle over K = 4 iterations
+    dims, ranks, I = [40, 250, 40], [4, 6, 12], [20, 250, 30]
+    inst = synth.tucker_plus_sparse(dims, ranks, alpha=0.2, seed=77)
+    X = inst.X if dtype == "f64" else inst.X.astype(np.float32)
+    K = 4
+    label = f"{dims} r={ranks} I={I} {variant} {dtype}"
+    res = oracle_rtcur(X, inst.ranks, I, None, None, 0.7, 0.0, K, 5, variant)
+    h, info, _ = run_gpu(X, inst.ranks, I, None, tol=0.0, max_iter=K, seed=5,
+                         variant=variant, check=False,
+                         dtype=torch.float64 if dtype == "f64" else torch.float32)
+    assert info.status >= 0, (label, info.status)
+    assert info.iters == res.iters == K, label
+    compare(res, h, info, fp64=dtype == "f64", label=label)
